@@ -1,0 +1,173 @@
+/* hm.h — C-ABI of the MI355X H-matrix LU library (libhm.so).
+ *
+ * Method: Boerm, Christophersen, Kriemann, "Semi-Automatic Task Graph
+ * Construction for H-Matrix Arithmetic" (arXiv 1911.07531).
+ *   build_htree  cluster tree (Def. 2.1) by geometric bisection and block tree
+ *                (Def. 2.2) with standard admissibility (Sec. 5.1)
+ *   h_assemble   H-matrix of Def. 2.3: dense inadmissible leaves, low-rank
+ *                U V^T admissible leaves compressed to precision eps
+ *   h_lu         H-LU of Algorithm 2 (with Algorithms 1 and 3 and the
+ *                truncated low-rank addition of Sec. 2.3); the recursion is
+ *                traced on the host into a task DAG (Sec. 3, Def. 3.1/3.2)
+ *                and replayed on the GPU
+ *   h_solve      forward/backward substitution through the factors, with
+ *                optional iterative refinement against h_matvec (not in the
+ *                paper: textbook block substitution)
+ *   h_matvec     y = alpha A_H x + beta y over all leaves (not in the paper)
+ *
+ * Conventions
+ *   - Every call returns hm_status: 0 on success, a negative code otherwise;
+ *     hm_last_error() returns a thread-local message for the last failure.
+ *   - Handles are opaque and owned by the library; release them with the
+ *     matching *_free.  A tree must outlive every matrix and factor built on
+ *     it; a matrix must outlive refinement calls that name it.
+ *   - Vectors cross the boundary in the caller's original point ordering,
+ *     FP64, column-major with a leading dimension.  Vector arguments are
+ *     device pointers owned by the caller, and must stay valid until the
+ *     work on `stream` has completed.
+ *   - `stream` is a hipStream_t (NULL = default stream).  h_assemble and h_lu
+ *     synchronise the stream before returning (they report pivot and rank
+ *     status); h_matvec is stream-ordered and asynchronous; h_solve
+ *     synchronises only when refinement is requested (it must read residuals).
+ *   - Device memory of handles comes from the allocator installed with
+ *     hm_set_allocator, else hipMalloc/hipFree.
+ *   - Nothing here falls back to the CPU: the compute entry points return
+ *     HM_EDEVICE when no gfx950 device is usable.
+ */
+#ifndef HM_H_
+#define HM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HM_OK = 0,
+  HM_EINVAL = -1,     /* bad argument: n < 1, leaf < 1, eta <= 0, eps < 0, null pointer, ... */
+  HM_ENOMEM = -2,     /* host or device allocation failed */
+  HM_ESINGULAR = -3,  /* exact zero pivot in a diagonal leaf; *info = permuted global row */
+  HM_ENOCONV = -4,    /* refinement did not reach rtol within max_iter */
+  HM_EDEVICE = -5,    /* HIP error, no usable device, or executor timeout */
+  HM_ERANK = -6       /* a truncation wanted more than the stored rank capacity (64) */
+} hm_status;
+
+typedef enum {
+  HM_FP64 = 0,  /* every block FP64 */
+  HM_MIXED = 1  /* FP32 off-diagonal blocks and products; FP64 diagonal leaves,
+                   pivots, Gram/core SVD of truncations, residuals */
+} hm_precision;
+
+typedef enum {
+  HM_LAPLACE3D = 0, /* a_ij = 1 / (4 pi |x_i - x_j|) */
+  HM_LOG2D = 1      /* a_ij = -log |x_i - x_j| / (2 pi) */
+} hm_kernel;
+
+typedef enum {
+  HM_EXEC_DATAFLOW = 0, /* one persistent launch; workgroups take ready tasks */
+  HM_EXEC_LEVEL = 1     /* one launch per DAG level */
+} hm_exec;
+
+typedef struct {
+  int leaf;         /* cluster leaf size (Def. 2.1 stop criterion |t| <= leaf) */
+  double eta;       /* admissibility parameter, min diam <= eta * dist */
+  double eps;       /* relative truncation accuracy (keep sigma_i > eps sigma_1) */
+  int max_rank;     /* rank cap, 0 = none (then the capacity 64 bounds it) */
+  int prec;         /* hm_precision */
+  int exec;         /* hm_exec */
+} hm_opts;
+
+typedef struct hm_tree_s* hm_tree;
+typedef struct hm_matrix_s* hm_matrix;
+typedef struct hm_lu_s* hm_lu;
+
+typedef struct {
+  int64_t ntasks, nedges, nlevels;
+  int64_t tasks_by_op[10];
+  int64_t bytes_alg;   /* algorithmic bytes of the executed tasks (run-time ranks) */
+  int64_t flops_alg;
+  double exec_ms;      /* device time of the executor launch(es), HIP events */
+  int64_t temp_bytes;  /* temporaries of the traced DAG */
+  int64_t rank_overflows;
+} hm_lu_stats;
+
+/* Device allocator hook; ctx is passed back.  Both may be NULL to restore
+ * hipMalloc/hipFree. */
+hm_status hm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*dealloc)(void* ptr, size_t bytes, void* stream, void* ctx), void* ctx);
+
+/* Cluster tree + block tree (host only, no device needed).
+ * pts_host: n x dim, row-major, FP64, caller-owned (copied).  dim in {2, 3}.
+ * Uses opts->leaf and opts->eta. */
+hm_status build_htree(const double* pts_host, int64_t n, int dim, const hm_opts* opts, hm_tree* out);
+
+/* Tree tables (host): sizes, then copies.  Any output pointer may be NULL.
+ * clusters: ncl x 5 int64 (begin, end, son0, son1, level), boxes ncl x 6
+ * (lo[3], hi[3]); blocks: nbl x 7 int32 (tau, sigma, kind 0 struct / 1 dense
+ * / 2 low-rank, son00, son01, son10, son11); perm: n int64, perm[k] =
+ * original index of permuted index k.  Both tables are depth-first pre-order. */
+hm_status hm_tree_sizes(hm_tree t, int64_t* n, int64_t* nclusters, int64_t* nblocks);
+hm_status hm_tree_export(hm_tree t, int64_t* perm, int64_t* clusters, double* boxes, int32_t* blocks);
+
+/* Assemble the H-matrix of Def. 2.3 on the device: dense leaves hold the
+ * kernel entries (a_ii = diag), admissible leaves the adaptive cross
+ * approximation recompressed to eps (opts->eps, opts->max_rank).  The matrix
+ * is stored in FP64.  Synchronises `stream`. */
+hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, void* stream, hm_matrix* out);
+
+/* H-LU (Algorithm 2) of A into new factors; A is not modified.  Uses
+ * opts->eps, max_rank, prec, exec.  On HM_ESINGULAR, *info (may be NULL) is the
+ * permuted global row of the first exact zero pivot; the factors are invalid.
+ * Synchronises `stream`. */
+hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info);
+
+/* Solve A X = B in place.  B: device, n x nrhs, column-major, leading
+ * dimension ldb >= n.  With A_or_null != NULL the solution is refined with
+ * r = b - A_H x (FP64 h_matvec) until every column has ||r|| / ||b|| <= rtol
+ * or max_iter corrections were applied (then HM_ENOCONV, X still the last
+ * iterate).  iters_host / relres_host (nrhs doubles) may be NULL.  A column's
+ * result does not depend on the other columns of the call. */
+hm_status h_solve(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                  void* stream, int* iters_host, double* relres_host);
+
+/* Y = alpha A_H X + beta Y; X, Y device, n x nrhs column-major. */
+hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, double beta, double* Y, int64_t ldy,
+                   int64_t nrhs, void* stream);
+
+/* Device bytes held by a handle: kind 0 matrix, 1 factors, 2 factor workspace
+ * (temporaries, scratch and DAG). */
+hm_status hm_footprint(const void* handle, int kind, size_t* bytes);
+
+/* Copy one leaf block to the host in FP64 (parity hook).  kind 0: matrix,
+ * 1: factors.  Dense leaf: data (m x n column-major), *rank = -1.  Low-rank
+ * leaf: data = U (m x rank) then V (n x rank), column-major, *rank = rank
+ * (call with data = NULL first to learn the rank).  Diagonal leaves of
+ * factors also fill piv (m int32, LAPACK interchanges, 0-based) if non-NULL. */
+hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* data, int32_t* rank, int32_t* piv);
+
+/* Statistics of the last h_lu on F. */
+hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out);
+
+/* The traced DAG without a device (host only), for inspection and tests.
+ * which: 0 = H-LU, 1 = solve.  sizes: ntasks, nedges, nlevels, task_bytes
+ * (sizeof one task record), n_f64, n_f32, n_piv (arena sizes in elements),
+ * nlr (low-rank leaves), nranks.  hm_dag_export copies (any pointer may be
+ * NULL): tasks (ntasks records), succ_ptr (ntasks + 1), succ_idx (nedges),
+ * level (ntasks), block_off (nblocks x 4 int64: data offset, data type,
+ * low-rank index, pivot offset; -1 where absent), lr (nlr x 6 int64: u_off,
+ * v_off, m, n, cap, type). */
+hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes);
+hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
+                        int32_t* level, int64_t* block_off, int64_t* lr);
+
+void hm_tree_free(hm_tree t);
+void hm_matrix_free(hm_matrix A);
+void hm_lu_free(hm_lu F);
+const char* hm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H_ */

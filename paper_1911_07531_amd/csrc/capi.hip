@@ -1,0 +1,963 @@
+// C-ABI of libhm: handles, device memory, executors and the entry points of
+// include/hm.h.  Host-only entry points (trees, DAG export) work without a
+// device; compute entry points fail with HM_EDEVICE when none is usable.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hm.h"
+#include "hm_internal.h"
+#include "host.h"
+
+namespace hm {
+// kernels.hip
+__global__ void exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end);
+__global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots);
+__global__ void exec_dataflow_kernel(ExecArgs a);
+__global__ void assemble_dense_kernel(ExecArgs a, AsmArgs s, const DenseAsm* blocks);
+__global__ void assemble_aca_kernel(ExecArgs a, AsmArgs s, const LrAsm* blocks, double* fac, int64_t fac_stride,
+                                    double aca_eps);
+__global__ void matvec_phase1_kernel(ExecArgs a, const MvLeaf* leaves, const int32_t* lr_leaves, const double* x,
+                                     int64_t ldx, int nrhs, double* T);
+__global__ void matvec_phase2_kernel(ExecArgs a, const MvLeaf* leaves, const int32_t* row_ptr, const MvRow* segs,
+                                     const int64_t* row_begin, const int32_t* row_size, const double* x, int64_t ldx,
+                                     int nrhs, const double* T, double* y, int64_t ldy, double alpha, double beta);
+__global__ void gather_rows_kernel(const double* src, int64_t lds_, const int64_t* perm, int64_t n, int nrhs,
+                                   double* dst, int64_t ldd);
+__global__ void scatter_rows_kernel(const double* src, int64_t lds_, const int64_t* perm, int64_t n, int nrhs,
+                                    double* dst, int64_t ldd, double alpha, double beta);
+__global__ void colnorm2_kernel(const double* v, int64_t ld, int64_t n, double* out);
+__global__ void axpy_cols_kernel(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
+                                 const int32_t* active);
+__global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs);
+}  // namespace hm
+
+using namespace hm;
+
+// ---------------------------------------------------------------------------
+// errors and allocation
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static hm_status fail(hm_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(HM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static void* (*g_alloc)(size_t, void*, void*) = nullptr;
+static void (*g_dealloc)(void*, size_t, void*, void*) = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+};
+
+static bool dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
+  b.bytes = bytes;
+  b.stream = s;
+  if (bytes == 0) {
+    b.p = nullptr;
+    return true;
+  }
+  if (g_alloc) {
+    b.p = g_alloc(bytes, (void*)s, g_alloc_ctx);
+    return b.p != nullptr;
+  }
+  return hipMalloc(&b.p, bytes) == hipSuccess;
+}
+
+static void dev_free(DevBuf& b) {
+  if (!b.p) return;
+  if (g_dealloc)
+    g_dealloc(b.p, b.bytes, (void*)b.stream, g_alloc_ctx);
+  else
+    (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <class T>
+static hm_status upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  if (!dev_alloc(b, v.size() * sizeof(T), s)) return fail(HM_ENOMEM, "device allocation failed");
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return HM_OK;
+}
+
+static hm_status device_ok() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(HM_EDEVICE, "no HIP device available");
+  return HM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct DevDag {
+  int64_t ntasks = 0, nlevels = 0, nedges = 0;
+  DevBuf tasks, indeg, succ_ptr, succ_idx, roots, order;
+  int32_t nroots = 0;
+  std::vector<int32_t> level_ptr;
+};
+
+struct PlanEntry {
+  Plan plan;
+  bool traced = false;
+  bool uploaded = false;
+  DevDag lu, solve;
+  DevBuf lr;
+  int device = -1;
+};
+
+struct hm_tree_s {
+  Tree t;
+  hm_opts opts;
+  std::map<std::pair<int, int>, std::unique_ptr<PlanEntry>> plans;  // (prec, max_rank)
+  std::mutex mu;
+  std::vector<int64_t> leaf_begin;  // leaf clusters in order
+  std::vector<int32_t> leaf_size;
+};
+
+struct hm_matrix_s {
+  hm_tree tree;
+  PlanEntry* pe;
+  int kernel;
+  double diag, eps;
+  int max_rank;
+  DevBuf f64, ranks, pts, perm;
+  // matvec tables
+  DevBuf mv_leaves, mv_lr, mv_row_ptr, mv_segs, mv_row_begin, mv_row_size, mv_T, mv_x, mv_y;
+  int64_t n_lr_leaves = 0, n_rows = 0;
+  DevBuf status;
+  size_t bytes() const {
+    return f64.bytes + ranks.bytes + pts.bytes + perm.bytes + mv_leaves.bytes + mv_lr.bytes + mv_row_ptr.bytes +
+           mv_segs.bytes + mv_row_begin.bytes + mv_row_size.bytes + mv_T.bytes + mv_x.bytes + mv_y.bytes;
+  }
+};
+
+struct ExecState {
+  DevBuf deps, queue, qctl, status, counters;
+};
+
+struct hm_lu_s {
+  hm_tree tree;
+  PlanEntry* pe;
+  int prec, exec;
+  double eps;
+  int max_rank;
+  DevBuf f64, f32, piv, ranks, perm;
+  ExecState lu_st, solve_st;
+  DevBuf work;  // solve/refinement vectors
+  size_t work_cols = 0;
+  hm_lu_stats stats;
+};
+
+static int g_nwg = 0;
+static int64_t g_clock_khz = 0;
+
+static hm_status device_setup() {
+  if (g_nwg > 0) return HM_OK;
+  hm_status st = device_ok();
+  if (st) return st;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int rate = 0;
+  if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate <= 0) rate = 100000;
+  g_clock_khz = rate;
+  (void)hipFuncSetAttribute((const void*)exec_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  (void)hipFuncSetAttribute((const void*)exec_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes);
+  (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)exec_dataflow_kernel, kThreads, kLdsBytes) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  g_nwg = cus * per_cu;
+  return HM_OK;
+}
+
+static const int64_t kScratchPerWg = kScratchDoubles;
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+static const int64_t kTempBudget = int64_t(4) << 30;
+
+static hm_status get_plan(hm_tree t, int prec, int max_rank, bool need_trace, PlanEntry** out) {
+  std::lock_guard<std::mutex> lk(t->mu);
+  auto key = std::make_pair(prec, max_rank);
+  auto it = t->plans.find(key);
+  PlanEntry* pe;
+  if (it == t->plans.end()) {
+    auto up = std::make_unique<PlanEntry>();
+    if (!make_layout(t->t, prec, max_rank, 64, up->plan)) return fail(HM_EINVAL, up->plan.err);
+    pe = up.get();
+    t->plans[key] = std::move(up);
+  } else {
+    pe = it->second.get();
+  }
+  if (need_trace && !pe->traced) {
+    if (!trace_lu(pe->plan, kTempBudget)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_solve(pe->plan)) return fail(HM_EINVAL, pe->plan.err);
+    pe->traced = true;
+  }
+  *out = pe;
+  return HM_OK;
+}
+
+static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
+  dd.ntasks = (int64_t)d.tasks.size();
+  dd.nedges = d.nedges;
+  dd.nlevels = (int64_t)d.level_ptr.size() - 1;
+  dd.level_ptr = d.level_ptr;
+  dd.nroots = (int32_t)d.roots.size();
+  hm_status st;
+  if ((st = upload(dd.tasks, d.tasks, s))) return st;
+  if ((st = upload(dd.indeg, d.indeg, s))) return st;
+  if ((st = upload(dd.succ_ptr, d.succ_ptr, s))) return st;
+  if ((st = upload(dd.succ_idx, d.succ_idx, s))) return st;
+  if ((st = upload(dd.roots, d.roots, s))) return st;
+  if ((st = upload(dd.order, d.level_order, s))) return st;
+  return HM_OK;
+}
+
+static hm_status ensure_uploaded(PlanEntry* pe, hipStream_t s) {
+  if (pe->uploaded) return HM_OK;
+  hm_status st;
+  if ((st = upload_dag(pe->plan.lu, pe->lu, s))) return st;
+  if ((st = upload_dag(pe->plan.solve, pe->solve, s))) return st;
+  if ((st = upload(pe->lr, pe->plan.lr, s))) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  pe->uploaded = true;
+  return HM_OK;
+}
+
+static hm_status exec_state_alloc(ExecState& es, int64_t ntasks, hipStream_t s) {
+  if (!dev_alloc(es.deps, std::max<int64_t>(1, ntasks) * 4, s) ||
+      !dev_alloc(es.queue, std::max<int64_t>(1, ntasks) * 4, s) || !dev_alloc(es.qctl, 64, s) ||
+      !dev_alloc(es.status, 64, s) || !dev_alloc(es.counters, 64, s))
+    return fail(HM_ENOMEM, "device allocation failed (executor state)");
+  return HM_OK;
+}
+
+static void exec_state_free(ExecState& es) {
+  dev_free(es.deps);
+  dev_free(es.queue);
+  dev_free(es.qctl);
+  dev_free(es.status);
+  dev_free(es.counters);
+}
+
+// Run a DAG on `s`.  Returns the executor's device time in *ms.
+static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, hipStream_t s, float* ms) {
+  if (dd.ntasks == 0) {
+    if (ms) *ms = 0.f;
+    return HM_OK;
+  }
+  a.tasks = (const Task*)dd.tasks.p;
+  a.ntasks = (int32_t)dd.ntasks;
+  a.succ_ptr = (const int32_t*)dd.succ_ptr.p;
+  a.succ_idx = (const int32_t*)dd.succ_idx.p;
+  a.deps = (int32_t*)es.deps.p;
+  a.queue = (int32_t*)es.queue.p;
+  a.qctl = (int32_t*)es.qctl.p;
+  a.status = (int32_t*)es.status.p;
+  a.counters = (unsigned long long*)es.counters.p;
+  a.nwg = g_nwg;
+  a.spin_limit = g_clock_khz * 1000 * 30;  // 30 s of wall clock
+  HIPCHK(hipMemsetAsync(es.status.p, 0, 16, s));
+  int32_t big = 0x7fffffff;
+  HIPCHK(hipMemcpyAsync((char*)es.status.p + 4, &big, 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(es.counters.p, 0, 16, s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  if (mode == HM_EXEC_LEVEL) {
+    HIPCHK(hipEventRecord(e0, s));
+    for (int64_t l = 0; l < dd.nlevels; ++l) {
+      int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
+      int grid = std::min(e - b, g_nwg);
+      hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsBytes, s, a,
+                         (const int32_t*)dd.order.p, b, e);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, s));
+  } else {
+    int rg = (int)std::min<int64_t>(1024, (dd.ntasks + 255) / 256);
+    hipLaunchKernelGGL(exec_reset_kernel, dim3(rg), dim3(256), 0, s, a, (const int32_t*)dd.indeg.p,
+                       (const int32_t*)dd.roots.p, dd.nroots);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsBytes, s, a);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, s));
+  }
+  if (ms) {
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return HM_OK;
+}
+
+static ExecArgs base_args(double* f64, float* f32, int32_t* piv, int32_t* ranks, const LrDesc* lr, double eps,
+                          int max_rank) {
+  ExecArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.f64 = f64;
+  a.f32 = f32;
+  a.piv = piv;
+  a.ranks = ranks;
+  a.lr = lr;
+  a.eps = eps;
+  a.max_rank = max_rank;
+  return a;
+}
+
+static bool valid_opts(const hm_opts* o) {
+  return o && o->leaf >= 1 && o->eta > 0 && o->eps >= 0 && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
+         (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL);
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hm_last_error(void) { return g_err.c_str(); }
+
+hm_status hm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*dealloc)(void*, size_t, void*, void*),
+                           void* ctx) {
+  if ((alloc == nullptr) != (dealloc == nullptr)) return fail(HM_EINVAL, "allocator and deallocator come in pairs");
+  g_alloc = alloc;
+  g_dealloc = dealloc;
+  g_alloc_ctx = ctx;
+  return HM_OK;
+}
+
+hm_status build_htree(const double* pts, int64_t n, int dim, const hm_opts* opts, hm_tree* out) {
+  if (!pts || !out || !opts) return fail(HM_EINVAL, "null pointer");
+  if (n < 1 || opts->leaf < 1 || !(opts->eta > 0) || (dim != 2 && dim != 3))
+    return fail(HM_EINVAL, "need n >= 1, leaf >= 1, eta > 0, dim in {2,3}");
+  if (n > (int64_t)1 << 30) return fail(HM_EINVAL, "n too large");
+  auto t = new (std::nothrow) hm_tree_s();
+  if (!t) return fail(HM_ENOMEM, "host allocation failed");
+  t->opts = *opts;
+  build_cluster_tree(pts, n, dim, opts->leaf, t->t);
+  build_block_tree(t->t, opts->eta);
+  for (const Cluster& c : t->t.cl)
+    if (c.leaf()) {
+      t->leaf_begin.push_back(c.begin);
+      t->leaf_size.push_back((int32_t)c.size());
+    }
+  *out = t;
+  return HM_OK;
+}
+
+hm_status hm_tree_sizes(hm_tree t, int64_t* n, int64_t* ncl, int64_t* nbl) {
+  if (!t) return fail(HM_EINVAL, "null tree");
+  if (n) *n = t->t.n;
+  if (ncl) *ncl = (int64_t)t->t.cl.size();
+  if (nbl) *nbl = (int64_t)t->t.bl.size();
+  return HM_OK;
+}
+
+hm_status hm_tree_export(hm_tree t, int64_t* perm, int64_t* clusters, double* boxes, int32_t* blocks) {
+  if (!t) return fail(HM_EINVAL, "null tree");
+  if (perm) std::memcpy(perm, t->t.perm.data(), t->t.n * sizeof(int64_t));
+  for (size_t i = 0; i < t->t.cl.size(); ++i) {
+    const Cluster& c = t->t.cl[i];
+    if (clusters) {
+      int64_t* r = clusters + 5 * i;
+      r[0] = c.begin;
+      r[1] = c.end;
+      r[2] = c.son[0];
+      r[3] = c.son[1];
+      r[4] = c.level;
+    }
+    if (boxes)
+      for (int d = 0; d < 3; ++d) {
+        boxes[6 * i + d] = c.lo[d];
+        boxes[6 * i + 3 + d] = c.hi[d];
+      }
+  }
+  if (blocks)
+    for (size_t i = 0; i < t->t.bl.size(); ++i) {
+      const BlockNode& b = t->t.bl[i];
+      int32_t* r = blocks + 7 * i;
+      r[0] = b.tau;
+      r[1] = b.sigma;
+      r[2] = b.kind;
+      for (int k = 0; k < 4; ++k) r[3 + k] = b.son[k];
+    }
+  return HM_OK;
+}
+
+void hm_tree_free(hm_tree t) {
+  if (!t) return;
+  for (auto& kv : t->plans) {
+    PlanEntry* pe = kv.second.get();
+    for (DevDag* dd : {&pe->lu, &pe->solve}) {
+      dev_free(dd->tasks);
+      dev_free(dd->indeg);
+      dev_free(dd->succ_ptr);
+      dev_free(dd->succ_idx);
+      dev_free(dd->roots);
+      dev_free(dd->order);
+    }
+    dev_free(pe->lr);
+  }
+  delete t;
+}
+
+hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes) {
+  if (!t || !opts || !sizes || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
+  if (opts->max_rank < 0 || opts->max_rank > kMaxCap) return fail(HM_EINVAL, "max_rank must be in [0, 64]");
+  PlanEntry* pe;
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, true, &pe);
+  if (st) return st;
+  const Dag& d = which == 0 ? pe->plan.lu : pe->plan.solve;
+  sizes[0] = (int64_t)d.tasks.size();
+  sizes[1] = d.nedges;
+  sizes[2] = (int64_t)d.level_ptr.size() - 1;
+  sizes[3] = (int64_t)sizeof(Task);
+  sizes[4] = pe->plan.n_f64;
+  sizes[5] = pe->plan.n_f32;
+  sizes[6] = pe->plan.n_piv;
+  sizes[7] = (int64_t)pe->plan.lr.size();
+  sizes[8] = pe->plan.nranks;
+  return HM_OK;
+}
+
+hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
+                        int32_t* level, int64_t* block_off, int64_t* lr) {
+  if (!t || !opts || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
+  PlanEntry* pe;
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, true, &pe);
+  if (st) return st;
+  const Plan& p = pe->plan;
+  const Dag& d = which == 0 ? p.lu : p.solve;
+  if (tasks) std::memcpy(tasks, d.tasks.data(), d.tasks.size() * sizeof(Task));
+  if (succ_ptr) std::memcpy(succ_ptr, d.succ_ptr.data(), d.succ_ptr.size() * 4);
+  if (succ_idx) std::memcpy(succ_idx, d.succ_idx.data(), d.succ_idx.size() * 4);
+  if (level) std::memcpy(level, d.level.data(), d.level.size() * 4);
+  if (block_off)
+    for (size_t b = 0; b < p.data_off.size(); ++b) {
+      block_off[4 * b] = p.data_off[b];
+      block_off[4 * b + 1] = p.data_type[b];
+      block_off[4 * b + 2] = p.lr_index[b];
+      block_off[4 * b + 3] = p.piv_off[b];
+    }
+  if (lr)
+    for (size_t i = 0; i < p.lr.size(); ++i) {
+      lr[6 * i] = p.lr[i].u_off;
+      lr[6 * i + 1] = p.lr[i].v_off;
+      lr[6 * i + 2] = p.lr[i].m;
+      lr[6 * i + 3] = p.lr[i].n;
+      lr[6 * i + 4] = p.lr[i].cap;
+      lr[6 * i + 5] = p.lr[i].type;
+    }
+  return HM_OK;
+}
+
+// ----------------------------------------------------------------------------
+hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, void* stream, hm_matrix* out) {
+  if (!t || !out) return fail(HM_EINVAL, "null pointer");
+  if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
+  if (kernel != HM_LAPLACE3D && kernel != HM_LOG2D) return fail(HM_EINVAL, "unknown kernel");
+  hm_status st = device_setup();
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PlanEntry* pe;
+  if ((st = get_plan(t, HM_FP64, opts->max_rank, false, &pe))) return st;
+  const Plan& p = pe->plan;
+  const Tree& tr = t->t;
+  auto A = std::make_unique<hm_matrix_s>();
+  A->tree = t;
+  A->pe = pe;
+  A->kernel = kernel;
+  A->diag = diag;
+  A->eps = opts->eps;
+  A->max_rank = opts->max_rank;
+  // A's arena: blocks only (no temporaries, no panel)
+  if (!dev_alloc(A->f64, p.blocks_f64 * 8, s) || !dev_alloc(A->ranks, p.nranks * 4, s) ||
+      !dev_alloc(A->status, 64, s))
+    return fail(HM_ENOMEM, "device allocation failed (matrix)");
+  HIPCHK(hipMemsetAsync(A->ranks.p, 0, p.nranks * 4, s));
+  HIPCHK(hipMemsetAsync(A->status.p, 0, 64, s));
+  if ((st = upload(A->pts, tr.pts_perm, s))) return st;
+  if ((st = upload(A->perm, tr.perm, s))) return st;
+  DevBuf lrbuf;
+  if ((st = upload(lrbuf, p.lr, s))) return st;
+  ExecArgs a = base_args((double*)A->f64.p, nullptr, nullptr, (int32_t*)A->ranks.p, (const LrDesc*)lrbuf.p,
+                         opts->eps, opts->max_rank);
+  a.status = (int32_t*)A->status.p;
+  AsmArgs as{(const double*)A->pts.p, kernel, diag};
+  // dense leaves
+  std::vector<DenseAsm> dense;
+  std::vector<LrAsm> lrs;
+  for (size_t b = 0; b < tr.bl.size(); ++b) {
+    const BlockNode& bn = tr.bl[b];
+    if (bn.kind == BK_DENSE)
+      dense.push_back(DenseAsm{p.data_off[b], tr.cl[bn.tau].begin, tr.cl[bn.sigma].begin,
+                               (int32_t)tr.cl[bn.tau].size(), (int32_t)tr.cl[bn.sigma].size(), VT_F64, 0});
+    else if (bn.kind == BK_LOWRANK)
+      lrs.push_back(LrAsm{tr.cl[bn.tau].begin, tr.cl[bn.sigma].begin, p.lr_index[b], 0});
+  }
+  DevBuf dbuf;
+  if ((st = upload(dbuf, dense, s))) return st;
+  if (!dense.empty()) {
+    hipLaunchKernelGGL(assemble_dense_kernel, dim3((unsigned)dense.size()), dim3(kThreads), 0, s, a, as,
+                       (const DenseAsm*)dbuf.p);
+    HIPCHK(hipGetLastError());
+  }
+  // low-rank leaves: ACA in batches bounded by scratch memory, largest first
+  std::sort(lrs.begin(), lrs.end(), [&](const LrAsm& x, const LrAsm& y) {
+    const LrDesc &dx = p.lr[x.lr], &dy = p.lr[y.lr];
+    return dx.m + dx.n > dy.m + dy.n;
+  });
+  DevBuf lbuf;
+  if ((st = upload(lbuf, lrs, s))) return st;
+  const int64_t fac_budget = int64_t(2) << 30;
+  DevBuf scratch, fac;
+  const int maxb = std::max(1, g_nwg);
+  if (!dev_alloc(scratch, (size_t)maxb * kScratchPerWg * 8, s)) return fail(HM_ENOMEM, "device allocation failed");
+  a.scratch = (double*)scratch.p;
+  a.scratch_stride = kScratchPerWg;
+  size_t i0 = 0;
+  size_t fac_bytes = 0;
+  while (i0 < lrs.size()) {
+    const LrDesc& d0 = p.lr[lrs[i0].lr];
+    int64_t stride = ((int64_t)(d0.m + d0.n) * kMaxK * 8 + d0.m + 255) / 256 * 32;  // doubles
+    int64_t cnt = std::min<int64_t>({(int64_t)(lrs.size() - i0), maxb, std::max<int64_t>(1, fac_budget / (stride * 8))});
+    size_t need = (size_t)(cnt * stride * 8);
+    if (need > fac_bytes) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_free(fac);
+      if (!dev_alloc(fac, need, s)) return fail(HM_ENOMEM, "device allocation failed (ACA)");
+      fac_bytes = need;
+    }
+    double aca_eps = opts->eps > 0 ? opts->eps * 0.1 : 1e-14;
+    hipLaunchKernelGGL(assemble_aca_kernel, dim3((unsigned)cnt), dim3(kThreads), kLdsBytes, s, a, as,
+                       (const LrAsm*)lbuf.p + i0, (double*)fac.p, stride, aca_eps);
+    HIPCHK(hipGetLastError());
+    i0 += cnt;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  dev_free(fac);
+  dev_free(scratch);
+  dev_free(dbuf);
+  dev_free(lbuf);
+  dev_free(lrbuf);
+  int32_t stv[4];
+  HIPCHK(hipMemcpy(stv, A->status.p, 16, hipMemcpyDeviceToHost));
+  // matvec tables
+  std::vector<MvLeaf> leaves;
+  std::vector<int32_t> lr_leaves;
+  std::vector<int32_t> leaf_of_block(tr.bl.size(), -1);
+  for (size_t b = 0; b < tr.bl.size(); ++b) {
+    const BlockNode& bn = tr.bl[b];
+    if (bn.kind == BK_STRUCT) continue;
+    MvLeaf L;
+    L.r0 = tr.cl[bn.tau].begin;
+    L.c0 = tr.cl[bn.sigma].begin;
+    L.m = (int32_t)tr.cl[bn.tau].size();
+    L.n = (int32_t)tr.cl[bn.sigma].size();
+    L.type = VT_F64;
+    if (bn.kind == BK_DENSE) {
+      L.off = p.data_off[b];
+      L.u_off = L.v_off = 0;
+      L.lr = -1;
+    } else {
+      const LrDesc& d = p.lr[p.lr_index[b]];
+      L.off = 0;
+      L.u_off = d.u_off;
+      L.v_off = d.v_off;
+      L.lr = p.lr_index[b];
+      lr_leaves.push_back((int32_t)leaves.size());
+    }
+    leaf_of_block[b] = (int32_t)leaves.size();
+    leaves.push_back(L);
+  }
+  // row segments per leaf cluster
+  const auto& lb = t->leaf_begin;
+  std::vector<std::vector<MvRow>> per(lb.size());
+  for (size_t i = 0; i < leaves.size(); ++i) {
+    const MvLeaf& L = leaves[i];
+    auto it = std::lower_bound(lb.begin(), lb.end(), L.r0);
+    for (; it != lb.end() && *it < L.r0 + L.m; ++it) {
+      size_t rc = it - lb.begin();
+      per[rc].push_back(MvRow{(int32_t)i, (int32_t)(*it - L.r0)});
+    }
+  }
+  std::vector<int32_t> row_ptr(1, 0);
+  std::vector<MvRow> segs;
+  for (auto& v : per) {
+    segs.insert(segs.end(), v.begin(), v.end());
+    row_ptr.push_back((int32_t)segs.size());
+  }
+  if ((st = upload(A->mv_leaves, leaves, s))) return st;
+  if ((st = upload(A->mv_lr, lr_leaves, s))) return st;
+  if ((st = upload(A->mv_row_ptr, row_ptr, s))) return st;
+  if ((st = upload(A->mv_segs, segs, s))) return st;
+  if ((st = upload(A->mv_row_begin, t->leaf_begin, s))) return st;
+  if ((st = upload(A->mv_row_size, t->leaf_size, s))) return st;
+  A->n_lr_leaves = (int64_t)lr_leaves.size();
+  A->n_rows = (int64_t)lb.size();
+  if (!dev_alloc(A->mv_T, std::max<size_t>(1, p.lr.size()) * kMaxCap * 16 * 8, s) ||
+      !dev_alloc(A->mv_x, (size_t)tr.n * 16 * 8, s) || !dev_alloc(A->mv_y, (size_t)tr.n * 16 * 8, s))
+    return fail(HM_ENOMEM, "device allocation failed (matvec)");
+  HIPCHK(hipStreamSynchronize(s));
+  *out = A.release();
+  if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "compression wanted more than 64 columns");
+  return HM_OK;
+}
+
+void hm_matrix_free(hm_matrix A) {
+  if (!A) return;
+  for (DevBuf* b : {&A->f64, &A->ranks, &A->pts, &A->perm, &A->mv_leaves, &A->mv_lr, &A->mv_row_ptr, &A->mv_segs,
+                    &A->mv_row_begin, &A->mv_row_size, &A->mv_T, &A->mv_x, &A->mv_y, &A->status})
+    dev_free(*b);
+  delete A;
+}
+
+// y = alpha A x + beta y, user ordering
+static hm_status matvec_impl(hm_matrix A, double alpha, const double* X, int64_t ldx, double beta, double* Y,
+                             int64_t ldy, int64_t nrhs, hipStream_t s) {
+  const Plan& p = A->pe->plan;
+  const int64_t n = A->tree->t.n;
+  ExecArgs a = base_args((double*)A->f64.p, nullptr, nullptr, (int32_t*)A->ranks.p, nullptr, A->eps, A->max_rank);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 16) {
+    int nc = (int)std::min<int64_t>(16, nrhs - c0);
+    int64_t tot = n * nc;
+    unsigned g = (unsigned)((tot + 255) / 256);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, s, X + c0 * ldx, ldx,
+                       (const int64_t*)A->perm.p, n, nc, (double*)A->mv_x.p, n);
+    if (A->n_lr_leaves > 0)
+      hipLaunchKernelGGL(matvec_phase1_kernel, dim3((unsigned)A->n_lr_leaves), dim3(kThreads), 0, s, a,
+                         (const MvLeaf*)A->mv_leaves.p, (const int32_t*)A->mv_lr.p, (const double*)A->mv_x.p, n, nc,
+                         (double*)A->mv_T.p);
+    hipLaunchKernelGGL(matvec_phase2_kernel, dim3((unsigned)A->n_rows), dim3(kThreads), 0, s, a,
+                       (const MvLeaf*)A->mv_leaves.p, (const int32_t*)A->mv_row_ptr.p, (const MvRow*)A->mv_segs.p,
+                       (const int64_t*)A->mv_row_begin.p, (const int32_t*)A->mv_row_size.p,
+                       (const double*)A->mv_x.p, n, nc, (const double*)A->mv_T.p, (double*)A->mv_y.p, n, 1.0, 0.0);
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)A->mv_y.p, n,
+                       (const int64_t*)A->perm.p, n, nc, Y + c0 * ldy, ldy, alpha, beta);
+  }
+  HIPCHK(hipGetLastError());
+  (void)p;
+  return HM_OK;
+}
+
+hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, double beta, double* Y, int64_t ldy,
+                   int64_t nrhs, void* stream) {
+  if (!A || !X || !Y) return fail(HM_EINVAL, "null pointer");
+  const int64_t n = A->tree->t.n;
+  if (nrhs < 0 || ldx < n || ldy < n) return fail(HM_EINVAL, "bad leading dimension or nrhs");
+  if (nrhs == 0) return HM_OK;
+  hm_status st = device_setup();
+  if (st) return st;
+  return matvec_impl(A, alpha, X, ldx, beta, Y, ldy, nrhs, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------------------
+hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info) {
+  if (!A || !out) return fail(HM_EINVAL, "null pointer");
+  if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
+  if (opts->max_rank != A->max_rank) return fail(HM_EINVAL, "max_rank differs from the assembled matrix");
+  hm_status st = device_setup();
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hm_tree t = A->tree;
+  PlanEntry* pe;
+  if ((st = get_plan(t, opts->prec, opts->max_rank, true, &pe))) return st;
+  if ((st = ensure_uploaded(pe, s))) return st;
+  const Plan& p = pe->plan;
+  const Plan& pa = A->pe->plan;
+  auto F = std::make_unique<hm_lu_s>();
+  F->tree = t;
+  F->pe = pe;
+  F->prec = opts->prec;
+  F->exec = opts->exec;
+  F->eps = opts->eps;
+  F->max_rank = opts->max_rank;
+  std::memset(&F->stats, 0, sizeof(F->stats));
+  if (!dev_alloc(F->f64, p.n_f64 * 8, s) || !dev_alloc(F->f32, p.n_f32 * 4, s) ||
+      !dev_alloc(F->piv, std::max<int64_t>(1, p.n_piv) * 4, s) || !dev_alloc(F->ranks, p.nranks * 4, s))
+    return fail(HM_ENOMEM, "device allocation failed (factors)");
+  if ((st = upload(F->perm, t->t.perm, s))) return st;
+  if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
+  if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
+  // copy A into the factor layout
+  HIPCHK(hipMemcpyAsync(F->ranks.p, A->ranks.p, p.nranks * 4, hipMemcpyDeviceToDevice, s));
+  if (opts->prec == HM_FP64) {
+    HIPCHK(hipMemcpyAsync(F->f64.p, A->f64.p, pa.blocks_f64 * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<CopyDesc> cd;
+    const Tree& tr = t->t;
+    for (size_t b = 0; b < tr.bl.size(); ++b) {
+      const BlockNode& bn = tr.bl[b];
+      if (bn.kind == BK_DENSE) {
+        int64_t cnt = tr.cl[bn.tau].size() * tr.cl[bn.sigma].size();
+        cd.push_back(CopyDesc{pa.data_off[b], p.data_off[b], cnt, p.data_type[b], 0});
+      } else if (bn.kind == BK_LOWRANK) {
+        const LrDesc& da = pa.lr[pa.lr_index[b]];
+        const LrDesc& dl = p.lr[p.lr_index[b]];
+        cd.push_back(CopyDesc{da.u_off, dl.u_off, (int64_t)da.m * da.cap, dl.type, 0});
+        cd.push_back(CopyDesc{da.v_off, dl.v_off, (int64_t)da.n * da.cap, dl.type, 0});
+      }
+    }
+    DevBuf cbuf;
+    if ((st = upload(cbuf, cd, s))) return st;
+    if (!cd.empty())
+      hipLaunchKernelGGL(convert_blocks_kernel, dim3((unsigned)cd.size()), dim3(256), 0, s, (const double*)A->f64.p,
+                         (double*)F->f64.p, (float*)F->f32.p, (const CopyDesc*)cbuf.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(cbuf);
+  }
+  DevBuf scratch;
+  if (!dev_alloc(scratch, (size_t)g_nwg * kScratchPerWg * 8, s)) return fail(HM_ENOMEM, "device allocation failed");
+  ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
+                         (const LrDesc*)pe->lr.p, opts->eps, opts->max_rank);
+  a.scratch = (double*)scratch.p;
+  a.scratch_stride = kScratchPerWg;
+  float ms = 0.f;
+  st = run_dag(pe->lu, a, F->lu_st, opts->exec, s, &ms);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  dev_free(scratch);
+  int32_t stv[4];
+  unsigned long long ctr[2];
+  HIPCHK(hipMemcpy(stv, F->lu_st.status.p, 16, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ctr, F->lu_st.counters.p, 16, hipMemcpyDeviceToHost));
+  F->stats.ntasks = pe->lu.ntasks;
+  F->stats.nedges = pe->lu.nedges;
+  F->stats.nlevels = pe->lu.nlevels;
+  for (const Task& tk : p.lu.tasks)
+    if (tk.op >= 0 && tk.op < 10) F->stats.tasks_by_op[tk.op]++;
+  F->stats.bytes_alg = (int64_t)ctr[0];
+  F->stats.flops_alg = (int64_t)ctr[1];
+  F->stats.exec_ms = ms;
+  F->stats.temp_bytes = p.temp_bytes;
+  F->stats.rank_overflows = stv[2];
+  if (info) *info = 0;
+  if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  if (stv[0] & ST_SINGULAR) {
+    if (info) *info = stv[1];
+    hm_lu_s* f = F.release();
+    hm_lu_free(f);
+    return fail(HM_ESINGULAR, "exact zero pivot in a diagonal leaf");
+  }
+  *out = F.release();
+  if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "a truncation wanted more than 64 columns");
+  return HM_OK;
+}
+
+void hm_lu_free(hm_lu F) {
+  if (!F) return;
+  for (DevBuf* b : {&F->f64, &F->f32, &F->piv, &F->ranks, &F->perm, &F->work}) dev_free(*b);
+  exec_state_free(F->lu_st);
+  exec_state_free(F->solve_st);
+  delete F;
+}
+
+hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out) {
+  if (!F || !out) return fail(HM_EINVAL, "null pointer");
+  *out = F->stats;
+  return HM_OK;
+}
+
+// one pass of the traced forward/backward substitution on up to 64 columns in
+// permuted order held in the factor's panel
+static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
+  PlanEntry* pe = F->pe;
+  HIPCHK(hipMemcpyAsync((int32_t*)F->ranks.p + pe->plan.nrhs_slot, &nc, 4, hipMemcpyHostToDevice, s));
+  ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
+                         (const LrDesc*)pe->lr.p, F->eps, F->max_rank);
+  return run_dag(pe->solve, a, F->solve_st, F->exec, s, nullptr);
+}
+
+hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                  void* stream, int* iters_host, double* relres_host) {
+  if (!F || !B) return fail(HM_EINVAL, "null pointer");
+  const int64_t n = F->tree->t.n;
+  if (nrhs < 0 || ldb < n || max_iter < 0) return fail(HM_EINVAL, "bad nrhs, ldb or max_iter");
+  if (A && A->tree != F->tree) return fail(HM_EINVAL, "matrix and factors are on different trees");
+  if (nrhs == 0) return HM_OK;
+  hm_status st = device_setup();
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Plan& p = F->pe->plan;
+  double* panel = (double*)F->f64.p + p.panel_off;
+  const int64_t CW = p.nrhs_cap;
+  // work: b copy, residual (user order), norms, active flags
+  size_t need = (size_t)(3 * n * CW + 4 * CW) * 8;
+  if (F->work.bytes < need) {
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(F->work);
+    if (!dev_alloc(F->work, need, s)) return fail(HM_ENOMEM, "device allocation failed (solve work)");
+  }
+  double* bcopy = (double*)F->work.p;
+  double* R = bcopy + n * CW;
+  double* norms = R + n * CW;
+  int32_t* active = (int32_t*)(norms + 2 * CW);
+  bool all_conv = true;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += CW) {
+    const int nc = (int)std::min<int64_t>(CW, nrhs - c0);
+    double* Bc = B + c0 * ldb;
+    const int64_t tot = n * nc;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+    if (A) HIPCHK(hipMemcpy2DAsync(bcopy, n * 8, Bc, ldb * 8, n * 8, nc, hipMemcpyDeviceToDevice, s));
+    // x0 = U^{-1} L^{-1} P b
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)Bc, ldb,
+                       (const int64_t*)F->perm.p, n, nc, panel, n);
+    if ((st = solve_pass(F, nc, s))) return st;
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)panel, n,
+                       (const int64_t*)F->perm.p, n, nc, Bc, ldb, 1.0, 0.0);
+    HIPCHK(hipGetLastError());
+    if (!A) continue;
+    std::vector<double> bn(nc), rn(nc);
+    std::vector<int32_t> act(nc, 1);
+    hipLaunchKernelGGL(colnorm2_kernel, dim3(nc), dim3(kThreads), 0, s, (const double*)bcopy, n, n, norms);
+    HIPCHK(hipMemcpyAsync(bn.data(), norms, nc * 8, hipMemcpyDeviceToHost, s));
+    int it = 0;
+    for (;;) {
+      // r = b - A x
+      HIPCHK(hipMemcpyAsync(R, bcopy, n * nc * 8, hipMemcpyDeviceToDevice, s));
+      if ((st = matvec_impl(A, -1.0, Bc, ldb, 1.0, R, n, nc, s))) return st;
+      hipLaunchKernelGGL(colnorm2_kernel, dim3(nc), dim3(kThreads), 0, s, (const double*)R, n, n, norms);
+      HIPCHK(hipMemcpyAsync(rn.data(), norms, nc * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool done = true;
+      for (int c = 0; c < nc; ++c) {
+        double rel = bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]);
+        if (relres_host) relres_host[c0 + c] = rel;
+        act[c] = rel > rtol ? 1 : 0;
+        if (act[c]) done = false;
+      }
+      if (done) break;
+      if (it >= max_iter) {
+        all_conv = false;
+        break;
+      }
+      // x += solve(r) on the columns still above rtol
+      HIPCHK(hipMemcpyAsync(active, act.data(), nc * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)R, n,
+                         (const int64_t*)F->perm.p, n, nc, panel, n);
+      if ((st = solve_pass(F, nc, s))) return st;
+      hipLaunchKernelGGL(scatter_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)panel, n,
+                         (const int64_t*)F->perm.p, n, nc, R, n, 1.0, 0.0);
+      hipLaunchKernelGGL(axpy_cols_kernel, dim3(g), dim3(256), 0, s, Bc, ldb, (const double*)R, n, n, nc,
+                         (const int32_t*)active);
+      HIPCHK(hipGetLastError());
+      ++it;
+    }
+    if (iters_host) iters_host[c0 / CW] = it;
+  }
+  if (A) {
+    int32_t stv[4];
+    HIPCHK(hipMemcpy(stv, F->solve_st.status.p, 16, hipMemcpyDeviceToHost));
+    if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  }
+  if (!all_conv) return fail(HM_ENOCONV, "refinement did not reach rtol");
+  return HM_OK;
+}
+
+hm_status hm_footprint(const void* handle, int kind, size_t* bytes) {
+  if (!handle || !bytes) return fail(HM_EINVAL, "null pointer");
+  if (kind == 0) {
+    *bytes = ((const hm_matrix_s*)handle)->bytes();
+  } else if (kind == 1 || kind == 2) {
+    const hm_lu_s* F = (const hm_lu_s*)handle;
+    const Plan& p = F->pe->plan;
+    size_t blocks = (size_t)p.blocks_f64 * 8 + (size_t)p.blocks_f32 * 4 + F->piv.bytes + F->ranks.bytes;
+    size_t total = F->f64.bytes + F->f32.bytes + F->piv.bytes + F->ranks.bytes + F->perm.bytes + F->work.bytes +
+                   F->lu_st.deps.bytes + F->lu_st.queue.bytes + F->solve_st.deps.bytes + F->solve_st.queue.bytes;
+    *bytes = kind == 1 ? blocks : total - blocks;
+  } else {
+    return fail(HM_EINVAL, "kind must be 0, 1 or 2");
+  }
+  return HM_OK;
+}
+
+hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* data, int32_t* rank, int32_t* piv) {
+  if (!handle || !rank) return fail(HM_EINVAL, "null pointer");
+  hm_tree t;
+  const Plan* p;
+  const void* f64;
+  const void* f32;
+  const void* ranks;
+  const void* pivs = nullptr;
+  if (kind == 0) {
+    const hm_matrix_s* A = (const hm_matrix_s*)handle;
+    t = A->tree;
+    p = &A->pe->plan;
+    f64 = A->f64.p;
+    f32 = nullptr;
+    ranks = A->ranks.p;
+  } else if (kind == 1) {
+    const hm_lu_s* F = (const hm_lu_s*)handle;
+    t = F->tree;
+    p = &F->pe->plan;
+    f64 = F->f64.p;
+    f32 = F->f32.p;
+    ranks = F->ranks.p;
+    pivs = F->piv.p;
+  } else {
+    return fail(HM_EINVAL, "kind must be 0 or 1");
+  }
+  if (block < 0 || block >= (int64_t)t->t.bl.size()) return fail(HM_EINVAL, "block index out of range");
+  const BlockNode& bn = t->t.bl[block];
+  if (bn.kind == BK_STRUCT) return fail(HM_EINVAL, "not a leaf block");
+  const int64_t m = t->t.cl[bn.tau].size(), n = t->t.cl[bn.sigma].size();
+  auto fetch = [&](int64_t off, int type, int64_t count, double* dst) -> hm_status {
+    if (type == VT_F64) {
+      HIPCHK(hipMemcpy(dst, (const double*)f64 + off, count * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(count);
+      HIPCHK(hipMemcpy(tmp.data(), (const float*)f32 + off, count * 4, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < count; ++i) dst[i] = tmp[i];
+    }
+    return HM_OK;
+  };
+  hm_status st;
+  if (bn.kind == BK_DENSE) {
+    *rank = -1;
+    if (data && (st = fetch(p->data_off[block], p->data_type[block], m * n, data))) return st;
+    if (piv && pivs && p->piv_off[block] >= 0)
+      HIPCHK(hipMemcpy(piv, (const int32_t*)pivs + p->piv_off[block], m * 4, hipMemcpyDeviceToHost));
+    return HM_OK;
+  }
+  const int li = p->lr_index[block];
+  const LrDesc& d = p->lr[li];
+  int32_t k = 0;
+  HIPCHK(hipMemcpy(&k, (const int32_t*)ranks + li, 4, hipMemcpyDeviceToHost));
+  *rank = k;
+  if (data && k > 0) {
+    if ((st = fetch(d.u_off, d.type, m * k, data))) return st;
+    if ((st = fetch(d.v_off, d.type, n * k, data + m * k))) return st;
+  }
+  return HM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal structures shared by the host trace (C++) and the device executor (HIP).
+//
+// The H-LU of Algorithm 2 (with Algorithms 1 and 3 and their leaf branches)
+// is traced once on the host into a list of leaf-level tasks.  Each task
+// works on strided views of block storage held in one device arena per
+// element type.  Data dependencies follow Def. 3.1 / Def. 3.2 (outputs of one
+// task intersecting inputs of another on the same storage), extended with
+// write-after-read and write-after-write ordering so that any topological
+// order reproduces the sequential result.
+#pragma once
+#include <cstdint>
+
+namespace hm {
+
+constexpr int kThreads = 256;      // threads per workgroup of every block kernel
+constexpr int kMaxK = 128;         // widest stacked rank in a truncated addition
+constexpr int kMaxCap = 64;        // widest stored rank of a low-rank leaf
+constexpr int kMaxLeaf = 128;      // largest diagonal leaf the getrf/trsm kernels take
+constexpr int kLdsBytes = 80 * 1024;  // dynamic LDS per workgroup
+constexpr int kNrhsSlotOffset = 0; // rank slot that carries the current nrhs of a solve
+
+enum ViewType : int32_t { VT_F64 = 0, VT_F32 = 1, VT_IDENT = 2, VT_NONE = 3 };
+enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2 };
+
+// Strided matrix view: element (i, j) lives at arena[off + i*rs + j*cs].
+// With DYN_ROWS / DYN_COLS the extent is ranks[rank_id] (a low-rank leaf's
+// current rank, or the nrhs of a solve), bounded by rows / cols.
+struct View {
+  int64_t off;
+  int32_t rows, cols;
+  int32_t rs, cs;
+  int32_t type;
+  int32_t dyn;
+  int32_t rank_id;
+  int32_t pad_;
+};
+
+enum Op : int32_t {
+  OP_NOP = 0,
+  OP_GETRF = 1,    // a: diagonal leaf (f64, m x m, col-major), piv: int32 offset
+  OP_TRSM_L = 2,   // x <- L^{-1} P x     (a: packed LU of a diagonal leaf, piv)
+  OP_TRSM_UT = 3,  // x <- U^{-T} x
+  OP_TRSM_U = 4,   // x <- U^{-1} x
+  OP_GEMM = 5,     // y <- beta y + alpha a b
+  OP_LRGEMM = 6,   // y <- beta y + alpha a (b x)
+  OP_TRUNC = 7,    // low-rank leaf lr <- T_eps(U V^T + alpha pad(a) pad(b)^T)
+  OP_ZERO = 8,     // y <- 0
+  OP_COPY = 9,     // y <- a (element type conversion allowed)
+};
+
+struct Task {
+  int32_t op;
+  int32_t lr;        // OP_TRUNC: low-rank leaf index
+  int32_t r0, c0;    // OP_TRUNC: offsets of the term inside the leaf
+  int32_t row0;      // OP_GETRF: first permuted row of the leaf (error report)
+  int32_t pad_;
+  int64_t piv;       // OP_GETRF / OP_TRSM_L: offset into the int32 pivot arena
+  double alpha, beta;
+  View y, a, b, x;
+};
+
+// One low-rank leaf: U (m x cap) and V (n x cap), column-major, in the arena of
+// element type `type`; its current rank is ranks[index].
+struct LrDesc {
+  int64_t u_off, v_off;
+  int32_t m, n, cap, type;
+};
+
+// Device-side arguments of an executor launch.
+struct ExecArgs {
+  double* f64;
+  float* f32;
+  int32_t* piv;
+  int32_t* ranks;
+  const LrDesc* lr;
+  const Task* tasks;
+  int32_t ntasks;
+  int32_t pad0_;
+  double eps;
+  int32_t max_rank;
+  int32_t nwg;
+  int32_t* status;     // [0] error code, [1] first singular row, [2] rank overflow count
+  double* scratch;     // per-workgroup f64 scratch, scratch_stride doubles each
+  int64_t scratch_stride;
+  // dataflow executor
+  const int32_t* succ_ptr;
+  const int32_t* succ_idx;
+  int32_t* deps;       // remaining predecessor counts
+  int32_t* queue;      // ready queue (ntasks slots, -1 = empty)
+  int32_t* qctl;       // [0] head, [1] tail, [2] done, [3] abort
+  int64_t spin_limit;  // wall-clock ticks a waiting workgroup polls before giving up
+  unsigned long long* counters;  // [0] algorithmic bytes, [1] algorithmic flops (null: off)
+};
+
+
+// Assembly, matvec and conversion descriptors (one per workgroup).
+struct AsmArgs {
+  const double* pts;  // n x 3, permuted order
+  int kernel;         // 0: 1/(4 pi r), 1: -log(r)/(2 pi)
+  double diag;
+};
+struct DenseAsm {
+  int64_t off;
+  int64_t r0, c0;     // permuted row / column start
+  int32_t m, n, type, pad;
+};
+struct LrAsm {
+  int64_t r0, c0;
+  int32_t lr;         // low-rank leaf index
+  int32_t pad;
+};
+struct MvLeaf {
+  int64_t off, u_off, v_off;  // dense data or low-rank factors
+  int64_t r0, c0;             // permuted row / column start of the leaf
+  int32_t m, n, lr, type;     // lr >= 0: low-rank leaf index
+};
+struct MvRow {                // one leaf's rows inside a leaf row cluster
+  int32_t leaf;
+  int32_t lrow;               // first row of the segment inside the leaf
+};
+struct CopyDesc {
+  int64_t src, dst, count;
+  int32_t dst_type, pad;
+};
+
+constexpr int64_t kScratchDoubles = 4 * kMaxK * kMaxK + 4 * kMaxK * kMaxCap + 6 * kMaxK + 64;
+
+enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4 };
+
+}  // namespace hm

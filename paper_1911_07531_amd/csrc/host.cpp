@@ -1,0 +1,872 @@
+// Host side of the H-LU library: trees (Def. 2.1, Def. 2.2), storage layout
+// (Def. 2.3) and the symbolic trace of Algorithms 1-3 into a task DAG.
+//
+// The trace walks the recursion of hlu / htrsl / htrsu / hmul exactly as the
+// sequential algorithm would run it and records, instead of arithmetic, one
+// task per leaf-level block operation together with the storage it reads and
+// writes (Def. 3.1).  Edges follow Def. 3.2 (an output intersecting a later
+// input on the same storage) plus write-after-read and write-after-write
+// ordering, so that every topological order of the DAG computes the
+// sequential result.
+#include "host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+namespace hm {
+
+// ---------------------------------------------------------------------------
+// Def. 2.1: cluster tree by geometric bisection of the longest axis
+// ---------------------------------------------------------------------------
+// Compiled with -ffp-contract=off: the bounding boxes, midpoints and the
+// admissibility test must round exactly like a plain evaluation.
+void build_cluster_tree(const double* pts, int64_t n, int dim, int leaf, Tree& t) {
+  t.n = n;
+  t.dim = dim;
+  t.leaf = leaf;
+  t.cl.clear();
+  t.perm.clear();
+  t.perm.reserve(n);
+  std::vector<double> p3(3 * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d) p3[3 * i + d] = pts[i * dim + d];
+
+  std::function<int(std::vector<int64_t>&, int)> rec = [&](std::vector<int64_t>& idx, int level) -> int {
+    Cluster c;
+    c.begin = (int64_t)t.perm.size();
+    c.end = -1;
+    c.son[0] = c.son[1] = -1;
+    c.level = level;
+    for (int d = 0; d < 3; ++d) {
+      c.lo[d] = p3[3 * idx[0] + d];
+      c.hi[d] = p3[3 * idx[0] + d];
+    }
+    for (int64_t i : idx)
+      for (int d = 0; d < 3; ++d) {
+        double v = p3[3 * i + d];
+        if (v < c.lo[d]) c.lo[d] = v;
+        if (v > c.hi[d]) c.hi[d] = v;
+      }
+    int me = (int)t.cl.size();
+    t.cl.push_back(c);
+    if ((int64_t)idx.size() > leaf) {
+      int axis = 0;
+      double best = c.hi[0] - c.lo[0];
+      for (int d = 1; d < 3; ++d) {
+        double e = c.hi[d] - c.lo[d];
+        if (e > best) {
+          best = e;
+          axis = d;
+        }
+      }
+      double mid = 0.5 * (c.lo[axis] + c.hi[axis]);
+      std::vector<int64_t> left, right;
+      left.reserve(idx.size());
+      right.reserve(idx.size());
+      for (int64_t i : idx) (p3[3 * i + axis] <= mid ? left : right).push_back(i);
+      if (!left.empty() && !right.empty()) {
+        std::vector<int64_t>().swap(idx);
+        int s0 = rec(left, level + 1);
+        int s1 = rec(right, level + 1);
+        t.cl[me].son[0] = s0;
+        t.cl[me].son[1] = s1;
+      }
+    }
+    if (t.cl[me].son[0] < 0)
+      for (int64_t i : idx) t.perm.push_back(i);
+    t.cl[me].end = (int64_t)t.perm.size();
+    return me;
+  };
+  std::vector<int64_t> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  rec(all, 0);
+  t.pts_perm.assign(3 * n, 0.0);
+  for (int64_t k = 0; k < n; ++k)
+    for (int d = 0; d < 3; ++d) t.pts_perm[3 * k + d] = p3[3 * t.perm[k] + d];
+}
+
+static double diam(const Cluster& c) {
+  double s = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double e = c.hi[d] - c.lo[d];
+    s = s + e * e;
+  }
+  return std::sqrt(s);
+}
+
+// Standard admissibility (Sec. 5.1) on bounding boxes; touching boxes are inadmissible.
+static bool admissible(const Cluster& t, const Cluster& s, double eta) {
+  double g2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double g = std::max(0.0, std::max(s.lo[d] - t.hi[d], t.lo[d] - s.hi[d]));
+    g2 = g2 + g * g;
+  }
+  double dist = std::sqrt(g2);
+  if (dist <= 0.0) return false;
+  return std::min(diam(t), diam(s)) <= eta * dist;
+}
+
+// Def. 2.2: sons(t, s) empty if admissible or a cluster is a leaf; pre-order numbering.
+void build_block_tree(Tree& t, double eta) {
+  t.eta = eta;
+  t.bl.clear();
+  std::function<int(int, int)> rec = [&](int tau, int sigma) -> int {
+    BlockNode b;
+    b.tau = tau;
+    b.sigma = sigma;
+    for (int k = 0; k < 4; ++k) b.son[k] = -1;
+    int me = (int)t.bl.size();
+    const Cluster& ct = t.cl[tau];
+    const Cluster& cs = t.cl[sigma];
+    if (admissible(ct, cs, eta))
+      b.kind = BK_LOWRANK;
+    else if (ct.leaf() || cs.leaf())
+      b.kind = BK_DENSE;
+    else
+      b.kind = BK_STRUCT;
+    t.bl.push_back(b);
+    if (b.kind == BK_STRUCT) {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          int s = rec(ct.son[i], cs.son[j]);
+          t.bl[me].son[2 * i + j] = s;
+        }
+    }
+    return me;
+  };
+  rec(0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Def. 2.3: storage of the leaves
+// ---------------------------------------------------------------------------
+static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p) {
+  p.tree = &t;
+  p.prec = prec;
+  p.max_rank = max_rank;
+  if (max_rank < 0 || max_rank > kMaxCap) {
+    p.err = "max_rank must be in [0, 64]";
+    return false;
+  }
+  p.cap = max_rank > 0 ? max_rank : kMaxCap;
+  p.nrhs_cap = nrhs_cap;
+  size_t nb = t.bl.size();
+  p.data_off.assign(nb, -1);
+  p.data_type.assign(nb, -1);
+  p.lr_index.assign(nb, -1);
+  p.piv_off.assign(nb, -1);
+  p.lr.clear();
+  p.lr_block.clear();
+  p.diag_leaves.clear();
+  int64_t f64 = 0, f32 = 0, piv = 0;
+  const int64_t A = 32;
+  for (size_t b = 0; b < nb; ++b) {
+    const BlockNode& bn = t.bl[b];
+    if (bn.kind == BK_STRUCT) continue;
+    int64_t m = t.cl[bn.tau].size(), n = t.cl[bn.sigma].size();
+    bool diag = bn.tau == bn.sigma;
+    int type = (prec == 1 && !diag) ? VT_F32 : VT_F64;
+    if (bn.kind == BK_DENSE) {
+      if (diag && m > kMaxLeaf) {
+        p.err = "diagonal leaf larger than 128 rows";
+        return false;
+      }
+      int64_t& cur = type == VT_F64 ? f64 : f32;
+      cur = align_up(cur, A);
+      p.data_off[b] = cur;
+      p.data_type[b] = type;
+      cur += m * n;
+      if (diag) {
+        p.piv_off[b] = piv;
+        piv += m;
+        p.diag_leaves.push_back((int)b);
+      }
+    } else {
+      LrDesc d;
+      d.m = (int32_t)m;
+      d.n = (int32_t)n;
+      d.cap = (int32_t)std::min<int64_t>(p.cap, std::min(m, n));
+      d.type = type;
+      int64_t& cur = type == VT_F64 ? f64 : f32;
+      cur = align_up(cur, A);
+      d.u_off = cur;
+      cur += m * d.cap;
+      cur = align_up(cur, A);
+      d.v_off = cur;
+      cur += n * d.cap;
+      p.lr_index[b] = (int32_t)p.lr.size();
+      p.lr.push_back(d);
+      p.lr_block.push_back((int32_t)b);
+    }
+  }
+  p.blocks_f64 = align_up(f64, A);
+  p.blocks_f32 = align_up(f32, A);
+  p.panel_off = p.blocks_f64;
+  p.n_f64 = p.panel_off + t.n * (int64_t)nrhs_cap;
+  p.n_f32 = p.blocks_f32;
+  p.n_piv = piv;
+  p.nrhs_slot = (int)p.lr.size();
+  p.nranks = p.nrhs_slot + 1;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Symbolic trace
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Rect {
+  int32_t r0, r1, c0, c1;
+};
+static bool overlap(const Rect& a, const Rect& b) {
+  return a.r0 < b.r1 && b.r0 < a.r1 && a.c0 < b.c1 && b.c0 < a.c1;
+}
+static bool covers(const Rect& a, const Rect& b) {
+  return a.r0 <= b.r0 && a.r1 >= b.r1 && a.c0 <= b.c0 && a.c1 >= b.c1;
+}
+
+// A view plus the storage it touches: object id and the rectangle in the
+// object's own (row, col) storage coordinates.
+struct HView {
+  View v;
+  int obj;
+  Rect rect;
+  bool tr;
+};
+
+struct Term {
+  HView u, v;  // U (rows x k), V (cols x k)
+  int32_t r0, c0;
+  double alpha;
+};
+
+struct Rec {
+  Rect r;
+  int task;
+};
+struct ObjState {
+  std::vector<Rec> writes, reads;
+};
+
+enum { ACC_R = 1, ACC_W = 2, ACC_RW = 3 };
+
+class Tracer {
+ public:
+  Tracer(Plan& p, Dag& d, int64_t temp_budget_bytes) : p_(p), t_(*p.tree), d_(d) {
+    tsize_ = p.prec == 1 ? 4 : 8;
+    temp_type_ = p.prec == 1 ? VT_F32 : VT_F64;
+    temp_budget_ = temp_budget_bytes / tsize_;
+    size_t nb = t_.bl.size();
+    obj_a_.assign(nb, -1);
+    obj_b_.assign(nb, -1);
+    for (size_t b = 0; b < nb; ++b) {
+      if (t_.bl[b].kind == BK_DENSE) obj_a_[b] = new_obj();
+      if (t_.bl[b].kind == BK_LOWRANK) {
+        obj_a_[b] = new_obj();
+        obj_b_[b] = new_obj();
+      }
+    }
+    temp_base_ = p.prec == 1 ? p.blocks_f32 : p.n_f64;
+    temp_top_ = temp_base_;
+  }
+
+  bool ok() const { return err_.empty(); }
+  const std::string& err() const { return err_; }
+  int64_t temp_end() const { return temp_top_; }
+
+  // ---- views -------------------------------------------------------------
+  HView dense(int b) {
+    const BlockNode& bn = t_.bl[b];
+    int32_t m = (int32_t)t_.cl[bn.tau].size(), n = (int32_t)t_.cl[bn.sigma].size();
+    HView h;
+    h.v = View{p_.data_off[b], m, n, 1, m, p_.data_type[b], 0, -1, 0};
+    h.obj = obj_a_[b];
+    h.rect = Rect{0, m, 0, n};
+    h.tr = false;
+    return h;
+  }
+  HView lr_u(int b) {
+    const LrDesc& d = p_.lr[p_.lr_index[b]];
+    HView h;
+    h.v = View{d.u_off, d.m, d.cap, 1, d.m, d.type, DYN_COLS, p_.lr_index[b], 0};
+    h.obj = obj_a_[b];
+    h.rect = Rect{0, d.m, 0, d.cap};
+    h.tr = false;
+    return h;
+  }
+  HView lr_v(int b) {
+    const LrDesc& d = p_.lr[p_.lr_index[b]];
+    HView h;
+    h.v = View{d.v_off, d.n, d.cap, 1, d.n, d.type, DYN_COLS, p_.lr_index[b], 0};
+    h.obj = obj_b_[b];
+    h.rect = Rect{0, d.n, 0, d.cap};
+    h.tr = false;
+    return h;
+  }
+  static HView ident(int32_t m) {
+    HView h;
+    h.v = View{0, m, m, 0, 0, VT_IDENT, 0, -1, 0};
+    h.obj = -1;
+    h.rect = Rect{0, 0, 0, 0};
+    h.tr = false;
+    return h;
+  }
+  static HView transpose(const HView& x) {
+    HView h = x;
+    std::swap(h.v.rows, h.v.cols);
+    std::swap(h.v.rs, h.v.cs);
+    int dyn = 0;
+    if (x.v.dyn & DYN_ROWS) dyn |= DYN_COLS;
+    if (x.v.dyn & DYN_COLS) dyn |= DYN_ROWS;
+    h.v.dyn = dyn;
+    h.tr = !x.tr;
+    return h;
+  }
+  HView rows(const HView& x, int32_t a, int32_t b) {
+    if (x.v.dyn & DYN_ROWS) fail("row slice of a view with a run-time row count");
+    HView h = x;
+    if (x.v.type == VT_IDENT) {
+      // a row slice of I is a shifted identity: only used through restriction,
+      // which the trace expresses as a sub-view of a materialised factor
+      fail("row slice of an identity view");
+      return h;
+    }
+    h.v.off = x.v.off + (int64_t)a * x.v.rs;
+    h.v.rows = b - a;
+    if (!x.tr) {
+      h.rect.r0 = x.rect.r0 + a;
+      h.rect.r1 = x.rect.r0 + b;
+    } else {
+      h.rect.c0 = x.rect.c0 + a;
+      h.rect.c1 = x.rect.c0 + b;
+    }
+    return h;
+  }
+  // Temporary panel rows x cols (cols may follow a rank slot), in the LU's
+  // off-diagonal element type.  Temporaries live in rings per size class;
+  // reusing a slot orders the new writer after every earlier access.
+  HView temp(int32_t r, int32_t cols, int dyn_rank_id) {
+    int64_t elems = (int64_t)r * cols;
+    int cls = 0;
+    int64_t sz = 1024;
+    while (sz < elems) {
+      sz <<= 1;
+      ++cls;
+    }
+    if ((int)pools_.size() <= cls) pools_.resize(cls + 1);
+    Pool& pool = pools_[cls];
+    if (pool.limit == 0) pool.limit = std::max<int64_t>(64, std::min<int64_t>(1 << 16, temp_budget_ / 8 / sz));
+    int64_t slot = pool.next % pool.limit;
+    pool.next++;
+    if (slot >= (int64_t)pool.off.size()) {
+      temp_top_ = align_up(temp_top_, 32);
+      pool.off.push_back(temp_top_);
+      pool.obj.push_back(new_obj());
+      temp_top_ += sz;
+    }
+    HView h;
+    h.v = View{pool.off[slot], r, cols, 1, r, temp_type_, dyn_rank_id >= 0 ? DYN_COLS : 0, dyn_rank_id, 0};
+    h.obj = pool.obj[slot];
+    h.rect = Rect{0, r, 0, cols};
+    h.tr = false;
+    return h;
+  }
+  HView panel() {
+    HView h;
+    h.v = View{p_.panel_off, (int32_t)t_.n, p_.nrhs_cap, 1, (int32_t)t_.n, VT_F64, DYN_COLS, p_.nrhs_slot, 0};
+    if (panel_obj_ < 0) panel_obj_ = new_obj();
+    h.obj = panel_obj_;
+    h.rect = Rect{0, (int32_t)t_.n, 0, p_.nrhs_cap};
+    h.tr = false;
+    return h;
+  }
+
+  // ---- task emission with dependency tracking (Def. 3.2 + WAR/WAW) -----------
+  void emit(Task tk, std::initializer_list<std::pair<const HView*, int>> acc) {
+    int id = (int)d_.tasks.size();
+    d_.tasks.push_back(tk);
+    preds_.clear();
+    for (auto& a : acc)
+      if (a.first->obj >= 0 && (a.second & ACC_R)) access(id, a.first->obj, a.first->rect, false);
+    for (auto& a : acc)
+      if (a.first->obj >= 0 && (a.second & ACC_W)) access(id, a.first->obj, a.first->rect, true);
+    std::sort(preds_.begin(), preds_.end());
+    preds_.erase(std::unique(preds_.begin(), preds_.end()), preds_.end());
+    int lvl = 0;
+    for (int q : preds_) {
+      edges_.push_back({q, id});
+      lvl = std::max(lvl, d_.level[q] + 1);
+    }
+    d_.level.push_back(lvl);
+    d_.indeg.push_back((int32_t)preds_.size());
+  }
+
+  void finish() {
+    int nt = (int)d_.tasks.size();
+    d_.nedges = (int64_t)edges_.size();
+    d_.succ_ptr.assign(nt + 1, 0);
+    for (auto& e : edges_) d_.succ_ptr[e.first + 1]++;
+    for (int i = 0; i < nt; ++i) d_.succ_ptr[i + 1] += d_.succ_ptr[i];
+    d_.succ_idx.assign(edges_.size(), 0);
+    std::vector<int32_t> fill(d_.succ_ptr.begin(), d_.succ_ptr.end() - 1);
+    for (auto& e : edges_) d_.succ_idx[fill[e.first]++] = e.second;
+    std::vector<std::pair<int, int>>().swap(edges_);
+    int nl = 0;
+    for (int l : d_.level) nl = std::max(nl, l + 1);
+    d_.level_ptr.assign(nl + 1, 0);
+    for (int l : d_.level) d_.level_ptr[l + 1]++;
+    for (int i = 0; i < nl; ++i) d_.level_ptr[i + 1] += d_.level_ptr[i];
+    d_.level_order.assign(nt, 0);
+    std::vector<int32_t> pos(d_.level_ptr.begin(), d_.level_ptr.end() - 1);
+    for (int i = 0; i < nt; ++i) d_.level_order[pos[d_.level[i]]++] = i;
+    d_.roots.clear();
+    for (int i = 0; i < nt; ++i)
+      if (d_.indeg[i] == 0) d_.roots.push_back(i);
+  }
+
+  // ---- leaf operations ------------------------------------------------------
+  static Task blank(int op) {
+    Task t;
+    std::memset(&t, 0, sizeof(t));
+    t.op = op;
+    t.lr = -1;
+    t.piv = -1;
+    View none{0, 0, 0, 0, 0, VT_NONE, 0, -1, 0};
+    t.y = t.a = t.b = t.x = none;
+    return t;
+  }
+  void gemm(const HView& y, double alpha, const HView& a, const HView& b, double beta) {
+    Task t = blank(OP_GEMM);
+    t.alpha = alpha;
+    t.beta = beta;
+    t.y = y.v;
+    t.a = a.v;
+    t.b = b.v;
+    emit(t, {{&a, ACC_R}, {&b, ACC_R}, {&y, beta != 0.0 ? ACC_RW : ACC_W}});
+  }
+  void lrgemm(const HView& y, double alpha, const HView& a, const HView& b, const HView& x, double beta) {
+    Task t = blank(OP_LRGEMM);
+    t.alpha = alpha;
+    t.beta = beta;
+    t.y = y.v;
+    t.a = a.v;
+    t.b = b.v;
+    t.x = x.v;
+    emit(t, {{&a, ACC_R}, {&b, ACC_R}, {&x, ACC_R}, {&y, beta != 0.0 ? ACC_RW : ACC_W}});
+  }
+  void zero(const HView& y) {
+    Task t = blank(OP_ZERO);
+    t.y = y.v;
+    emit(t, {{&y, ACC_W}});
+  }
+  void trsm(int op, int d, const HView& x) {
+    Task t = blank(op);
+    HView a = dense(d);
+    t.a = a.v;
+    t.piv = p_.piv_off[d];
+    t.x = x.v;
+    emit(t, {{&a, ACC_R}, {&x, ACC_RW}});
+  }
+  void getrf(int d) {
+    Task t = blank(OP_GETRF);
+    HView a = dense(d);
+    t.a = a.v;
+    t.piv = p_.piv_off[d];
+    t.row0 = (int32_t)t_.cl[t_.bl[d].tau].begin;
+    emit(t, {{&a, ACC_RW}});
+  }
+  void trunc(int c, const Term& term) {
+    int li = p_.lr_index[c];
+    const LrDesc& d = p_.lr[li];
+    int kb = term.u.v.cols;  // static bound of the term's rank
+    if (d.cap + kb > kMaxK) fail("stacked rank above 128 in a truncated addition");
+    Task t = blank(OP_TRUNC);
+    t.lr = li;
+    t.r0 = term.r0;
+    t.c0 = term.c0;
+    t.alpha = term.alpha;
+    t.a = term.u.v;
+    t.b = term.v.v;
+    HView cu = lr_u(c), cv = lr_v(c);
+    emit(t, {{&term.u, ACC_R}, {&term.v, ACC_R}, {&cu, ACC_RW}, {&cv, ACC_RW}});
+  }
+
+  // ---- exact products (no truncation) ---------------------------------------
+  // y += alpha B x
+  void hmat_mul_into(const HView& y, double alpha, int b, const HView& x) {
+    const BlockNode& bn = t_.bl[b];
+    if (bn.kind == BK_DENSE) {
+      gemm(y, alpha, dense(b), x, 1.0);
+    } else if (bn.kind == BK_LOWRANK) {
+      lrgemm(y, alpha, lr_u(b), transpose(lr_v(b)), x, 1.0);
+    } else {
+      int64_t rb = t_.cl[bn.tau].begin, cb = t_.cl[bn.sigma].begin;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          int s = bn.son[2 * i + j];
+          const Cluster& ct = t_.cl[t_.bl[s].tau];
+          const Cluster& cs = t_.cl[t_.bl[s].sigma];
+          hmat_mul_into(rows(y, (int32_t)(ct.begin - rb), (int32_t)(ct.end - rb)), alpha, s,
+                        rows(x, (int32_t)(cs.begin - cb), (int32_t)(cs.end - cb)));
+        }
+    }
+  }
+  // y += alpha B^T x
+  void hmat_tmul_into(const HView& y, double alpha, int b, const HView& x) {
+    const BlockNode& bn = t_.bl[b];
+    if (bn.kind == BK_DENSE) {
+      gemm(y, alpha, transpose(dense(b)), x, 1.0);
+    } else if (bn.kind == BK_LOWRANK) {
+      lrgemm(y, alpha, lr_v(b), transpose(lr_u(b)), x, 1.0);
+    } else {
+      int64_t rb = t_.cl[bn.tau].begin, cb = t_.cl[bn.sigma].begin;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          int s = bn.son[2 * i + j];
+          const Cluster& ct = t_.cl[t_.bl[s].tau];
+          const Cluster& cs = t_.cl[t_.bl[s].sigma];
+          hmat_tmul_into(rows(y, (int32_t)(cs.begin - cb), (int32_t)(cs.end - cb)), alpha, s,
+                         rows(x, (int32_t)(ct.begin - rb), (int32_t)(ct.end - rb)));
+        }
+    }
+  }
+
+  // alpha A B as exact low-rank terms (the leaf-case products after Algorithm 1).
+  void product_terms(double alpha, int a, int b, int32_t ro, int32_t co, std::vector<Term>& out) {
+    const BlockNode& A = t_.bl[a];
+    const BlockNode& B = t_.bl[b];
+    int32_t ra = (int32_t)t_.cl[A.tau].size();
+    int32_t cb_ = (int32_t)t_.cl[B.sigma].size();
+    if (A.kind == BK_STRUCT && B.kind == BK_STRUCT) {
+      int64_t rbase = t_.cl[A.tau].begin, cbase = t_.cl[B.sigma].begin;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int l = 0; l < 2; ++l) {
+            int sa = A.son[2 * i + l], sb = B.son[2 * l + j];
+            int32_t r = (int32_t)(t_.cl[t_.bl[sa].tau].begin - rbase);
+            int32_t c = (int32_t)(t_.cl[t_.bl[sb].sigma].begin - cbase);
+            product_terms(alpha, sa, sb, ro + r, co + c, out);
+          }
+      return;
+    }
+    Term tm;
+    tm.r0 = ro;
+    tm.c0 = co;
+    tm.alpha = alpha;
+    if (A.kind == BK_LOWRANK) {
+      // U = U_A, V = B^T V_A
+      int li = p_.lr_index[a];
+      HView z = temp(cb_, p_.lr[li].cap, li);
+      if (B.kind == BK_DENSE)
+        gemm(z, 1.0, transpose(dense(b)), lr_v(a), 0.0);
+      else if (B.kind == BK_LOWRANK)
+        lrgemm(z, 1.0, lr_v(b), transpose(lr_u(b)), lr_v(a), 0.0);
+      else {
+        zero(z);
+        hmat_tmul_into(z, 1.0, b, lr_v(a));
+      }
+      tm.u = lr_u(a);
+      tm.v = z;
+    } else if (B.kind == BK_LOWRANK) {
+      // U = A U_B, V = V_B
+      int li = p_.lr_index[b];
+      HView y = temp(ra, p_.lr[li].cap, li);
+      if (A.kind == BK_DENSE)
+        gemm(y, 1.0, dense(a), lr_u(b), 0.0);
+      else {
+        zero(y);
+        hmat_mul_into(y, 1.0, a, lr_u(b));
+      }
+      tm.u = y;
+      tm.v = lr_v(b);
+    } else if (A.kind == BK_DENSE && B.kind == BK_DENSE) {
+      if (t_.cl[A.sigma].leaf()) {
+        tm.u = dense(a);
+        tm.v = transpose(dense(b));
+      } else {
+        HView y = temp(ra, cb_, -1);
+        gemm(y, 1.0, dense(a), dense(b), 0.0);
+        tm.u = y;
+        tm.v = ident(cb_);
+      }
+    } else if (A.kind == BK_DENSE) {
+      // B structured, row cluster of A is a leaf: U = I, V = B^T A^T
+      HView z = temp(cb_, ra, -1);
+      zero(z);
+      hmat_tmul_into(z, 1.0, b, transpose(dense(a)));
+      tm.u = ident(ra);
+      tm.v = z;
+    } else {
+      // A structured, B dense, column cluster of B is a leaf: U = A B, V = I
+      HView y = temp(ra, cb_, -1);
+      zero(y);
+      hmat_mul_into(y, 1.0, a, dense(b));
+      tm.u = y;
+      tm.v = ident(cb_);
+    }
+    out.push_back(tm);
+  }
+
+  // Restrict a term to rows [rl, rh) x cols [cl, ch) of its target (relative);
+  // returns false if empty.  Identity factors are materialised when sliced.
+  bool restrict_term(const Term& in, int32_t rl, int32_t rh, int32_t cl, int32_t ch, Term& out) {
+    int32_t mu = in.u.v.rows, mv = in.v.v.rows;
+    int32_t a0 = std::max(in.r0, rl), a1 = std::min(in.r0 + mu, rh);
+    int32_t b0 = std::max(in.c0, cl), b1 = std::min(in.c0 + mv, ch);
+    if (a0 >= a1 || b0 >= b1) return false;
+    out = in;
+    out.r0 = a0 - rl;
+    out.c0 = b0 - cl;
+    if (a0 != in.r0 || a1 != in.r0 + mu) out.u = slice_factor(in.u, a0 - in.r0, a1 - in.r0);
+    if (b0 != in.c0 || b1 != in.c0 + mv) out.v = slice_factor(in.v, b0 - in.c0, b1 - in.c0);
+    return true;
+  }
+  HView slice_factor(const HView& f, int32_t a, int32_t b) {
+    if (f.v.type != VT_IDENT) return rows(f, a, b);
+    // rows [a, b) of I_m: a (b-a) x m matrix with ones at (i, a+i)
+    int32_t m = f.v.rows;
+    HView z = temp(b - a, m, -1);
+    zero(z);
+    HView e = ident(b - a);
+    // copy I_{b-a} into columns [a, b) of z
+    HView zc = z;
+    zc.v.off += (int64_t)a * z.v.cs;
+    zc.v.cols = b - a;
+    zc.rect.c0 = a;
+    zc.rect.c1 = b;
+    Task t = blank(OP_COPY);
+    t.y = zc.v;
+    t.a = e.v;
+    emit(t, {{&zc, ACC_W}});
+    return z;
+  }
+
+  void add_term_to_leaf(int c, const Term& tm) {
+    const BlockNode& C = t_.bl[c];
+    if (C.kind == BK_DENSE) {
+      HView y = dense(c);
+      HView ys = rows(y, tm.r0, tm.r0 + tm.u.v.rows);
+      // column slice [c0, c0 + rows(V))
+      ys.v.off += (int64_t)tm.c0 * ys.v.cs;
+      ys.v.cols = tm.v.v.rows;
+      ys.rect.c0 = tm.c0;
+      ys.rect.c1 = tm.c0 + tm.v.v.rows;
+      gemm(ys, tm.alpha, tm.u, transpose(tm.v), 1.0);
+    } else {
+      trunc(c, tm);
+    }
+  }
+
+  void leaf_update(double alpha, int a, int b, int c) {
+    std::vector<Term> terms;
+    product_terms(alpha, a, b, 0, 0, terms);
+    const BlockNode& C = t_.bl[c];
+    if (C.kind != BK_STRUCT) {
+      for (auto& tm : terms) add_term_to_leaf(c, tm);
+      return;
+    }
+    if (terms.size() != 1) {
+      fail("structured target with a multi-term product");
+      return;
+    }
+    int64_t br = t_.cl[C.tau].begin, bc = t_.cl[C.sigma].begin;
+    std::function<void(int)> visit = [&](int x) {
+      const BlockNode& X = t_.bl[x];
+      if (X.kind == BK_STRUCT) {
+        for (int k = 0; k < 4; ++k) visit(X.son[k]);
+        return;
+      }
+      const Cluster& ct = t_.cl[X.tau];
+      const Cluster& cs = t_.cl[X.sigma];
+      Term r;
+      if (restrict_term(terms[0], (int32_t)(ct.begin - br), (int32_t)(ct.end - br), (int32_t)(cs.begin - bc),
+                        (int32_t)(cs.end - bc), r))
+        add_term_to_leaf(x, r);
+    };
+    visit(c);
+  }
+
+  // Algorithm 1
+  void hmul(double alpha, int a, int b, int c) {
+    const BlockNode& A = t_.bl[a];
+    const BlockNode& B = t_.bl[b];
+    const BlockNode& C = t_.bl[c];
+    if (A.kind == BK_STRUCT && B.kind == BK_STRUCT && C.kind == BK_STRUCT) {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int l = 0; l < 2; ++l) hmul(alpha, A.son[2 * i + l], B.son[2 * l + j], C.son[2 * i + j]);
+    } else {
+      leaf_update(alpha, a, b, c);
+    }
+  }
+
+  // Panel solves over a diagonal block (leaf or structured).
+  void solve_lower(int d, const HView& x) {
+    const BlockNode& D = t_.bl[d];
+    if (D.kind == BK_DENSE) {
+      trsm(OP_TRSM_L, d, x);
+      return;
+    }
+    int32_t n0 = (int32_t)t_.cl[t_.bl[D.son[0]].tau].size(), nn = (int32_t)t_.cl[D.tau].size();
+    HView x0 = rows(x, 0, n0), x1 = rows(x, n0, nn);
+    solve_lower(D.son[0], x0);
+    hmat_mul_into(x1, -1.0, D.son[2], x0);
+    solve_lower(D.son[3], x1);
+  }
+  void solve_upper_t(int d, const HView& x) {
+    const BlockNode& D = t_.bl[d];
+    if (D.kind == BK_DENSE) {
+      trsm(OP_TRSM_UT, d, x);
+      return;
+    }
+    int32_t n0 = (int32_t)t_.cl[t_.bl[D.son[0]].tau].size(), nn = (int32_t)t_.cl[D.tau].size();
+    HView x0 = rows(x, 0, n0), x1 = rows(x, n0, nn);
+    solve_upper_t(D.son[0], x0);
+    hmat_tmul_into(x1, -1.0, D.son[1], x0);
+    solve_upper_t(D.son[3], x1);
+  }
+  void solve_upper(int d, const HView& x) {
+    const BlockNode& D = t_.bl[d];
+    if (D.kind == BK_DENSE) {
+      trsm(OP_TRSM_U, d, x);
+      return;
+    }
+    int32_t n0 = (int32_t)t_.cl[t_.bl[D.son[0]].tau].size(), nn = (int32_t)t_.cl[D.tau].size();
+    HView x0 = rows(x, 0, n0), x1 = rows(x, n0, nn);
+    solve_upper(D.son[3], x1);
+    hmat_mul_into(x0, -1.0, D.son[1], x1);
+    solve_upper(D.son[0], x0);
+  }
+
+  // Algorithm 3: L X = M (X overwrites M)
+  void htrsl(int ld, int m) {
+    const BlockNode& M = t_.bl[m];
+    const BlockNode& L = t_.bl[ld];
+    if (M.kind == BK_STRUCT) {
+      for (int j = 0; j < 2; ++j) htrsl(L.son[0], M.son[j]);
+      for (int j = 0; j < 2; ++j) hmul(-1.0, L.son[2], M.son[j], M.son[2 + j]);
+      for (int j = 0; j < 2; ++j) htrsl(L.son[3], M.son[2 + j]);
+    } else if (M.kind == BK_DENSE) {
+      solve_lower(ld, dense(m));
+    } else {
+      solve_lower(ld, lr_u(m));
+    }
+  }
+  // Mirror of Algorithm 3: X U = M (X overwrites M)
+  void htrsu(int ud, int m) {
+    const BlockNode& M = t_.bl[m];
+    const BlockNode& U = t_.bl[ud];
+    if (M.kind == BK_STRUCT) {
+      for (int j = 0; j < 2; ++j) htrsu(U.son[0], M.son[2 * j]);
+      for (int j = 0; j < 2; ++j) hmul(-1.0, M.son[2 * j], U.son[1], M.son[2 * j + 1]);
+      for (int j = 0; j < 2; ++j) htrsu(U.son[3], M.son[2 * j + 1]);
+    } else if (M.kind == BK_DENSE) {
+      solve_upper_t(ud, transpose(dense(m)));
+    } else {
+      solve_upper_t(ud, lr_v(m));
+    }
+  }
+  // Algorithm 2
+  void hlu(int a) {
+    const BlockNode& A = t_.bl[a];
+    if (A.kind == BK_STRUCT) {
+      hlu(A.son[0]);
+      htrsu(A.son[0], A.son[2]);
+      htrsl(A.son[0], A.son[1]);
+      hmul(-1.0, A.son[2], A.son[1], A.son[3]);
+      hlu(A.son[3]);
+    } else {
+      getrf(a);
+    }
+  }
+
+  void fail(const std::string& m) {
+    if (err_.empty()) err_ = m;
+  }
+
+ private:
+  struct Pool {
+    int64_t limit = 0;
+    int64_t next = 0;
+    std::vector<int64_t> off;
+    std::vector<int> obj;
+  };
+  int new_obj() {
+    objs_.emplace_back();
+    return (int)objs_.size() - 1;
+  }
+  void access(int task, int obj, const Rect& r, bool write) {
+    ObjState& o = objs_[obj];
+    for (auto& w : o.writes)
+      if (w.task != task && overlap(w.r, r)) preds_.push_back(w.task);
+    if (write) {
+      for (auto& rd : o.reads)
+        if (rd.task != task && overlap(rd.r, r)) preds_.push_back(rd.task);
+      o.writes.erase(std::remove_if(o.writes.begin(), o.writes.end(), [&](const Rec& x) { return covers(r, x.r); }),
+                     o.writes.end());
+      o.reads.erase(std::remove_if(o.reads.begin(), o.reads.end(), [&](const Rec& x) { return covers(r, x.r); }),
+                    o.reads.end());
+      o.writes.push_back({r, task});
+    } else {
+      o.reads.push_back({r, task});
+    }
+  }
+
+  Plan& p_;
+  const Tree& t_;
+  Dag& d_;
+  int tsize_;
+  int temp_type_;
+  int64_t temp_budget_;
+  int64_t temp_base_, temp_top_;
+  int panel_obj_ = -1;
+  std::vector<int> obj_a_, obj_b_;
+  std::vector<ObjState> objs_;
+  std::vector<Pool> pools_;
+  std::vector<int> preds_;
+  std::vector<std::pair<int, int>> edges_;
+  std::string err_;
+};
+
+}  // namespace
+
+bool trace_lu(Plan& p, int64_t temp_budget_bytes) {
+  p.lu = Dag();
+  Tracer tr(p, p.lu, temp_budget_bytes);
+  tr.hlu(0);
+  if (!tr.ok()) {
+    p.err = tr.err();
+    return false;
+  }
+  tr.finish();
+  int64_t end = tr.temp_end();
+  if (p.prec == 1) {
+    p.temp_bytes = (end - p.blocks_f32) * 4;
+    p.n_f32 = end;
+  } else {
+    p.temp_bytes = (end - p.n_f64) * 8;
+    p.n_f64 = end;
+  }
+  return true;
+}
+
+bool trace_solve(Plan& p) {
+  p.solve = Dag();
+  Tracer tr(p, p.solve, 0);
+  HView x = tr.panel();
+  tr.solve_lower(0, x);
+  tr.solve_upper(0, x);
+  if (!tr.ok()) {
+    p.err = tr.err();
+    return false;
+  }
+  tr.finish();
+  return true;
+}
+
+}  // namespace hm

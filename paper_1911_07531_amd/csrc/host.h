@@ -1,0 +1,85 @@
+// Host-side structures: cluster tree, block tree, storage plan and task DAGs.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+enum BlockKind : int32_t { BK_STRUCT = 0, BK_DENSE = 1, BK_LOWRANK = 2 };
+
+struct Cluster {
+  int64_t begin, end;
+  double lo[3], hi[3];
+  int32_t son[2];
+  int32_t level;
+  int64_t size() const { return end - begin; }
+  bool leaf() const { return son[0] < 0; }
+};
+
+struct BlockNode {
+  int32_t tau, sigma;
+  int32_t kind;
+  int32_t son[4];  // (0,0),(0,1),(1,0),(1,1)
+};
+
+struct Tree {
+  int64_t n = 0;
+  int dim = 3;
+  int leaf = 0;
+  double eta = 0;
+  std::vector<int64_t> perm;      // perm[k] = original index of permuted index k
+  std::vector<double> pts_perm;   // n x 3 (z = 0 for dim 2), permuted order
+  std::vector<Cluster> cl;        // depth-first pre-order
+  std::vector<BlockNode> bl;      // depth-first pre-order
+};
+
+void build_cluster_tree(const double* pts, int64_t n, int dim, int leaf, Tree& t);
+void build_block_tree(Tree& t, double eta);
+
+// Storage of every leaf block inside the arenas, and the traced task DAGs.
+struct Dag {
+  std::vector<Task> tasks;
+  std::vector<int32_t> indeg;
+  std::vector<int32_t> succ_ptr, succ_idx;
+  std::vector<int32_t> level;       // longest-path level of each task
+  std::vector<int32_t> level_order; // tasks sorted by level
+  std::vector<int32_t> level_ptr;   // start of each level in level_order
+  std::vector<int32_t> roots;
+  int64_t nedges = 0;
+};
+
+struct Plan {
+  const Tree* tree = nullptr;
+  int prec = 0;            // 0 = FP64, 1 = mixed (FP32 off-diagonal storage)
+  int max_rank = 0;
+  int cap = 0;             // stored rank capacity of low-rank leaves
+  int nrhs_cap = 64;       // widest solve panel
+  // per block (index = block id); -1 where not a leaf
+  std::vector<int64_t> data_off;   // dense leaves
+  std::vector<int32_t> data_type;
+  std::vector<int32_t> lr_index;   // low-rank leaves
+  std::vector<int64_t> piv_off;    // diagonal dense leaves
+  std::vector<LrDesc> lr;
+  std::vector<int32_t> lr_block;
+  std::vector<int32_t> diag_leaves;  // diagonal dense leaves in order
+  int64_t n_f64 = 0, n_f32 = 0, n_piv = 0;
+  int64_t blocks_f64 = 0, blocks_f32 = 0;  // arena prefix that holds block data
+  int64_t panel_off = -1;  // solve panel (f64 arena), n x nrhs_cap
+  int nranks = 0;          // rank slots (low-rank leaves + nrhs slot)
+  int nrhs_slot = 0;
+  Dag lu, solve;
+  int64_t temp_bytes = 0;
+  std::string err;
+};
+
+// Storage layout for a tree.  prec = 0: every block FP64; prec = 1: diagonal
+// leaves FP64, all other blocks FP32.
+bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
+// Trace the H-LU (Algorithm 2) and the forward/backward solve into task DAGs.
+bool trace_lu(Plan& p, int64_t temp_budget_bytes);
+bool trace_solve(Plan& p);
+
+}  // namespace hm

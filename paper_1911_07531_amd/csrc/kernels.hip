@@ -1,0 +1,1205 @@
+// Device kernels of the H-LU library (gfx950).
+//
+// Every task of the traced DAG runs in one 256-thread workgroup:
+//   GETRF    dense LU of a diagonal leaf with leaf-local partial pivoting
+//            (Algorithm 2, non-recursive branch)
+//   TRSM_*   triangular solves of a panel with a diagonal leaf
+//            (Algorithm 3, non-recursive branch, and its mirror)
+//   GEMM     dense products of leaves and panels (Algorithm 1 leaf cases)
+//   LRGEMM   product with a low-rank leaf, y += alpha U (V^T x)
+//   TRUNC    truncated low-rank addition C <- T_eps(C + alpha A B) (Sec. 2.3)
+// plus the executors that replay the DAG (one launch per level, or one
+// persistent dataflow launch), the assembly kernels and the H-matvec.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+// ---------------------------------------------------------------------------
+// views
+// ---------------------------------------------------------------------------
+struct RV {  // a view with its run-time extents resolved
+  int64_t off;
+  int rows, cols, rs, cs, type;
+};
+
+__device__ __forceinline__ RV resolve(const ExecArgs& a, const View& v) {
+  RV r;
+  r.off = v.off;
+  r.rows = (v.dyn & DYN_ROWS) ? a.ranks[v.rank_id] : v.rows;
+  r.cols = (v.dyn & DYN_COLS) ? a.ranks[v.rank_id] : v.cols;
+  r.rs = v.rs;
+  r.cs = v.cs;
+  r.type = v.type;
+  return r;
+}
+
+__device__ __forceinline__ double vld(const ExecArgs& a, const RV& v, int i, int j) {
+  if (v.type == VT_F64) return a.f64[v.off + (int64_t)i * v.rs + (int64_t)j * v.cs];
+  if (v.type == VT_F32) return (double)a.f32[v.off + (int64_t)i * v.rs + (int64_t)j * v.cs];
+  if (v.type == VT_IDENT) return i == j ? 1.0 : 0.0;
+  return 0.0;
+}
+
+__device__ __forceinline__ void vst(const ExecArgs& a, const RV& v, int i, int j, double x) {
+  if (v.type == VT_F64)
+    a.f64[v.off + (int64_t)i * v.rs + (int64_t)j * v.cs] = x;
+  else if (v.type == VT_F32)
+    a.f32[v.off + (int64_t)i * v.rs + (int64_t)j * v.cs] = (float)x;
+}
+
+__device__ __forceinline__ int64_t vbytes(const RV& v) {
+  if (v.type == VT_F64) return (int64_t)v.rows * v.cols * 8;
+  if (v.type == VT_F32) return (int64_t)v.rows * v.cols * 4;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// tiled GEMM core: C(m x n) = sum_k A(i, k) B(k, j), 64x64 output tiles,
+// 16-deep k slices staged in LDS, 4x4 outputs per thread.
+// a_kcontig / b_kcontig choose which tile index consecutive threads walk so
+// that global loads are coalesced for the operand's storage order.
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 16, TP = 4;
+
+template <typename CT, class LA, class LB, class ST>
+__device__ void gemm_tiles(int m, int n, int k, LA la, LB lb, ST st, bool a_kcontig, bool b_kcontig, CT* sA,
+                           CT* sB) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  for (int i0 = 0; i0 < m; i0 += TM)
+    for (int j0 = 0; j0 < n; j0 += TN) {
+      CT acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = CT(0);
+      for (int k0 = 0; k0 < k; k0 += TK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int l = tid + 256 * q;
+          int ii, kk;
+          if (a_kcontig) {
+            kk = l & 15;
+            ii = l >> 4;
+          } else {
+            ii = l & 63;
+            kk = l >> 6;
+          }
+          int gi = i0 + ii, gk = k0 + kk;
+          sA[kk * (TM + TP) + ii] = (gi < m && gk < k) ? (CT)la(gi, gk) : CT(0);
+          int jj;
+          if (b_kcontig) {
+            kk = l & 15;
+            jj = l >> 4;
+          } else {
+            jj = l & 63;
+            kk = l >> 6;
+          }
+          int gj = j0 + jj;
+          gk = k0 + kk;
+          sB[kk * (TN + TP) + jj] = (gj < n && gk < k) ? (CT)lb(gk, gj) : CT(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+          CT av[4], bv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) av[r] = sA[kk * (TM + TP) + tx * 4 + r];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bv[c] = sB[kk * (TN + TP) + ty * 4 + c];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += av[r] * bv[c];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          int gi = i0 + tx * 4 + r, gj = j0 + ty * 4 + c;
+          if (gi < m && gj < n) st(gi, gj, (double)acc[r][c]);
+        }
+      __syncthreads();
+    }
+}
+
+constexpr int kTileBytes = 2 * TK * (TM + TP) * 8;  // both tiles in double
+
+// ---------------------------------------------------------------------------
+// simple element-wise ops
+// ---------------------------------------------------------------------------
+__device__ void op_zero(const ExecArgs& a, const Task& t) {
+  RV y = resolve(a, t.y);
+  int total = y.rows * y.cols;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) vst(a, y, e % y.rows, e / y.rows, 0.0);
+}
+
+__device__ void op_copy(const ExecArgs& a, const Task& t) {
+  RV y = resolve(a, t.y), x = resolve(a, t.a);
+  int total = y.rows * y.cols;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int i = e % y.rows, j = e / y.rows;
+    vst(a, y, i, j, vld(a, x, i, j));
+  }
+}
+
+// y <- beta y + alpha a b
+template <typename CT>
+__device__ void op_gemm_ct(const ExecArgs& a, const Task& t, char* lds) {
+  RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+  int m = y.rows, n = y.cols, k = A.cols;
+  if (m == 0 || n == 0) return;
+  const double alpha = t.alpha, beta = t.beta;
+  if (k == 0) {
+    for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+      int i = e % m, j = e / m;
+      vst(a, y, i, j, beta == 0.0 ? 0.0 : beta * vld(a, y, i, j));
+    }
+    return;
+  }
+  CT* sA = (CT*)lds;
+  CT* sB = sA + TK * (TM + TP);
+  gemm_tiles<CT>(
+      m, n, k, [&](int i, int kk) { return vld(a, A, i, kk); }, [&](int kk, int j) { return vld(a, B, kk, j); },
+      [&](int i, int j, double v) {
+        double o = beta == 0.0 ? 0.0 : beta * vld(a, y, i, j);
+        vst(a, y, i, j, o + alpha * v);
+      },
+      A.rs != 1, B.rs == 1, sA, sB);
+}
+
+// y <- beta y + alpha a (b x); a: m x k, b: k x n2, x: n2 x c, k <= 64
+template <typename CT>
+__device__ void op_lrgemm_ct(const ExecArgs& a, const Task& t, char* lds) {
+  RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b), X = resolve(a, t.x);
+  int m = y.rows, c = y.cols, k = A.cols, n2 = B.cols;
+  if (m == 0 || c == 0) return;
+  const double alpha = t.alpha, beta = t.beta;
+  if (k == 0 || n2 == 0) {
+    for (int e = threadIdx.x; e < m * c; e += blockDim.x) {
+      int i = e % m, j = e / m;
+      vst(a, y, i, j, beta == 0.0 ? 0.0 : beta * vld(a, y, i, j));
+    }
+    return;
+  }
+  CT* sA = (CT*)lds;
+  CT* sB = sA + TK * (TM + TP);
+  CT* sT = (CT*)(lds + kTileBytes);  // k x 64 chunk of T = b x
+  for (int j0 = 0; j0 < c; j0 += 64) {
+    int cc = min(64, c - j0);
+    gemm_tiles<CT>(
+        k, cc, n2, [&](int i, int kk) { return vld(a, B, i, kk); },
+        [&](int kk, int j) { return vld(a, X, kk, j0 + j); }, [&](int i, int j, double v) { sT[j * 64 + i] = (CT)v; },
+        B.rs != 1, X.rs == 1, sA, sB);
+    __syncthreads();
+    gemm_tiles<CT>(
+        m, cc, k, [&](int i, int kk) { return vld(a, A, i, kk); },
+        [&](int kk, int j) { return (double)sT[j * 64 + kk]; },
+        [&](int i, int j, double v) {
+          double o = beta == 0.0 ? 0.0 : beta * vld(a, y, i, j0 + j);
+          vst(a, y, i, j0 + j, o + alpha * v);
+        },
+        A.rs != 1, true, sA, sB);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool all_f32(const View& v) { return v.type != VT_F64; }
+
+// ---------------------------------------------------------------------------
+// GETRF: dense LU with partial pivoting (LAPACK getrf convention: first
+// maximum |a| wins, full-row interchanges, unit lower L)
+// ---------------------------------------------------------------------------
+__device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
+#pragma clang fp contract(off)
+  const int m = t.a.rows;
+  double* g = a.f64 + t.a.off;
+  const bool in_lds = (int64_t)m * (m + 1) * 8 + 64 <= kLdsBytes;
+  const int ld = in_lds ? m + 1 : m;
+  double* A = in_lds ? (double*)lds : g;
+  int* s_piv = (int*)(lds + kLdsBytes - 16);
+  const int tid = threadIdx.x;
+  if (in_lds)
+    for (int e = tid; e < m * m; e += blockDim.x) A[(e / m) * ld + (e % m)] = g[e];
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = m;
+      for (int i = j + tid; i < m; i += 64) {
+        double v = fabs(A[j * ld + i]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off);
+        int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv[0] = bi;
+        a.piv[t.piv + j] = bi;
+      }
+    }
+    __syncthreads();
+    const int p = s_piv[0];
+    if (p != j)
+      for (int c = tid; c < m; c += blockDim.x) {
+        double x = A[c * ld + j];
+        A[c * ld + j] = A[c * ld + p];
+        A[c * ld + p] = x;
+      }
+    __syncthreads();
+    const double pv = A[j * ld + j];
+    if (pv == 0.0) {
+      if (tid == 0) {
+        atomicOr(&a.status[0], ST_SINGULAR);
+        atomicMin(&a.status[1], t.row0 + j);
+      }
+    } else {
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) A[j * ld + i] = A[j * ld + i] / pv;
+    }
+    __syncthreads();
+    const int rem = m - j - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      int i = j + 1 + e % rem, c = j + 1 + e / rem;
+      double prod = A[j * ld + i] * A[c * ld + j];
+      A[c * ld + i] = A[c * ld + i] - prod;
+    }
+    __syncthreads();
+  }
+  if (in_lds)
+    for (int e = tid; e < m * m; e += blockDim.x) g[e] = A[(e / m) * ld + (e % m)];
+}
+
+// ---------------------------------------------------------------------------
+// triangular panel solves with a factored diagonal leaf (f64, m x m packed LU)
+// kind 0: x <- L^{-1} P x (unit lower, interchanges first)
+// kind 1: x <- U^{-T} x
+// kind 2: x <- U^{-1} x
+// ---------------------------------------------------------------------------
+__device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
+  const int m = t.a.rows;
+  RV X = resolve(a, t.x);
+  const int c = X.cols;
+  if (m == 0 || c == 0) return;
+  const double* g = a.f64 + t.a.off;
+  const int CC = 64;
+  const bool tri_lds = (int64_t)m * m * 8 + (int64_t)m * CC * 8 <= kLdsBytes;
+  double* sX = (double*)lds;
+  double* sL = sX + m * CC;
+  const double* T = tri_lds ? sL : g;
+  const int tid = threadIdx.x;
+  if (tri_lds)
+    for (int e = tid; e < m * m; e += blockDim.x) sL[e] = g[e];
+  const int32_t* piv = a.piv + t.piv;
+  for (int j0 = 0; j0 < c; j0 += CC) {
+    int cc = min(CC, c - j0);
+    for (int e = tid; e < m * cc; e += blockDim.x) {
+      int i = X.rs == 1 ? e % m : e / cc;
+      int j = X.rs == 1 ? e / m : e % cc;
+      sX[i * CC + j] = vld(a, X, i, j0 + j);
+    }
+    __syncthreads();
+    if (tid < cc) {
+      const int j = tid;
+      if (kind == 0) {
+        for (int r = 0; r < m; ++r) {
+          int p = piv[r];
+          if (p != r) {
+            double x = sX[r * CC + j];
+            sX[r * CC + j] = sX[p * CC + j];
+            sX[p * CC + j] = x;
+          }
+        }
+        for (int i = 1; i < m; ++i) {
+          double s = sX[i * CC + j];
+          for (int q = 0; q < i; ++q) s -= T[q * m + i] * sX[q * CC + j];
+          sX[i * CC + j] = s;
+        }
+      } else if (kind == 1) {
+        for (int i = 0; i < m; ++i) {
+          double s = sX[i * CC + j];
+          for (int q = 0; q < i; ++q) s -= T[i * m + q] * sX[q * CC + j];
+          sX[i * CC + j] = s / T[i * m + i];
+        }
+      } else {
+        for (int i = m - 1; i >= 0; --i) {
+          double s = sX[i * CC + j];
+          for (int q = i + 1; q < m; ++q) s -= T[q * m + i] * sX[q * CC + j];
+          sX[i * CC + j] = s / T[i * m + i];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < m * cc; e += blockDim.x) {
+      int i = X.rs == 1 ? e % m : e / cc;
+      int j = X.rs == 1 ? e / m : e % cc;
+      vst(a, X, i, j0 + j, sX[i * CC + j]);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// TRUNC: C <- T_eps(U_C V_C^T + alpha pad(A) pad(B)^T)  (Sec. 2.3)
+//
+// The stacked factors U_s = [U_C, alpha A], V_s = [V_C, B] (m x K, n x K) are
+// never formed.  Each side's R factor comes from the Gram matrix (CholeskyQR
+// with column scaling and diagonal pivoting; accumulated in FP64 whatever the
+// storage type), the K x K core R_U R_V^T is diagonalised by one-sided Jacobi
+// in FP64, and the kept singular triplets are written back as
+//   U <- U_s T_U,  V <- V_s T_V   (Sigma folded into U).
+// ---------------------------------------------------------------------------
+struct Stack {  // one side of the stack: rows [0, m), columns [0, kc) from C and
+  RV c;         // columns [kc, kc+kp) from the term (rows offset by r0, zero outside)
+  RV t;
+  const double* tptr;  // term factor outside the arenas (column-major, ld t.cs), or null
+  int m, kc, kp, r0;
+  double alpha;
+  __device__ __forceinline__ double operator()(const ExecArgs& a, int r, int i) const {
+    if (i < kc) return vld(a, c, r, i);
+    int rr = r - r0;
+    if (rr < 0 || rr >= t.rows) return 0.0;
+    if (tptr) return alpha * tptr[rr + (int64_t)(i - kc) * t.cs];
+    return alpha * vld(a, t, rr, i - kc);
+  }
+};
+
+// scaled, diagonally pivoted Cholesky of the K x K Gram matrix G (row-major, full);
+// on exit rows [0, r) of G hold R' (upper trapezoidal, pivoted order), perm[q] =
+// original column at pivot position q, dsc[l] = 1/||column l|| (0 for a zero column).
+__device__ int pivoted_cholesky(double* G, int K, int* perm, double* dsc, int* s_int) {
+  const int tid = threadIdx.x;
+  for (int l = tid; l < K; l += blockDim.x) {
+    double d = G[l * K + l];
+    dsc[l] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    perm[l] = l;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += blockDim.x) G[e] *= dsc[e / K] * dsc[e % K];
+  __syncthreads();
+  const double tol = 8.0 * K * 2.220446049250313e-16;
+  int r = K;
+  for (int s = 0; s < K; ++s) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = K;
+      for (int i = s + tid; i < K; i += 64) {
+        double v = G[i * K + i];
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off);
+        int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_int[0] = bi;
+        s_int[1] = best > tol ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int go = s_int[1];
+    const int p = s_int[0];
+    __syncthreads();
+    if (!go) {
+      r = s;
+      break;
+    }
+    if (p != s) {
+      for (int l = tid; l < K; l += blockDim.x) {  // swap rows s, p
+        double x = G[s * K + l];
+        G[s * K + l] = G[p * K + l];
+        G[p * K + l] = x;
+      }
+      __syncthreads();
+      for (int l = tid; l < K; l += blockDim.x) {  // swap columns s, p
+        double x = G[l * K + s];
+        G[l * K + s] = G[l * K + p];
+        G[l * K + p] = x;
+      }
+      if (tid == 0) {
+        int x = perm[s];
+        perm[s] = perm[p];
+        perm[p] = x;
+      }
+      __syncthreads();
+    }
+    const double d = sqrt(G[s * K + s]);
+    __syncthreads();
+    for (int l = s + tid; l < K; l += blockDim.x) G[s * K + l] = (l == s) ? d : G[s * K + l] / d;
+    __syncthreads();
+    const int rem = K - s - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      int i = s + 1 + e / rem, j = s + 1 + e % rem;
+      G[i * K + j] -= G[s * K + i] * G[s * K + j];
+    }
+    __syncthreads();
+  }
+  return r;
+}
+
+// Per-workgroup scratch (doubles) of a truncation with K <= kMaxK, k' <= kMaxCap.
+struct TruncScratch {
+  double *GU, *GV, *B, *Z, *YU, *YV, *TU, *TV, *dU, *dV, *sig;
+  int *pU, *pV, *sel, *posU, *posV;
+};
+
+
+__device__ TruncScratch trunc_scratch(double* p) {
+  TruncScratch s;
+  s.GU = p;
+  p += kMaxK * kMaxK;
+  s.GV = p;
+  p += kMaxK * kMaxK;
+  s.B = p;
+  p += kMaxK * kMaxK;
+  s.Z = p;
+  p += kMaxK * kMaxK;
+  s.YU = p;
+  p += kMaxK * kMaxCap;
+  s.YV = p;
+  p += kMaxK * kMaxCap;
+  s.TU = p;
+  p += kMaxK * kMaxCap;
+  s.TV = p;
+  p += kMaxK * kMaxCap;
+  s.dU = p;
+  p += kMaxK;
+  s.dV = p;
+  p += kMaxK;
+  s.sig = p;
+  p += kMaxK;
+  int* ip = (int*)p;  // 5 * kMaxK ints = 2.5 * kMaxK doubles
+  s.pU = ip;
+  ip += kMaxK;
+  s.pV = ip;
+  ip += kMaxK;
+  s.sel = ip;
+  ip += kMaxK;
+  s.posU = ip;
+  ip += kMaxK;
+  s.posV = ip;
+  return s;
+}
+
+// One-sided Jacobi (Hestenes) on B (p x q, column-major, ld p): orthogonalise the
+// columns; Z (q x q, column-major) accumulates the rotations.  Round-robin
+// pairing, all pairs of a round in parallel.
+__device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
+  __syncthreads();
+  if (q < 2) return;
+  const int N = q + (q & 1);
+  const int npairs = N / 2;
+  int tpp = 1;
+  while (tpp * 2 * npairs <= (int)blockDim.x && tpp < 64) tpp *= 2;
+  const int pair = tid / tpp, lane = tid % tpp;
+  const double tol = 4e-15;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) s_flag[0] = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < N - 1; ++rnd) {
+      int ci = -1, cj = -1;
+      if (pair < npairs) {
+        const int mm = N - 1;
+        if (pair == 0) {
+          ci = mm;
+          cj = rnd;
+        } else {
+          ci = (rnd + pair) % mm;
+          cj = (rnd - pair + mm) % mm;
+        }
+        if (ci >= q || cj >= q) ci = cj = -1;
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (ci >= 0)
+        for (int r = lane; r < p; r += tpp) {
+          double x = B[ci * p + r], y = B[cj * p + r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+      for (int off = tpp / 2; off >= 1; off >>= 1) {
+        al += __shfl_xor(al, off);
+        be += __shfl_xor(be, off);
+        ga += __shfl_xor(ga, off);
+      }
+      if (ci >= 0 && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        if (lane == 0) s_flag[0] = 1;
+        double zeta = (be - al) / (2.0 * ga);
+        double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int r = lane; r < p; r += tpp) {
+          double x = B[ci * p + r], y = B[cj * p + r];
+          B[ci * p + r] = cs * x - sn * y;
+          B[cj * p + r] = sn * x + cs * y;
+        }
+        for (int r = lane; r < q; r += tpp) {
+          double x = Z[ci * q + r], y = Z[cj * q + r];
+          Z[ci * q + r] = cs * x - sn * y;
+          Z[cj * q + r] = sn * x + cs * y;
+        }
+      }
+      __syncthreads();
+    }
+    const int again = s_flag[0];
+    __syncthreads();
+    if (!again) break;
+  }
+}
+
+// Solve the r x r upper triangle of R' (rows of G, stride K) against rhs columns
+// (r x kk, column-major, ld r) in place; one thread per column.
+__device__ void upper_solve(const double* R, int K, int r, double* X, int kk) {
+  for (int j = threadIdx.x; j < kk; j += blockDim.x) {
+    double* x = X + (int64_t)j * r;
+    for (int i = r - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int q = i + 1; q < r; ++q) s -= R[i * K + q] * x[q];
+      x[i] = s / R[i * K + i];
+    }
+  }
+}
+
+// Returns the new rank.
+__device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+                          char* lds, double* scratch) {
+  const int tid = threadIdx.x;
+  const int K = su.kc + su.kp;
+  const int m = su.m, n = sv.m;
+  int* s_int = (int*)(lds + kLdsBytes - 64);
+  if (K == 0) {
+    if (tid == 0) a.ranks[lr_index] = 0;
+    __syncthreads();
+    return 0;
+  }
+  TruncScratch S = trunc_scratch(scratch);
+  double* sA = (double*)lds;
+  double* sB = sA + TK * (TM + TP);
+  // 1. Gram matrices G_U = U_s^T U_s, G_V = V_s^T V_s (FP64)
+  gemm_tiles<double>(
+      K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
+      [&](int i, int j, double v) { S.GU[i * K + j] = v; }, true, true, sA, sB);
+  gemm_tiles<double>(
+      K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
+      [&](int i, int j, double v) { S.GV[i * K + j] = v; }, true, true, sA, sB);
+  __syncthreads();
+  // 2. R factors
+  const int rU = pivoted_cholesky(S.GU, K, S.pU, S.dU, s_int);
+  const int rV = pivoted_cholesky(S.GV, K, S.pV, S.dV, s_int);
+  if (rU == 0 || rV == 0) {
+    if (tid == 0) a.ranks[lr_index] = 0;
+    __syncthreads();
+    return 0;
+  }
+  for (int q = tid; q < K; q += blockDim.x) {
+    S.posU[S.pU[q]] = q;
+    S.posV[S.pV[q]] = q;
+  }
+  __syncthreads();
+  // 3. core B = Rt_U Rt_V^T, Rt[i][l] = R'[i][pos(l)] * ||column l||  (rU x rV, column-major)
+  const bool core_lds = (int64_t)(rU * rV + rV * rV) * 8 <= kLdsBytes - 128;
+  double* B = core_lds ? (double*)lds : S.B;
+  double* Z = core_lds ? (double*)lds + rU * rV : S.Z;
+  for (int e = tid; e < rU * rV; e += blockDim.x) {
+    int i = e % rU, j = e / rU;
+    double s = 0.0;
+    for (int l = 0; l < K; ++l) {
+      int qu = S.posU[l], qv = S.posV[l];
+      if (qu < i || qv < j || S.dU[l] == 0.0 || S.dV[l] == 0.0) continue;
+      s += (S.GU[i * K + qu] / S.dU[l]) * (S.GV[j * K + qv] / S.dV[l]);
+    }
+    B[j * rU + i] = s;
+  }
+  __syncthreads();
+  // 4. SVD of the core: columns of B Z are W_j sigma_j
+  jacobi_svd(B, Z, rU, rV, s_int + 4);
+  for (int j = tid; j < rV; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
+    S.sig[j] = sqrt(s);
+  }
+  if (tid == 0) s_int[2] = 0;
+  __syncthreads();
+  // 5. descending order and truncation rank: keep sigma > eps * sigma_1, then cap
+  double smax = 0.0;
+  for (int j = 0; j < rV; ++j) smax = fmax(smax, S.sig[j]);
+  for (int j = tid; j < rV; j += blockDim.x) {
+    int rk = 0;
+    for (int l = 0; l < rV; ++l)
+      if (S.sig[l] > S.sig[j] || (S.sig[l] == S.sig[j] && l < j)) ++rk;
+    S.sel[rk] = j;
+    if (smax > 0.0 && S.sig[j] > a.eps * smax) atomicAdd(&s_int[2], 1);
+  }
+  __syncthreads();
+  int kk = s_int[2];
+  const int limit = min(d.cap, min(d.m, d.n));
+  if (kk > limit) {
+    if (tid == 0 && a.max_rank == 0) atomicAdd(&a.status[2], 1);
+    kk = limit;
+  }
+  if (kk == 0) {
+    if (tid == 0) a.ranks[lr_index] = 0;
+    __syncthreads();
+    return 0;
+  }
+  // 6. T_U = D_U P_U E_r R'_U^{-1} (B Z)_sel,  T_V = D_V P_V E_r R'_V^{-1} Z_sel
+  for (int e = tid; e < rU * kk; e += blockDim.x) {
+    int i = e % rU, c = e / rU;
+    S.YU[c * rU + i] = B[S.sel[c] * rU + i];
+  }
+  for (int e = tid; e < rV * kk; e += blockDim.x) {
+    int i = e % rV, c = e / rV;
+    S.YV[c * rV + i] = Z[S.sel[c] * rV + i];
+  }
+  __syncthreads();
+  upper_solve(S.GU, K, rU, S.YU, kk);
+  upper_solve(S.GV, K, rV, S.YV, kk);
+  __syncthreads();
+  for (int e = tid; e < K * kk; e += blockDim.x) {
+    int l = e % K, c = e / K;
+    int qu = S.posU[l], qv = S.posV[l];
+    S.TU[c * K + l] = qu < rU ? S.dU[l] * S.YU[c * rU + qu] : 0.0;
+    S.TV[c * K + l] = qv < rV ? S.dV[l] * S.YV[c * rV + qv] : 0.0;
+  }
+  __syncthreads();
+  // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile since
+  //    kk <= 64, so every row tile is read completely before it is overwritten)
+  RV uc{d.u_off, m, kk, 1, m, d.type};
+  RV vc{d.v_off, n, kk, 1, n, d.type};
+  gemm_tiles<double>(
+      m, kk, K, [&](int r, int l) { return su(a, r, l); }, [&](int l, int c) { return S.TU[c * K + l]; },
+      [&](int r, int c, double v) { vst(a, uc, r, c, v); }, false, true, sA, sB);
+  gemm_tiles<double>(
+      n, kk, K, [&](int r, int l) { return sv(a, r, l); }, [&](int l, int c) { return S.TV[c * K + l]; },
+      [&](int r, int c, double v) { vst(a, vc, r, c, v); }, false, true, sA, sB);
+  __syncthreads();
+  if (tid == 0) a.ranks[lr_index] = kk;
+  __syncthreads();
+  return kk;
+}
+
+__device__ void op_trunc(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
+  const LrDesc d = a.lr[t.lr];
+  const int kc = a.ranks[t.lr];
+  RV A = resolve(a, t.a), B = resolve(a, t.b);
+  Stack su, sv;
+  su.c = RV{d.u_off, d.m, kc, 1, d.m, d.type};
+  sv.c = RV{d.v_off, d.n, kc, 1, d.n, d.type};
+  su.t = A;
+  sv.t = B;
+  su.tptr = sv.tptr = nullptr;
+  su.m = d.m;
+  sv.m = d.n;
+  su.kc = sv.kc = kc;
+  su.kp = sv.kp = A.cols;
+  su.r0 = t.r0;
+  sv.r0 = t.c0;
+  su.alpha = t.alpha;
+  sv.alpha = 1.0;
+  __syncthreads();
+  const int kn = trunc_core(a, d, t.lr, su, sv, lds, scratch);
+  if (threadIdx.x == 0 && a.counters) {
+    int64_t s = d.type == VT_F64 ? 8 : 4;
+    int64_t K = kc + A.cols;
+    int64_t bytes = (int64_t)(d.m + d.n) * (kc + kn) * s + vbytes(A) + vbytes(B);
+    int64_t flops = 4 * (int64_t)(d.m + d.n) * K * K + 2 * (int64_t)(d.m + d.n) * K * kn + 20 * K * K * K;
+    atomicAdd(&a.counters[0], (unsigned long long)bytes);
+    atomicAdd(&a.counters[1], (unsigned long long)flops);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// task dispatch
+// ---------------------------------------------------------------------------
+// Algorithmic bytes (every operand read once, every output written once, at
+// run-time extents) and flops of one task; the truncation counts itself.
+__device__ void count_task(const ExecArgs& a, const Task& t) {
+  if (!a.counters || t.op == OP_TRUNC || t.op == OP_NOP) return;
+  int64_t bytes = 0, flops = 0;
+  if (t.op == OP_GETRF) {
+    int64_t m = t.a.rows;
+    bytes = 2 * m * m * 8;
+    flops = 2 * m * m * m / 3;
+  } else if (t.op == OP_TRSM_L || t.op == OP_TRSM_UT || t.op == OP_TRSM_U) {
+    RV x = resolve(a, t.x);
+    int64_t m = t.a.rows;
+    bytes = m * m * 8 + 2 * vbytes(x);
+    flops = m * m * x.cols;
+  } else if (t.op == OP_GEMM) {
+    RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+    bytes = vbytes(A) + vbytes(B) + (t.beta != 0.0 ? 2 : 1) * vbytes(y);
+    flops = 2 * (int64_t)y.rows * y.cols * A.cols;
+  } else if (t.op == OP_LRGEMM) {
+    RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b), X = resolve(a, t.x);
+    bytes = vbytes(A) + vbytes(B) + vbytes(X) + (t.beta != 0.0 ? 2 : 1) * vbytes(y);
+    flops = 2 * (int64_t)A.cols * B.cols * X.cols + 2 * (int64_t)y.rows * A.cols * y.cols;
+  } else if (t.op == OP_ZERO) {
+    bytes = vbytes(resolve(a, t.y));
+  } else if (t.op == OP_COPY) {
+    RV y = resolve(a, t.y);
+    bytes = 2 * vbytes(y);
+  }
+  atomicAdd(&a.counters[0], (unsigned long long)bytes);
+  atomicAdd(&a.counters[1], (unsigned long long)flops);
+}
+
+__device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
+  const Task& t = a.tasks[id];
+  if (threadIdx.x == 0) count_task(a, t);
+  switch (t.op) {
+    case OP_GETRF:
+      op_getrf(a, t, lds);
+      break;
+    case OP_TRSM_L:
+      op_trsm(a, t, lds, 0);
+      break;
+    case OP_TRSM_UT:
+      op_trsm(a, t, lds, 1);
+      break;
+    case OP_TRSM_U:
+      op_trsm(a, t, lds, 2);
+      break;
+    case OP_GEMM:
+      if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b))
+        op_gemm_ct<float>(a, t, lds);
+      else
+        op_gemm_ct<double>(a, t, lds);
+      break;
+    case OP_LRGEMM:
+      if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b) && all_f32(t.x))
+        op_lrgemm_ct<float>(a, t, lds);
+      else
+        op_lrgemm_ct<double>(a, t, lds);
+      break;
+    case OP_TRUNC:
+      op_trunc(a, t, lds, scratch);
+      break;
+    case OP_ZERO:
+      op_zero(a, t);
+      break;
+    case OP_COPY:
+      op_copy(a, t);
+      break;
+    default:
+      break;
+  }
+}
+
+// One launch per DAG level: workgroup w runs tasks order[begin + w], order[begin + w + grid], ...
+__global__ void __launch_bounds__(kThreads) exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end) {
+  extern __shared__ __align__(16) char lds[];
+  double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
+  for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
+    run_task(a, order[i], lds, scratch);
+    __syncthreads();
+  }
+}
+
+__global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (int k = i; k < a.ntasks; k += stride) {
+    a.deps[k] = indeg[k];
+    a.queue[k] = k < nroots ? roots[k] : -1;
+  }
+  if (i == 0) {
+    a.qctl[0] = 0;
+    a.qctl[1] = nroots;
+    a.qctl[2] = 0;
+    a.qctl[3] = 0;
+  }
+}
+
+// Persistent dataflow executor: workgroups claim queue slots in order, run the
+// task that lands there, and release successors whose predecessor count drops
+// to zero.  Every slot below ntasks is filled exactly once for an acyclic DAG;
+// a workgroup that waits longer than spin_limit wall-clock ticks raises ST_TIMEOUT and
+// every workgroup then leaves.
+__global__ void __launch_bounds__(kThreads) exec_dataflow_kernel(ExecArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_task;
+  double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      int t = -1;
+      int slot = atomicAdd(&a.qctl[0], 1);
+      if (slot < a.ntasks) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+          t = __hip_atomic_load(&a.queue[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (t >= 0) break;
+          if (__hip_atomic_load(&a.qctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          if ((int64_t)(wall_clock64() - t0) > a.spin_limit) {
+            atomicOr(&a.status[0], ST_TIMEOUT);
+            __hip_atomic_store(&a.qctl[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      s_task = t;
+    }
+    __syncthreads();
+    const int t = s_task;
+    if (t < 0) break;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    run_task(a, t, lds, scratch);
+    __threadfence();
+    __syncthreads();
+    if (tid < 64) {
+      const int b = a.succ_ptr[t], e = a.succ_ptr[t + 1];
+      for (int k = b + tid; k < e; k += 64) {
+        const int s = a.succ_idx[k];
+        int prev = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 1) {
+          int pos = atomicAdd(&a.qctl[1], 1);
+          __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// assembly: kernel entries and adaptive cross approximation
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double kernel_entry(const AsmArgs& s, int64_t i, int64_t j) {
+  if (i == j) return s.diag;
+  double dx = s.pts[3 * i] - s.pts[3 * j];
+  double dy = s.pts[3 * i + 1] - s.pts[3 * j + 1];
+  double dz = s.pts[3 * i + 2] - s.pts[3 * j + 2];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  if (s.kernel == 0) return 1.0 / (4.0 * 3.14159265358979323846 * r);
+  return -log(r) / (2.0 * 3.14159265358979323846);
+}
+
+
+__global__ void __launch_bounds__(kThreads) assemble_dense_kernel(ExecArgs a, AsmArgs s, const DenseAsm* blocks) {
+  const DenseAsm b = blocks[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)b.m * b.n; e += blockDim.x) {
+    int64_t i = e % b.m, j = e / b.m;
+    double v = kernel_entry(s, b.r0 + i, b.c0 + j);
+    if (b.type == VT_F64)
+      a.f64[b.off + e] = v;
+    else
+      a.f32[b.off + e] = (float)v;
+  }
+}
+
+
+// ACA with partial pivoting into scratch factors (capacity kMaxK), then
+// recompression through the truncation core with an empty C.
+__global__ void __launch_bounds__(kThreads) assemble_aca_kernel(ExecArgs a, AsmArgs s, const LrAsm* blocks,
+                                                               double* fac, int64_t fac_stride, double aca_eps) {
+  extern __shared__ __align__(16) char lds[];
+  const LrAsm blk = blocks[blockIdx.x];
+  const LrDesc d = a.lr[blk.lr];
+  const int m = d.m, n = d.n, tid = threadIdx.x;
+  double* U = fac + (int64_t)blockIdx.x * fac_stride;  // m x kMaxK
+  double* V = U + (int64_t)m * kMaxK;                  // n x kMaxK
+  char* used = (char*)(V + (int64_t)n * kMaxK);        // m flags
+  double* red = (double*)(lds + kLdsBytes - 4096);     // reduction scratch
+  int* ired = (int*)(lds + kLdsBytes - 2048);
+  for (int i = tid; i < m; i += blockDim.x) used[i] = 0;
+  const int kmax = min(kMaxK, min(m, n));
+  double norm2 = 0.0;  // ||S_k||_F^2
+  int k = 0, istar = 0, zero_rows = 0;
+  __syncthreads();
+  while (k < kmax) {
+    // row istar of the residual -> V[:, k]
+    for (int j = tid; j < n; j += blockDim.x) {
+      double v = kernel_entry(s, blk.r0 + istar, blk.c0 + j);
+      for (int l = 0; l < k; ++l) v -= U[(int64_t)l * m + istar] * V[(int64_t)l * n + j];
+      V[(int64_t)k * n + j] = v;
+    }
+    if (tid == 0) used[istar] = 1;
+    __syncthreads();
+    // pivot column: argmax |v_j|
+    double best = -1.0;
+    int bj = n;
+    for (int j = tid; j < n; j += blockDim.x) {
+      double x = fabs(V[(int64_t)k * n + j]);
+      if (x > best) {
+        best = x;
+        bj = j;
+      }
+    }
+    red[tid] = best;
+    ired[tid] = bj;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+      if (tid < off) {
+        double ob = red[tid + off];
+        int oi = ired[tid + off];
+        if (ob > red[tid] || (ob == red[tid] && oi < ired[tid])) {
+          red[tid] = ob;
+          ired[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int jstar = ired[0];
+    const double piv = V[(int64_t)k * n + jstar];
+    __syncthreads();
+    if (piv == 0.0) {
+      // zero residual row: try another unused row
+      ++zero_rows;
+      int next = -1;
+      if (tid == 0) {
+        for (int i = 0; i < m; ++i)
+          if (!used[i]) {
+            next = i;
+            break;
+          }
+        ired[0] = next;
+      }
+      __syncthreads();
+      next = ired[0];
+      __syncthreads();
+      if (next < 0 || zero_rows > 8) break;
+      istar = next;
+      continue;
+    }
+    for (int j = tid; j < n; j += blockDim.x) V[(int64_t)k * n + j] /= piv;
+    __syncthreads();
+    // column jstar of the residual -> U[:, k]
+    for (int i = tid; i < m; i += blockDim.x) {
+      double v = kernel_entry(s, blk.r0 + i, blk.c0 + jstar);
+      for (int l = 0; l < k; ++l) v -= V[(int64_t)l * n + jstar] * U[(int64_t)l * m + i];
+      U[(int64_t)k * m + i] = v;
+    }
+    __syncthreads();
+    // norms: ||u||^2 ||v||^2 and cross terms with earlier columns
+    double nu = 0, nv = 0;
+    for (int i = tid; i < m; i += blockDim.x) nu += U[(int64_t)k * m + i] * U[(int64_t)k * m + i];
+    for (int j = tid; j < n; j += blockDim.x) nv += V[(int64_t)k * n + j] * V[(int64_t)k * n + j];
+    red[tid] = nu;
+    red[blockDim.x + tid] = nv;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+      if (tid < off) {
+        red[tid] += red[tid + off];
+        red[blockDim.x + tid] += red[blockDim.x + tid + off];
+      }
+      __syncthreads();
+    }
+    nu = red[0];
+    nv = red[blockDim.x];
+    __syncthreads();
+    double cross = 0.0;
+    for (int l = 0; l < k; ++l) {
+      double cu = 0, cv = 0;
+      for (int i = tid; i < m; i += blockDim.x) cu += U[(int64_t)l * m + i] * U[(int64_t)k * m + i];
+      for (int j = tid; j < n; j += blockDim.x) cv += V[(int64_t)l * n + j] * V[(int64_t)k * n + j];
+      red[tid] = cu;
+      red[blockDim.x + tid] = cv;
+      __syncthreads();
+      for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+        if (tid < off) {
+          red[tid] += red[tid + off];
+          red[blockDim.x + tid] += red[blockDim.x + tid + off];
+        }
+        __syncthreads();
+      }
+      cross += red[0] * red[blockDim.x];
+      __syncthreads();
+    }
+    norm2 += nu * nv + 2.0 * cross;
+    ++k;
+    // next row: argmax |u_i| over unused rows
+    best = -1.0;
+    int bi = m;
+    for (int i = tid; i < m; i += blockDim.x) {
+      double x = used[i] ? -1.0 : fabs(U[(int64_t)(k - 1) * m + i]);
+      if (x > best) {
+        best = x;
+        bi = i;
+      }
+    }
+    red[tid] = best;
+    ired[tid] = bi;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+      if (tid < off) {
+        double ob = red[tid + off];
+        int oi = ired[tid + off];
+        if (ob > red[tid] || (ob == red[tid] && oi < ired[tid])) {
+          red[tid] = ob;
+          ired[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int nexti = ired[0];
+    const double nb = red[0];
+    __syncthreads();
+    if (sqrt(nu * nv) <= aca_eps * sqrt(fmax(norm2, 0.0))) break;
+    if (nexti >= m || nb < 0.0) break;
+    istar = nexti;
+  }
+  __syncthreads();
+  // recompress: C (empty) + U V^T through the truncation core
+  if (tid == 0) a.ranks[blk.lr] = 0;
+  __syncthreads();
+  Stack su, sv;
+  su.c = RV{d.u_off, m, 0, 1, m, d.type};
+  sv.c = RV{d.v_off, n, 0, 1, n, d.type};
+  su.t = RV{0, m, k, 1, m, VT_F64};
+  sv.t = RV{0, n, k, 1, n, VT_F64};
+  su.tptr = U;
+  sv.tptr = V;
+  su.m = m;
+  sv.m = n;
+  su.kc = sv.kc = 0;
+  su.kp = sv.kp = k;
+  su.r0 = sv.r0 = 0;
+  su.alpha = sv.alpha = 1.0;
+  trunc_core(a, d, blk.lr, su, sv, lds, a.scratch + (int64_t)blockIdx.x * a.scratch_stride);
+}
+
+// ---------------------------------------------------------------------------
+// H-matvec: y = alpha A x + beta y, permuted ordering, nrhs <= 16 per launch
+// ---------------------------------------------------------------------------
+
+// phase 1: T_b = V_b^T x_sigma for every low-rank leaf (k x nrhs, ld kMaxCap)
+__global__ void __launch_bounds__(kThreads) matvec_phase1_kernel(ExecArgs a, const MvLeaf* leaves,
+                                                                 const int32_t* lr_leaves, const double* x,
+                                                                 int64_t ldx, int nrhs, double* T) {
+  const MvLeaf L = leaves[lr_leaves[blockIdx.x]];
+  const int k = a.ranks[L.lr];
+  double* out = T + (int64_t)L.lr * kMaxCap * 16;
+  const int tid = threadIdx.x;
+  // each (l, r) output: sum over n rows
+  for (int e = tid / 4; e < k * nrhs; e += blockDim.x / 4) {
+    int l = e % k, r = e / k;
+    double s = 0.0;
+    for (int j = tid % 4; j < L.n; j += 4) {
+      double v = L.type == VT_F64 ? a.f64[L.v_off + (int64_t)l * L.n + j] : (double)a.f32[L.v_off + (int64_t)l * L.n + j];
+      s += v * x[(L.c0 + j) + (int64_t)r * ldx];
+    }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if (tid % 4 == 0) out[l + (int64_t)r * kMaxCap] = s;
+  }
+}
+
+// phase 2: one workgroup per leaf row cluster; y_tau = sum over covering leaves
+__global__ void __launch_bounds__(kThreads) matvec_phase2_kernel(ExecArgs a, const MvLeaf* leaves,
+                                                                 const int32_t* row_ptr, const MvRow* segs,
+                                                                 const int64_t* row_begin, const int32_t* row_size,
+                                                                 const double* x, int64_t ldx, int nrhs,
+                                                                 const double* T, double* y, int64_t ldy,
+                                                                 double alpha, double beta) {
+  const int rc = blockIdx.x;
+  const int64_t rb = row_begin[rc];
+  const int mr = row_size[rc];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < mr * nrhs; e += blockDim.x) {
+    int i = e % mr, r = e / mr;
+    double s = 0.0;
+    for (int q = row_ptr[rc]; q < row_ptr[rc + 1]; ++q) {
+      const MvRow sg = segs[q];
+      const MvLeaf L = leaves[sg.leaf];
+      const int li = sg.lrow + i;
+      if (L.lr < 0) {
+        for (int j = 0; j < L.n; ++j) {
+          double v = L.type == VT_F64 ? a.f64[L.off + li + (int64_t)j * L.m] : (double)a.f32[L.off + li + (int64_t)j * L.m];
+          s += v * x[(L.c0 + j) + (int64_t)r * ldx];
+        }
+      } else {
+        const int k = a.ranks[L.lr];
+        const double* t = T + (int64_t)L.lr * kMaxCap * 16 + (int64_t)r * kMaxCap;
+        for (int l = 0; l < k; ++l) {
+          double u = L.type == VT_F64 ? a.f64[L.u_off + li + (int64_t)l * L.m] : (double)a.f32[L.u_off + li + (int64_t)l * L.m];
+          s += u * t[l];
+        }
+      }
+    }
+    double* yp = y + (rb + i) + (int64_t)r * ldy;
+    *yp = (beta == 0.0 ? 0.0 : beta * *yp) + alpha * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vector helpers for the solve and refinement (all FP64)
+// ---------------------------------------------------------------------------
+// dst[k + r*ldd] = src[perm[k] + r*lds]   (gather into permuted order)
+__global__ void gather_rows_kernel(const double* src, int64_t lds_, const int64_t* perm, int64_t n, int nrhs,
+                                   double* dst, int64_t ldd) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t k = i % n, r = i / n;
+  dst[k + r * ldd] = src[perm[k] + r * lds_];
+}
+// dst[perm[k] + r*ldd] = alpha*src[k + r*lds] + beta*dst[...]
+__global__ void scatter_rows_kernel(const double* src, int64_t lds_, const int64_t* perm, int64_t n, int nrhs,
+                                    double* dst, int64_t ldd, double alpha, double beta) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t k = i % n, r = i / n;
+  double* d = dst + perm[k] + r * ldd;
+  *d = alpha * src[k + r * lds_] + (beta == 0.0 ? 0.0 : beta * *d);
+}
+// out[r] = sum_k v[k + r*ld]^2  (one workgroup per column)
+__global__ void __launch_bounds__(kThreads) colnorm2_kernel(const double* v, int64_t ld, int64_t n, double* out) {
+  __shared__ double red[kThreads];
+  const int r = blockIdx.x;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    double x = v[k + r * ld];
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = red[0];
+}
+// y += x (n x nrhs, separate leading dimensions), columns with active[r] == 0 skipped
+__global__ void axpy_cols_kernel(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
+                                 const int32_t* active) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t k = i % n, r = i / n;
+  if (active && !active[r]) return;
+  y[k + r * ldy] += x[k + r * ldx];
+}
+// copy / convert one leaf-block arena region (A layout -> LU layout)
+__global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs) {
+  const CopyDesc c = descs[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < c.count; e += blockDim.x) {
+    double v = src[c.src + e];
+    if (c.dst_type == VT_F64)
+      d64[c.dst + e] = v;
+    else
+      d32[c.dst + e] = (float)v;
+  }
+}
+
+}  // namespace hm

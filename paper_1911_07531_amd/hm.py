@@ -1,0 +1,299 @@
+"""ctypes binding of libhm.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; this module converts
+arguments, owns handles and raises on error codes.  PyTorch provides device
+tensors and the current stream.  There is no CPU fallback: if the library is
+missing, or no device is usable, the compute calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhm.so")
+
+HM_OK, HM_EINVAL, HM_ENOMEM, HM_ESINGULAR, HM_ENOCONV, HM_EDEVICE, HM_ERANK = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+LAPLACE3D, LOG2D = 0, 1
+DATAFLOW, LEVEL = 0, 1
+
+OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy"]
+
+
+class HmError(RuntimeError):
+    def __init__(self, code: int, msg: str, info: int = 0):
+        super().__init__(f"hm error {code}: {msg}")
+        self.code = code
+        self.info = info
+
+
+class Opts(C.Structure):
+    _fields_ = [("leaf", C.c_int), ("eta", C.c_double), ("eps", C.c_double), ("max_rank", C.c_int),
+                ("prec", C.c_int), ("exec", C.c_int)]
+
+
+class LuStats(C.Structure):
+    _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
+                ("tasks_by_op", C.c_int64 * 10), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
+                ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64)]
+
+
+# numpy view of one traced task record (struct Task in csrc/hm_internal.h)
+VIEW_DTYPE = np.dtype([("off", "<i8"), ("rows", "<i4"), ("cols", "<i4"), ("rs", "<i4"), ("cs", "<i4"),
+                       ("type", "<i4"), ("dyn", "<i4"), ("rank_id", "<i4"), ("pad", "<i4")])
+TASK_DTYPE = np.dtype([("op", "<i4"), ("lr", "<i4"), ("r0", "<i4"), ("c0", "<i4"), ("row0", "<i4"),
+                       ("pad", "<i4"), ("piv", "<i8"), ("alpha", "<f8"), ("beta", "<f8"),
+                       ("y", VIEW_DTYPE), ("a", VIEW_DTYPE), ("b", VIEW_DTYPE), ("x", VIEW_DTYPE)])
+
+_lib = None
+
+
+def exported_symbols():
+    """Names every build of libhm.so must export (the entry points of include/hm.h)."""
+    return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu",
+            "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
+            "hm_dag_export", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
+
+
+def lib():
+    """Load libhm.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1911_07531_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, dbl, ip = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    L.hm_last_error.restype = C.c_char_p
+    sig = {
+        "build_htree": [C.POINTER(C.c_double), i64, ip, C.POINTER(Opts), C.POINTER(vp)],
+        "hm_tree_sizes": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+        "hm_tree_export": [vp, vp, vp, vp, vp],
+        "h_assemble": [vp, ip, dbl, C.POINTER(Opts), vp, C.POINTER(vp)],
+        "h_lu": [vp, C.POINTER(Opts), vp, C.POINTER(vp), C.POINTER(i64)],
+        "h_solve": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
+        "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
+        "hm_footprint": [vp, ip, C.POINTER(C.c_size_t)],
+        "hm_export_leaf": [vp, ip, i64, vp, C.POINTER(C.c_int32), vp],
+        "hm_lu_stats_get": [vp, C.POINTER(LuStats)],
+        "hm_dag_sizes": [vp, C.POINTER(Opts), ip, vp],
+        "hm_dag_export": [vp, C.POINTER(Opts), ip, vp, vp, vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    for name in ("hm_tree_free", "hm_matrix_free", "hm_lu_free"):
+        getattr(L, name).argtypes = [vp]
+        getattr(L, name).restype = None
+    _lib = L
+    return L
+
+
+def _check(code: int, info: int = 0):
+    if code != HM_OK:
+        raise HmError(code, lib().hm_last_error().decode(), info)
+
+
+def make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=FP64, exec_mode=DATAFLOW) -> Opts:
+    return Opts(int(leaf), float(eta), float(eps), int(max_rank), int(prec), int(exec_mode))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("expected a float64 CUDA (HIP) tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _col_major(t):
+    """(n, nrhs) float64 tensor -> (ptr, ld) for column-major access; requires Fortran order."""
+    if t.dim() == 1:
+        return _dev_ptr(t), t.shape[0], 1
+    n, k = t.shape
+    if t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
+        raise ValueError("expected a column-major (n, nrhs) tensor: use t.t().contiguous().t()")
+    return _dev_ptr(t), t.stride(1) if k > 1 else n, k
+
+
+class Tree:
+    """Cluster tree and block tree (build_htree; host only)."""
+
+    def __init__(self, points: np.ndarray, opts: Opts):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        n, dim = pts.shape
+        h = C.c_void_p()
+        _check(lib().build_htree(pts.ctypes.data_as(C.POINTER(C.c_double)), n, dim, C.byref(opts), C.byref(h)))
+        self.h = h
+        self.opts = opts
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_tree_free(self.h)
+            self.h = None
+
+    def tables(self):
+        """(perm, clusters (ncl, 5), boxes (ncl, 6), blocks (nbl, 7))."""
+        n, ncl, nbl = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().hm_tree_sizes(self.h, C.byref(n), C.byref(ncl), C.byref(nbl)))
+        perm = np.zeros(n.value, np.int64)
+        cl = np.zeros((ncl.value, 5), np.int64)
+        box = np.zeros((ncl.value, 6), np.float64)
+        bl = np.zeros((nbl.value, 7), np.int32)
+        _check(lib().hm_tree_export(self.h, perm.ctypes.data, cl.ctypes.data, box.ctypes.data, bl.ctypes.data))
+        return perm, cl, box, bl
+
+    def dag(self, opts: Opts, which: int = 0):
+        """The traced DAG (host only): dict of numpy arrays and sizes."""
+        sz = np.zeros(9, np.int64)
+        _check(lib().hm_dag_sizes(self.h, C.byref(opts), which, sz.ctypes.data))
+        ntasks, nedges, nlevels, tbytes, n64, n32, npiv, nlr, nranks = (int(x) for x in sz)
+        assert tbytes == TASK_DTYPE.itemsize, (tbytes, TASK_DTYPE.itemsize)
+        tasks = np.zeros(ntasks, TASK_DTYPE)
+        sp = np.zeros(ntasks + 1, np.int32)
+        si = np.zeros(max(1, nedges), np.int32)
+        lv = np.zeros(max(1, ntasks), np.int32)
+        _, _, _, bl = self.tables()
+        boff = np.zeros((len(bl), 4), np.int64)
+        lr = np.zeros((max(1, nlr), 6), np.int64)
+        _check(lib().hm_dag_export(self.h, C.byref(opts), which, tasks.ctypes.data, sp.ctypes.data, si.ctypes.data,
+                                   lv.ctypes.data, boff.ctypes.data, lr.ctypes.data))
+        return dict(tasks=tasks, succ_ptr=sp, succ_idx=si[:nedges], level=lv[:ntasks], block_off=boff,
+                    lr=lr[:nlr], n_f64=n64, n_f32=n32, n_piv=npiv, nranks=nranks, nlevels=nlevels, nedges=nedges)
+
+
+class Matrix:
+    """H-matrix assembled on the device (h_assemble)."""
+
+    def __init__(self, tree: Tree, kernel: int, diag: float, opts: Opts, stream=None):
+        h = C.c_void_p()
+        _check(lib().h_assemble(tree.h, kernel, diag, C.byref(opts), _stream_ptr(stream), C.byref(h)))
+        self.h = h
+        self.tree = tree
+        self.opts = opts
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_matrix_free(self.h)
+            self.h = None
+
+    def matvec(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
+        import torch
+        if y is None:
+            y = torch.zeros_like(x)
+            beta = 0.0
+        xp, ldx, k = _col_major(x)
+        yp, ldy, k2 = _col_major(y)
+        assert k == k2
+        _check(lib().h_matvec(self.h, alpha, xp, ldx, beta, yp, ldy, k, _stream_ptr(stream)))
+        return y
+
+    def leaf(self, block: int):
+        return export_leaf(self.h, 0, block, self.tree)
+
+    def footprint(self) -> int:
+        b = C.c_size_t()
+        _check(lib().hm_footprint(self.h, 0, C.byref(b)))
+        return b.value
+
+
+class LU:
+    """H-LU factors (h_lu)."""
+
+    def __init__(self, a: Matrix, opts: Opts, stream=None):
+        h = C.c_void_p()
+        info = C.c_int64(0)
+        code = lib().h_lu(a.h, C.byref(opts), _stream_ptr(stream), C.byref(h), C.byref(info))
+        if code != HM_OK and code != HM_ERANK:
+            _check(code, info.value)
+        self.rank_overflow = code == HM_ERANK
+        self.h = h
+        self.a = a
+        self.tree = a.tree
+        self.opts = opts
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_lu_free(self.h)
+            self.h = None
+
+    def solve(self, b, refine_with: Matrix | None = None, rtol=1e-10, max_iter=50, stream=None):
+        """Solve in place on the (n, nrhs) column-major float64 device tensor b; returns (b, iters, relres)."""
+        bp, ldb, k = _col_major(b)
+        iters = np.zeros(max(1, (k + 63) // 64), np.int32)
+        rel = np.zeros(max(1, k), np.float64)
+        code = lib().h_solve(self.h, refine_with.h if refine_with is not None else None, bp, ldb, k, rtol,
+                             max_iter, _stream_ptr(stream), iters.ctypes.data, rel.ctypes.data)
+        if code == HM_ENOCONV:
+            return b, iters, rel
+        _check(code)
+        return b, iters, rel
+
+    def stats(self) -> dict:
+        s = LuStats()
+        _check(lib().hm_lu_stats_get(self.h, C.byref(s)))
+        d = {f: getattr(s, f) for f, _ in LuStats._fields_ if f != "tasks_by_op"}
+        d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(10) if s.tasks_by_op[i]}
+        return d
+
+    def leaf(self, block: int):
+        return export_leaf(self.h, 1, block, self.tree)
+
+    def footprint(self, kind=1) -> int:
+        b = C.c_size_t()
+        _check(lib().hm_footprint(self.h, kind, C.byref(b)))
+        return b.value
+
+
+def export_leaf(handle, kind, block, tree: Tree):
+    """('D', array, piv) or ('R', U, V) for one leaf block, FP64 host copies."""
+    _, cl, _, bl = tree.tables() if not hasattr(tree, "_tables") else tree._tables
+    tree._tables = (None, cl, None, bl)
+    tau, sigma, k = bl[block, 0], bl[block, 1], bl[block, 2]
+    m = int(cl[tau, 1] - cl[tau, 0])
+    n = int(cl[sigma, 1] - cl[sigma, 0])
+    rank = C.c_int32()
+    _check(lib().hm_export_leaf(handle, kind, block, None, C.byref(rank), None))
+    if k == 1:
+        d = np.zeros(m * n, np.float64)
+        piv = np.zeros(m, np.int32)
+        _check(lib().hm_export_leaf(handle, kind, block, d.ctypes.data, C.byref(rank), piv.ctypes.data))
+        return "D", d.reshape(n, m).T.copy(), piv
+    r = rank.value
+    d = np.zeros(max(1, (m + n) * r), np.float64)
+    _check(lib().hm_export_leaf(handle, kind, block, d.ctypes.data, C.byref(rank), None))
+    u = d[:m * r].reshape(r, m).T.copy()
+    v = d[m * r:(m + n) * r].reshape(r, n).T.copy()
+    return "R", u, v
+
+
+# names of the C-ABI, for callers who prefer the functional form
+def build_htree(points, opts: Opts) -> Tree:
+    return Tree(points, opts)
+
+
+def h_assemble(tree: Tree, kernel: int, diag: float, opts: Opts, stream=None) -> Matrix:
+    return Matrix(tree, kernel, diag, opts, stream)
+
+
+def h_lu(a: Matrix, opts: Opts, stream=None) -> LU:
+    return LU(a, opts, stream)
+
+
+def h_solve(f: LU, b, a: Matrix | None = None, rtol=1e-10, max_iter=50, stream=None):
+    return f.solve(b, a, rtol, max_iter, stream)
+
+
+def h_matvec(a: Matrix, x, y=None, alpha=1.0, beta=0.0, stream=None):
+    return a.matvec(x, y, alpha, beta, stream)

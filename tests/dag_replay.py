@@ -1,0 +1,177 @@
+"""Test-only replay of a traced task DAG in NumPy (no device).
+
+Interprets the task records exported by the library (struct Task) on NumPy
+arenas, in a random topological order of the DAG.  It checks on the CPU that
+the trace of Algorithms 1-3 and its dependencies are right: the result must
+match the oracle's sequential H-LU whatever order the DAG admits.  The task
+semantics here are plain NumPy/SciPy; nothing of this is used by the library.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+VT_F64, VT_F32, VT_IDENT, VT_NONE = 0, 1, 2, 3
+DYN_ROWS, DYN_COLS = 1, 2
+
+
+class Replay:
+    def __init__(self, dag, eps, max_rank):
+        self.d = dag
+        self.f64 = np.zeros(max(1, dag["n_f64"]))
+        self.f32 = np.zeros(max(1, dag["n_f32"]), np.float32)
+        self.piv = np.zeros(max(1, dag["n_piv"]), np.int32)
+        self.ranks = np.zeros(dag["nranks"], np.int32)
+        self.eps = eps
+        self.max_rank = max_rank
+
+    # -- views ---------------------------------------------------------------
+    def dims(self, v):
+        rows = self.ranks[v["rank_id"]] if v["dyn"] & DYN_ROWS else v["rows"]
+        cols = self.ranks[v["rank_id"]] if v["dyn"] & DYN_COLS else v["cols"]
+        return int(rows), int(cols)
+
+    def view(self, v):
+        rows, cols = self.dims(v)
+        t = int(v["type"])
+        if t == VT_IDENT:
+            return np.eye(rows, cols)
+        arena = self.f64 if t == VT_F64 else self.f32
+        off = int(v["off"])
+        if rows == 0 or cols == 0:
+            return np.zeros((rows, cols), arena.dtype)
+        isz = arena.itemsize
+        base = arena[off:]
+        return np.lib.stride_tricks.as_strided(base, (rows, cols), (int(v["rs"]) * isz, int(v["cs"]) * isz))
+
+    # -- storage ---------------------------------------------------------------
+    def load_matrix(self, blocks_by_index, block_off, lr):
+        """Fill the arenas from oracle leaves {block index: Block}."""
+        for bi, b in blocks_by_index.items():
+            off, typ, li, _ = block_off[bi]
+            arena = self.f64 if typ == VT_F64 or li >= 0 and lr[li][5] == VT_F64 else self.f32
+            if b.kind == "D":
+                arena = self.f64 if typ == VT_F64 else self.f32
+                arena[off:off + b.D.size] = b.D.flatten(order="F")
+            elif b.kind == "R":
+                u_off, v_off, m, n, cap, typ = lr[li]
+                arena = self.f64 if typ == VT_F64 else self.f32
+                k = b.rank
+                assert k <= cap
+                arena[u_off:u_off + m * k] = b.U.flatten(order="F")
+                arena[v_off:v_off + n * k] = b.V.flatten(order="F")
+                self.ranks[li] = k
+
+    def leaf(self, bi, kind, m, n, block_off, lr):
+        off, typ, li, poff = block_off[bi]
+        if kind == 1:
+            arena = self.f64 if typ == VT_F64 else self.f32
+            d = np.asarray(arena[off:off + m * n], np.float64).reshape(n, m).T.copy()
+            piv = self.piv[poff:poff + m].astype(np.int64) if poff >= 0 else None
+            return "D", d, piv
+        u_off, v_off, m_, n_, cap, typ = lr[li]
+        arena = self.f64 if typ == VT_F64 else self.f32
+        k = int(self.ranks[li])
+        u = np.asarray(arena[u_off:u_off + m * k], np.float64).reshape(k, m).T.copy()
+        v = np.asarray(arena[v_off:v_off + n * k], np.float64).reshape(k, n).T.copy()
+        return "R", u, v
+
+    # -- tasks -----------------------------------------------------------------
+    def run_task(self, t):
+        op = int(t["op"])
+        if op == 1:  # getrf
+            m = int(t["a"]["rows"])
+            a = self.view(t["a"])
+            lu, piv = sla.lu_factor(np.array(a, np.float64), check_finite=False)
+            a[:] = lu
+            self.piv[int(t["piv"]):int(t["piv"]) + m] = piv
+        elif op in (2, 3, 4):
+            m = int(t["a"]["rows"])
+            a = np.array(self.view(t["a"]), np.float64)
+            x = self.view(t["x"])
+            xs = np.array(x, np.float64)
+            if op == 2:
+                for j, p in enumerate(self.piv[int(t["piv"]):int(t["piv"]) + m]):
+                    if p != j:
+                        xs[[j, p]] = xs[[p, j]]
+                xs = sla.solve_triangular(a, xs, lower=True, unit_diagonal=True, check_finite=False)
+            elif op == 3:
+                xs = sla.solve_triangular(a, xs, trans="T", lower=False, check_finite=False)
+            else:
+                xs = sla.solve_triangular(a, xs, lower=False, check_finite=False)
+            x[:] = xs
+        elif op == 5:
+            y = self.view(t["y"])
+            prod = np.asarray(self.view(t["a"]), np.float64) @ np.asarray(self.view(t["b"]), np.float64)
+            out = t["alpha"] * prod
+            if t["beta"] != 0.0:
+                out = out + t["beta"] * np.asarray(y, np.float64)
+            y[:] = out
+        elif op == 6:
+            y = self.view(t["y"])
+            a = np.asarray(self.view(t["a"]), np.float64)
+            b = np.asarray(self.view(t["b"]), np.float64)
+            x = np.asarray(self.view(t["x"]), np.float64)
+            out = t["alpha"] * (a @ (b @ x))
+            if t["beta"] != 0.0:
+                out = out + t["beta"] * np.asarray(y, np.float64)
+            y[:] = out
+        elif op == 7:
+            self.trunc(t)
+        elif op == 8:
+            self.view(t["y"])[:] = 0.0
+        elif op == 9:
+            self.view(t["y"])[:] = self.view(t["a"])
+        else:
+            raise ValueError(op)
+
+    def trunc(self, t):
+        li = int(t["lr"])
+        u_off, v_off, m, n, cap, typ = (int(x) for x in self.d["lr"][li])
+        arena = self.f64 if typ == VT_F64 else self.f32
+        kc = int(self.ranks[li])
+        a = np.asarray(self.view(t["a"]), np.float64)
+        b = np.asarray(self.view(t["b"]), np.float64)
+        kp = a.shape[1]
+        K = kc + kp
+        if K == 0:
+            self.ranks[li] = 0
+            return
+        us = np.zeros((m, K))
+        vs = np.zeros((n, K))
+        us[:, :kc] = np.asarray(arena[u_off:u_off + m * kc], np.float64).reshape(kc, m).T
+        vs[:, :kc] = np.asarray(arena[v_off:v_off + n * kc], np.float64).reshape(kc, n).T
+        r0, c0 = int(t["r0"]), int(t["c0"])
+        us[r0:r0 + a.shape[0], kc:] = t["alpha"] * a
+        vs[c0:c0 + b.shape[0], kc:] = b
+        qu, ru = np.linalg.qr(us)
+        qv, rv = np.linalg.qr(vs)
+        w, s, zt = np.linalg.svd(ru @ rv.T)
+        k = 0 if s.size == 0 or s[0] <= 0 else int(np.count_nonzero(s > self.eps * s[0]))
+        k = min(k, cap, m, n)
+        unew = qu @ (w[:, :k] * s[:k])
+        vnew = qv @ zt[:k].T
+        arena[u_off:u_off + m * k] = unew.flatten(order="F")
+        arena[v_off:v_off + n * k] = vnew.flatten(order="F")
+        self.ranks[li] = k
+
+    def run(self, rng=None):
+        """Execute every task in a random topological order (Kahn with random picks)."""
+        tasks = self.d["tasks"]
+        n = len(tasks)
+        sp, si = self.d["succ_ptr"], self.d["succ_idx"]
+        indeg = np.zeros(n, np.int64)
+        np.add.at(indeg, si, 1)
+        ready = list(np.nonzero(indeg == 0)[0])
+        done = 0
+        while ready:
+            k = rng.integers(len(ready)) if rng is not None else 0
+            ready[k], ready[-1] = ready[-1], ready[k]
+            i = ready.pop()
+            self.run_task(tasks[i])
+            done += 1
+            for s in si[sp[i]:sp[i + 1]]:
+                indeg[s] -= 1
+                if indeg[s] == 0:
+                    ready.append(s)
+        assert done == n, "DAG has a cycle or unreachable tasks"

@@ -1,0 +1,97 @@
+"""The traced H-LU and solve DAGs, replayed in NumPy in random topological
+orders, reproduce the oracle's sequential H-LU (Algorithm 2) and solve (CPU).
+
+Same inputs on both sides (the oracle's assembled leaves are loaded into the
+traced storage layout).  Truncation decisions follow the same order, so the
+factors agree to rounding and the ranks agree exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import hmatrix as H
+from paper_1911_07531_amd import hm, inputs
+from tests.dag_replay import Replay
+
+
+def _setup(n, leaf, eta, eps, max_rank, prec=hm.FP64, seed=0):
+    pts, diag = inputs.sphere_problem(n, seed)
+    opts = hm.make_opts(leaf=leaf, eta=eta, eps=eps, max_rank=max_rank, prec=prec)
+    t = hm.Tree(pts, opts)
+    perm, cl = H.build_cluster_tree(pts, leaf)
+    root = H.build_block_tree(cl[0], eta)
+    a = H.assemble(pts, perm, cl, root, diag, eps, max_rank)
+    return t, opts, a
+
+
+def _factors_from_replay(rp, t, a_template, dag):
+    _, cl, _, bl = t.tables()
+    f = H.hlu.__globals__["_copy_block"](a_template.root)
+    for b in H.leaf_blocks(f):
+        kind = "D" if b.kind == "D" else "R"
+        m, n = b.rows, b.cols
+        r = rp.leaf(b.index, 1 if kind == "D" else 2, m, n, dag["block_off"], dag["lr"])
+        if kind == "D":
+            b.D = r[1]
+            if b.tau is b.sigma:
+                b.piv = r[2]
+        else:
+            b.U, b.V = r[1], r[2]
+    return H.HMatrix(f, a_template.perm, a_template.clusters, a_template.n, a_template.eps, a_template.max_rank)
+
+
+@pytest.mark.parametrize("n,leaf,eps,max_rank,orders", [(512, 32, 1e-6, 0, 2), (1024, 24, 1e-4, 8, 1),
+                                                        (600, 16, 1e-8, 0, 1)])
+def test_replay_matches_oracle_hlu(n, leaf, eps, max_rank, orders):
+    t, opts, a = _setup(n, leaf, 2.0, eps, max_rank)
+    ref = H.hlu(a)
+    dag = t.dag(opts, 0)
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    ref_d = H.densify(ref.root)
+    scale = np.abs(H.densify(a.root)).max()
+    ref_ranks = H.rank_table(ref)
+    for k in range(orders):
+        rp = Replay(dag, eps, max_rank)
+        rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+        rp.run(np.random.default_rng(k))
+        f = _factors_from_replay(rp, t, a, dag)
+        got = H.densify(f.root)
+        assert np.max(np.abs(got - ref_d)) <= 1e-9 * scale
+        ranks = H.rank_table(f)
+        diff = [abs(ranks[i] - ref_ranks[i]) for i in ref_ranks]
+        assert max(diff) <= 1 and sum(diff) <= max(2, len(diff) // 100)
+        for b in H.leaf_blocks(f.root):
+            if b.tau is b.sigma:
+                ob = next(x for x in H.leaf_blocks(ref.root) if x.index == b.index)
+                assert np.array_equal(b.piv, ob.piv)
+
+
+def test_replay_solve_matches_oracle():
+    n, leaf, eps = 512, 32, 1e-6
+    t, opts, a = _setup(n, leaf, 2.0, eps, 0)
+    ref = H.hlu(a)
+    dag = t.dag(opts, 0)
+    sdag = t.dag(opts, 1)
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    rp = Replay(dag, eps, 0)
+    rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+    rp.run(np.random.default_rng(3))
+    # the solve DAG shares the storage layout; its panel sits in the f64 arena
+    rs = Replay(sdag, eps, 0)
+    rs.f64[:len(rp.f64)] = rp.f64[:len(rs.f64)] if len(rs.f64) <= len(rp.f64) else np.pad(rp.f64, (0, len(rs.f64) - len(rp.f64)))
+    rs.piv[:] = rp.piv
+    rs.ranks[:] = rp.ranks
+    b = inputs.rhs(n, 5, seed=1)
+    nrhs_slot = sdag["nranks"] - 1
+    rs.ranks[nrhs_slot] = 5
+    panel_off = [int(tk["x"]["off"]) for tk in sdag["tasks"] if tk["op"] == 2][0]
+    # the panel is the view written by the first lower solve: rows start at its offset minus its row shift
+    first = sdag["tasks"][0]
+    del first
+    po = min(int(tk["x"]["off"]) for tk in sdag["tasks"] if tk["op"] in (2, 4))
+    assert po <= panel_off
+    rs.f64[po:po + n * 5] = b[a.perm].flatten(order="F")
+    rs.run(np.random.default_rng(4))
+    x = np.empty((n, 5))
+    x[a.perm] = rs.f64[po:po + n * 5].reshape(5, n).T
+    ref_x = H.solve(ref, b)
+    assert np.allclose(x, ref_x, rtol=0, atol=1e-9 * np.abs(ref_x).max())

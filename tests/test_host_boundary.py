@@ -1,0 +1,91 @@
+"""C-ABI library on the CPU: exported symbols, exact tree parity with the
+oracle (Def. 2.1, Def. 2.2), and invariants of the traced DAG (Def. 3.2:
+every edge runs forward in the sequential order, so the graph is acyclic).
+No compute call is made (no device here)."""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import hmatrix as H
+from paper_1911_07531_amd import hm, inputs
+
+
+@pytest.fixture(scope="module")
+def L():
+    return hm.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", hm.LIB_PATH], capture_output=True, text=True).stdout
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    header = open(hm.os.path.join(hm._HERE, "..", "include", "hm.h")).read()
+    for name in hm.exported_symbols():
+        assert name in names, name
+        assert name + "(" in header, name
+        getattr(L, name)
+
+
+@pytest.mark.parametrize("n,leaf,eta,seed", [(2048, 32, 2.0, 0), (3000, 64, 2.0, 1), (777, 20, 1.0, 2)])
+def test_tree_parity_with_oracle(n, leaf, eta, seed):
+    pts = inputs.sphere_points(n, seed)
+    t = hm.Tree(pts, hm.make_opts(leaf=leaf, eta=eta))
+    perm, cl, box, bl = t.tables()
+    operm, ocl = H.build_cluster_tree(pts, leaf)
+    oroot = H.build_block_tree(ocl[0], eta)
+    assert np.array_equal(perm, operm)
+    assert len(cl) == len(ocl)
+    for i, c in enumerate(ocl):
+        sons = [s.index for s in c.sons] if c.sons else [-1, -1]
+        assert list(cl[i]) == [c.begin, c.end, sons[0], sons[1], c.level]
+        assert np.array_equal(box[i, :3], c.lo) and np.array_equal(box[i, 3:], c.hi)
+    oblocks = H.block_list(oroot)
+    assert len(bl) == len(oblocks)
+    kind = {"S": 0, "D": 1, "R": 2}
+    for b in oblocks:
+        row = bl[b.index]
+        assert row[0] == b.tau.index and row[1] == b.sigma.index and row[2] == kind[b.kind]
+        if b.kind == "S":
+            assert list(row[3:]) == [b.sons[i][j].index for i in range(2) for j in range(2)]
+
+
+def test_invalid_arguments_rejected(L):
+    pts = np.zeros((4, 3))
+    h = ctypes.c_void_p()
+    bad = hm.make_opts(leaf=0)
+    assert L.build_htree(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4, 3, ctypes.byref(bad),
+                         ctypes.byref(h)) == hm.HM_EINVAL
+    bad = hm.make_opts(eta=0.0)
+    assert L.build_htree(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4, 3, ctypes.byref(bad),
+                         ctypes.byref(h)) == hm.HM_EINVAL
+    assert L.build_htree(None, 4, 3, ctypes.byref(hm.make_opts()), ctypes.byref(h)) == hm.HM_EINVAL
+    assert b"n >= 1" in L.hm_last_error() or b"null" in L.hm_last_error()
+    with pytest.raises(hm.HmError):
+        hm.Tree(pts, hm.make_opts(leaf=-3))
+
+
+@pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])
+def test_dag_is_forward_and_levels_consistent(prec):
+    pts = inputs.sphere_points(2048, 0)
+    opts = hm.make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=prec)
+    t = hm.Tree(pts, opts)
+    for which in (0, 1):
+        d = t.dag(opts, which)
+        sp, si, lv = d["succ_ptr"], d["succ_idx"], d["level"]
+        n = len(d["tasks"])
+        assert n > 0 and sp[-1] == len(si)
+        src = np.repeat(np.arange(n), np.diff(sp))
+        assert np.all(si > src)                 # edges run forward in trace order
+        assert np.all(lv[si] >= lv[src] + 1)    # levels are a valid schedule
+        assert lv.max() + 1 == d["nlevels"]
+        ops = d["tasks"]["op"]
+        assert set(np.unique(ops)) <= set(range(1, 10))
+    # every diagonal leaf is factored exactly once, in order along the diagonal
+    d = t.dag(opts, 0)
+    getrf = d["tasks"][d["tasks"]["op"] == 1]
+    rows = getrf["row0"]
+    assert np.all(np.diff(rows) > 0)
+    _, cl, _, bl = t.tables()
+    ndiag = sum(1 for b in bl if b[2] == 1 and b[0] == b[1])
+    assert len(getrf) == ndiag
