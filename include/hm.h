@@ -91,6 +91,9 @@ typedef struct {
   double exec_ms;      /* device time of the executor launch(es), HIP events */
   int64_t temp_bytes;  /* temporaries of the traced DAG */
   int64_t rank_overflows;
+  double op_busy_ms[10];  /* summed workgroup-busy time per task kind (index = task kind) */
+  double trunc_phase_ms[6]; /* truncation phases: Gram, Cholesky, core, SVD, solve, rebuild */
+  double trunc_mean_k, trunc_mean_mn; /* mean stacked rank K and mean m + n of truncations */
 } hm_lu_stats;
 
 /* Device allocator hook; ctx is passed back.  Both may be NULL to restore

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -38,6 +39,7 @@ __global__ void colnorm2_kernel(const double* v, int64_t ld, int64_t n, double* 
 __global__ void axpy_cols_kernel(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
                                  const int32_t* active);
 __global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs);
+__global__ void set_i32_kernel(int32_t* p, int32_t v0, int32_t v1, int32_t v2, int32_t v3, int n);
 }  // namespace hm
 
 using namespace hm;
@@ -68,6 +70,17 @@ struct DevBuf {
   hipStream_t stream = nullptr;
 };
 
+// HM_DEBUG_POISON=1 fills every new allocation with all-ones bytes (NaN for
+// floating point, -1 for integers) so that a read of unwritten memory shows.
+static bool poison_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("HM_DEBUG_POISON");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 static bool dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
   b.bytes = bytes;
   b.stream = s;
@@ -77,9 +90,11 @@ static bool dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
   }
   if (g_alloc) {
     b.p = g_alloc(bytes, (void*)s, g_alloc_ctx);
-    return b.p != nullptr;
+  } else if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
   }
-  return hipMalloc(&b.p, bytes) == hipSuccess;
+  if (b.p && poison_enabled()) (void)hipMemsetAsync(b.p, 0xff, bytes, s);
+  return b.p != nullptr;
 }
 
 static void dev_free(DevBuf& b) {
@@ -191,6 +206,11 @@ static hm_status device_setup() {
       per_cu < 1)
     per_cu = 1;
   g_nwg = cus * per_cu;
+  // HM_DEBUG_MAX_WG caps the executor workgroups (1 = one task at a time)
+  if (const char* e = getenv("HM_DEBUG_MAX_WG")) {
+    int v = atoi(e);
+    if (v >= 1 && v < g_nwg) g_nwg = v;
+  }
   return HM_OK;
 }
 
@@ -253,7 +273,7 @@ static hm_status ensure_uploaded(PlanEntry* pe, hipStream_t s) {
 static hm_status exec_state_alloc(ExecState& es, int64_t ntasks, hipStream_t s) {
   if (!dev_alloc(es.deps, std::max<int64_t>(1, ntasks) * 4, s) ||
       !dev_alloc(es.queue, std::max<int64_t>(1, ntasks) * 4, s) || !dev_alloc(es.qctl, 64, s) ||
-      !dev_alloc(es.status, 64, s) || !dev_alloc(es.counters, 64, s))
+      !dev_alloc(es.status, 64, s) || !dev_alloc(es.counters, 32 * 8, s))
     return fail(HM_ENOMEM, "device allocation failed (executor state)");
   return HM_OK;
 }
@@ -283,10 +303,8 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.counters = (unsigned long long*)es.counters.p;
   a.nwg = g_nwg;
   a.spin_limit = g_clock_khz * 1000 * 30;  // 30 s of wall clock
-  HIPCHK(hipMemsetAsync(es.status.p, 0, 16, s));
-  int32_t big = 0x7fffffff;
-  HIPCHK(hipMemcpyAsync((char*)es.status.p + 4, &big, 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(es.counters.p, 0, 16, s));
+  hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
+  HIPCHK(hipMemsetAsync(es.counters.p, 0, 32 * 8, s));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -747,9 +765,14 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   HIPCHK(hipStreamSynchronize(s));
   dev_free(scratch);
   int32_t stv[4];
-  unsigned long long ctr[2];
+  unsigned long long ctr[32];
   HIPCHK(hipMemcpy(stv, F->lu_st.status.p, 16, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(ctr, F->lu_st.counters.p, 16, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ctr, F->lu_st.counters.p, sizeof(ctr), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 10; ++k) F->stats.op_busy_ms[k] = (double)ctr[2 + k] / (double)g_clock_khz;
+  for (int k = 0; k < 6; ++k) F->stats.trunc_phase_ms[k] = (double)ctr[22 + k] / (double)g_clock_khz;
+  double ntr = (double)std::max<unsigned long long>(1, ctr[12 + OP_TRUNC]);
+  F->stats.trunc_mean_k = ctr[28] / ntr;
+  F->stats.trunc_mean_mn = ctr[29] / ntr;
   F->stats.ntasks = pe->lu.ntasks;
   F->stats.nedges = pe->lu.nedges;
   F->stats.nlevels = pe->lu.nlevels;
@@ -791,7 +814,8 @@ hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out) {
 // permuted order held in the factor's panel
 static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
   PlanEntry* pe = F->pe;
-  HIPCHK(hipMemcpyAsync((int32_t*)F->ranks.p + pe->plan.nrhs_slot, &nc, 4, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)F->ranks.p + pe->plan.nrhs_slot, nc, 0, 0,
+                     0, 1);
   ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
                          (const LrDesc*)pe->lr.p, F->eps, F->max_rank);
   return run_dag(pe->solve, a, F->solve_st, F->exec, s, nullptr);

@@ -16,7 +16,7 @@ constexpr int kThreads = 256;      // threads per workgroup of every block kerne
 constexpr int kMaxK = 128;         // widest stacked rank in a truncated addition
 constexpr int kMaxCap = 64;        // widest stored rank of a low-rank leaf
 constexpr int kMaxLeaf = 128;      // largest diagonal leaf the getrf/trsm kernels take
-constexpr int kLdsBytes = 80 * 1024;  // dynamic LDS per workgroup
+constexpr int kLdsBytes = 76 * 1024;  // dynamic LDS per workgroup (two workgroups per CU)
 constexpr int kNrhsSlotOffset = 0; // rank slot that carries the current nrhs of a solve
 
 enum ViewType : int32_t { VT_F64 = 0, VT_F32 = 1, VT_IDENT = 2, VT_NONE = 3 };
@@ -89,7 +89,10 @@ struct ExecArgs {
   int32_t* queue;      // ready queue (ntasks slots, -1 = empty)
   int32_t* qctl;       // [0] head, [1] tail, [2] done, [3] abort
   int64_t spin_limit;  // wall-clock ticks a waiting workgroup polls before giving up
-  unsigned long long* counters;  // [0] algorithmic bytes, [1] algorithmic flops (null: off)
+  // [0] algorithmic bytes, [1] algorithmic flops, [2 + op] busy wall-clock ticks
+  // of each task kind, [12 + op] task count, [22..27] ticks of the truncation
+  // phases, [28] sum of stacked ranks K, [29] sum of m + n (null: off)
+  unsigned long long* counters;
 };
 
 

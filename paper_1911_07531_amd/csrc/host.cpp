@@ -391,6 +391,17 @@ class Tracer {
     int id = (int)d_.tasks.size();
     d_.tasks.push_back(tk);
     preds_.clear();
+    // A view whose extent follows a low-rank leaf's rank must be ordered after
+    // the truncations that set that rank: the task must also access the leaf's
+    // U or V factor (a truncation rewrites both together with the rank).
+    for (auto& a : acc) {
+      const View& v = a.first->v;
+      if (!v.dyn || v.rank_id < 0 || v.rank_id >= (int)p_.lr_block.size()) continue;
+      int b = p_.lr_block[v.rank_id];
+      bool backed = false;
+      for (auto& c : acc) backed |= c.first->obj == obj_a_[b] || c.first->obj == obj_b_[b];
+      if (!backed) fail("internal: a run-time extent follows a rank the task does not read");
+    }
     for (auto& a : acc)
       if (a.first->obj >= 0 && (a.second & ACC_R)) access(id, a.first->obj, a.first->rect, false);
     for (auto& a : acc)
@@ -459,10 +470,15 @@ class Tracer {
     t.x = x.v;
     emit(t, {{&a, ACC_R}, {&b, ACC_R}, {&x, ACC_R}, {&y, beta != 0.0 ? ACC_RW : ACC_W}});
   }
+  // Clears the whole stored extent (capacity columns), so that it needs no
+  // ordering against the rank that later accumulations follow.
   void zero(const HView& y) {
     Task t = blank(OP_ZERO);
-    t.y = y.v;
-    emit(t, {{&y, ACC_W}});
+    HView full = y;
+    full.v.dyn = 0;
+    full.v.rank_id = -1;
+    t.y = full.v;
+    emit(t, {{&full, ACC_W}});
   }
   void trsm(int op, int d, const HView& x) {
     Task t = blank(op);

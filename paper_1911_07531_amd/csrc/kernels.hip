@@ -247,6 +247,7 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
           bi = oi;
         }
       }
+      if (bi >= m) bi = j;  // no comparable entry (NaN column): keep the row
       if (tid == 0) {
         s_piv[0] = bi;
         a.piv[t.piv + j] = bi;
@@ -412,8 +413,8 @@ __device__ int pivoted_cholesky(double* G, int K, int* perm, double* dsc, int* s
         }
       }
       if (tid == 0) {
-        s_int[0] = bi;
-        s_int[1] = best > tol ? 1 : 0;
+        s_int[0] = bi < K ? bi : s;
+        s_int[1] = (bi < K && best > tol) ? 1 : 0;
       }
     }
     __syncthreads();
@@ -581,6 +582,15 @@ __device__ void upper_solve(const double* R, int K, int r, double* X, int kk) {
   }
 }
 
+// Adds the wall-clock ticks since *t0 to counters[slot] (thread 0) and restarts *t0.
+__device__ __forceinline__ void phase_tick(const ExecArgs& a, int slot, uint64_t* t0) {
+  if (a.counters && threadIdx.x == 0) {
+    uint64_t t1 = wall_clock64();
+    atomicAdd(&a.counters[slot], (unsigned long long)(t1 - *t0));
+    *t0 = t1;
+  }
+}
+
 // Returns the new rank.
 __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
                           char* lds, double* scratch) {
@@ -593,9 +603,37 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     __syncthreads();
     return 0;
   }
+  uint64_t tph = threadIdx.x == 0 ? wall_clock64() : 0;
+  if (a.counters && tid == 0) {
+    atomicAdd(&a.counters[28], (unsigned long long)K);
+    atomicAdd(&a.counters[29], (unsigned long long)(m + n));
+  }
   TruncScratch S = trunc_scratch(scratch);
   double* sA = (double*)lds;
   double* sB = sA + TK * (TM + TP);
+  // index and scale vectors always in LDS after the GEMM tiles
+  {
+    double* v = (double*)(lds + kTileBytes);
+    S.dU = v;
+    S.dV = v + kMaxK;
+    S.sig = v + 2 * kMaxK;
+    int* ip = (int*)(v + 3 * kMaxK);
+    S.pU = ip;
+    S.pV = ip + kMaxK;
+    S.sel = ip + 2 * kMaxK;
+    S.posU = ip + 3 * kMaxK;
+    S.posV = ip + 4 * kMaxK;
+  }
+  constexpr int kVecBytes = 3 * kMaxK * 8 + 5 * kMaxK * 4;
+  // K x K work matrices in LDS too when they fit
+  const bool small = (int64_t)kTileBytes + kVecBytes + (int64_t)4 * K * K * 8 + 64 <= kLdsBytes;
+  if (small) {
+    double* w = (double*)(lds + kTileBytes + kVecBytes);
+    S.GU = w;
+    S.GV = w + K * K;
+    S.B = w + 2 * K * K;
+    S.Z = w + 3 * K * K;
+  }
   // 1. Gram matrices G_U = U_s^T U_s, G_V = V_s^T V_s (FP64)
   gemm_tiles<double>(
       K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
@@ -604,9 +642,11 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
       [&](int i, int j, double v) { S.GV[i * K + j] = v; }, true, true, sA, sB);
   __syncthreads();
+  phase_tick(a, 22, &tph);
   // 2. R factors
   const int rU = pivoted_cholesky(S.GU, K, S.pU, S.dU, s_int);
   const int rV = pivoted_cholesky(S.GV, K, S.pV, S.dV, s_int);
+  phase_tick(a, 23, &tph);
   if (rU == 0 || rV == 0) {
     if (tid == 0) a.ranks[lr_index] = 0;
     __syncthreads();
@@ -617,23 +657,31 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     S.posV[S.pV[q]] = q;
   }
   __syncthreads();
-  // 3. core B = Rt_U Rt_V^T, Rt[i][l] = R'[i][pos(l)] * ||column l||  (rU x rV, column-major)
-  const bool core_lds = (int64_t)(rU * rV + rV * rV) * 8 <= kLdsBytes - 128;
-  double* B = core_lds ? (double*)lds : S.B;
-  double* Z = core_lds ? (double*)lds + rU * rV : S.Z;
+  // 3. core B = Rt_U Rt_V^T with Rt[i][l] = R'[i][pos(l)] * ||column l||
+  //    (rU x rV, column-major).  R' is upper trapezoidal in pivoted order:
+  //    clear what lies left of its diagonal, then B[i][j] =
+  //    sum_l R'_U[i][posU l] R'_V[j][posV l] w[l], w[l] = ||u_l|| ||v_l||.
+  double* B = S.B;
+  double* Z = S.Z;
+  for (int e = tid; e < rU * K; e += blockDim.x)
+    if (e % K < e / K) S.GU[e] = 0.0;
+  for (int e = tid; e < rV * K; e += blockDim.x)
+    if (e % K < e / K) S.GV[e] = 0.0;
+  for (int l = tid; l < K; l += blockDim.x) S.sig[l] = (S.dU[l] == 0.0 || S.dV[l] == 0.0) ? 0.0 : 1.0 / (S.dU[l] * S.dV[l]);
+  __syncthreads();
   for (int e = tid; e < rU * rV; e += blockDim.x) {
-    int i = e % rU, j = e / rU;
+    const int i = e % rU, j = e / rU;
+    const double* ru = S.GU + i * K;
+    const double* rv = S.GV + j * K;
     double s = 0.0;
-    for (int l = 0; l < K; ++l) {
-      int qu = S.posU[l], qv = S.posV[l];
-      if (qu < i || qv < j || S.dU[l] == 0.0 || S.dV[l] == 0.0) continue;
-      s += (S.GU[i * K + qu] / S.dU[l]) * (S.GV[j * K + qv] / S.dV[l]);
-    }
+    for (int l = 0; l < K; ++l) s += ru[S.posU[l]] * rv[S.posV[l]] * S.sig[l];
     B[j * rU + i] = s;
   }
   __syncthreads();
+  phase_tick(a, 24, &tph);
   // 4. SVD of the core: columns of B Z are W_j sigma_j
   jacobi_svd(B, Z, rU, rV, s_int + 4);
+  phase_tick(a, 25, &tph);
   for (int j = tid; j < rV; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
@@ -673,16 +721,23 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     S.YV[c * rV + i] = Z[S.sel[c] * rV + i];
   }
   __syncthreads();
-  upper_solve(S.GU, K, rU, S.YU, kk);
-  upper_solve(S.GV, K, rV, S.YV, kk);
+  // the core and its rotations are no longer needed: solve in their place
+  double* yu = B;  // rU x kk <= rU x rV
+  double* yv = Z;  // rV x kk <= rV x rV
+  for (int e = tid; e < rU * kk; e += blockDim.x) yu[e] = S.YU[e];
+  for (int e = tid; e < rV * kk; e += blockDim.x) yv[e] = S.YV[e];
+  __syncthreads();
+  upper_solve(S.GU, K, rU, yu, kk);
+  upper_solve(S.GV, K, rV, yv, kk);
   __syncthreads();
   for (int e = tid; e < K * kk; e += blockDim.x) {
     int l = e % K, c = e / K;
     int qu = S.posU[l], qv = S.posV[l];
-    S.TU[c * K + l] = qu < rU ? S.dU[l] * S.YU[c * rU + qu] : 0.0;
-    S.TV[c * K + l] = qv < rV ? S.dV[l] * S.YV[c * rV + qv] : 0.0;
+    S.TU[c * K + l] = qu < rU ? S.dU[l] * yu[c * rU + qu] : 0.0;
+    S.TV[c * K + l] = qv < rV ? S.dV[l] * yv[c * rV + qv] : 0.0;
   }
   __syncthreads();
+  phase_tick(a, 26, &tph);
   // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile since
   //    kk <= 64, so every row tile is read completely before it is overwritten)
   RV uc{d.u_off, m, kk, 1, m, d.type};
@@ -694,6 +749,7 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       n, kk, K, [&](int r, int l) { return sv(a, r, l); }, [&](int l, int c) { return S.TV[c * K + l]; },
       [&](int r, int c, double v) { vst(a, vc, r, c, v); }, false, true, sA, sB);
   __syncthreads();
+  phase_tick(a, 27, &tph);
   if (tid == 0) a.ranks[lr_index] = kk;
   __syncthreads();
   return kk;
@@ -764,9 +820,26 @@ __device__ void count_task(const ExecArgs& a, const Task& t) {
   atomicAdd(&a.counters[1], (unsigned long long)flops);
 }
 
+__device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch);
+
 __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
   const Task& t = a.tasks[id];
-  if (threadIdx.x == 0) count_task(a, t);
+  uint64_t t0 = 0;
+  if (threadIdx.x == 0) {
+    count_task(a, t);
+    t0 = wall_clock64();
+  }
+  run_task_body(a, t, lds, scratch);
+  if (a.counters) {
+    __syncthreads();
+    if (threadIdx.x == 0 && t.op >= 0 && t.op < 10) {
+      atomicAdd(&a.counters[2 + t.op], (unsigned long long)(wall_clock64() - t0));
+      atomicAdd(&a.counters[12 + t.op], 1ull);
+    }
+  }
+}
+
+__device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
   switch (t.op) {
     case OP_GETRF:
       op_getrf(a, t, lds);
@@ -875,7 +948,7 @@ __global__ void __launch_bounds__(kThreads) exec_dataflow_kernel(ExecArgs a) {
         int prev = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 1) {
           int pos = atomicAdd(&a.qctl[1], 1);
-          __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
@@ -1189,6 +1262,15 @@ __global__ void axpy_cols_kernel(double* y, int64_t ldy, const double* x, int64_
   int64_t k = i % n, r = i / n;
   if (active && !active[r]) return;
   y[k + r * ldy] += x[k + r * ldx];
+}
+// p[i] = v[i] for i < n (small control words written in stream order)
+__global__ void set_i32_kernel(int32_t* p, int32_t v0, int32_t v1, int32_t v2, int32_t v3, int n) {
+  if (threadIdx.x == 0) {
+    if (n > 0) p[0] = v0;
+    if (n > 1) p[1] = v1;
+    if (n > 2) p[2] = v2;
+    if (n > 3) p[3] = v3;
+  }
 }
 // copy / convert one leaf-block arena region (A layout -> LU layout)
 __global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs) {

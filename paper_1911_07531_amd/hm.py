@@ -38,7 +38,9 @@ class Opts(C.Structure):
 class LuStats(C.Structure):
     _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
                 ("tasks_by_op", C.c_int64 * 10), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
-                ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64)]
+                ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64),
+                ("op_busy_ms", C.c_double * 10), ("trunc_phase_ms", C.c_double * 6),
+                ("trunc_mean_k", C.c_double), ("trunc_mean_mn", C.c_double)]
 
 
 # numpy view of one traced task record (struct Task in csrc/hm_internal.h)
@@ -65,6 +67,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: run paper_1911_07531_amd/build.py (or __graft_entry__.build())")
+    # torch ships its own libamdhip64.so.7; load it first so that the process
+    # holds a single HIP runtime, shared by torch's tensors and this library
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i64, dbl, ip = C.c_void_p, C.c_int64, C.c_double, C.c_int
     L.hm_last_error.restype = C.c_char_p
@@ -89,8 +97,42 @@ def lib():
     for name in ("hm_tree_free", "hm_matrix_free", "hm_lu_free"):
         getattr(L, name).argtypes = [vp]
         getattr(L, name).restype = None
+    L.hm_set_allocator.argtypes = [vp, vp, vp]
+    L.hm_set_allocator.restype = C.c_int
     _lib = L
+    _install_torch_allocator(L)
     return L
+
+
+_ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_callbacks = []
+
+
+def _install_torch_allocator(L):
+    """Route the library's device allocations through torch's caching allocator."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+    except Exception:
+        return
+
+    def alloc(size, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size), torch.cuda.current_device(), stream or 0)
+        except Exception:
+            return None
+
+    def free(ptr, size, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    ca, cf = _ALLOC_T(alloc), _FREE_T(free)
+    _callbacks[:] = [ca, cf]
+    _check(L.hm_set_allocator(C.cast(ca, C.c_void_p), C.cast(cf, C.c_void_p), None))
 
 
 def _check(code: int, info: int = 0):
@@ -121,9 +163,9 @@ def _col_major(t):
     if t.dim() == 1:
         return _dev_ptr(t), t.shape[0], 1
     n, k = t.shape
-    if t.stride(0) != 1 or (k > 1 and t.stride(1) < n):
+    if (n > 1 and t.stride(0) != 1) or (k > 1 and t.stride(1) < n):
         raise ValueError("expected a column-major (n, nrhs) tensor: use t.t().contiguous().t()")
-    return _dev_ptr(t), t.stride(1) if k > 1 else n, k
+    return _dev_ptr(t), max(n, t.stride(1)) if k > 1 else n, k
 
 
 class Tree:
@@ -243,8 +285,11 @@ class LU:
     def stats(self) -> dict:
         s = LuStats()
         _check(lib().hm_lu_stats_get(self.h, C.byref(s)))
-        d = {f: getattr(s, f) for f, _ in LuStats._fields_ if f != "tasks_by_op"}
+        d = {f: getattr(s, f) for f, _ in LuStats._fields_ if f not in ("tasks_by_op", "op_busy_ms", "trunc_phase_ms")}
+        d["trunc_phase_ms"] = dict(zip(["gram", "cholesky", "core", "svd", "solve", "rebuild"],
+                                       [float(x) for x in s.trunc_phase_ms]))
         d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(10) if s.tasks_by_op[i]}
+        d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(10) if s.tasks_by_op[i]}
         return d
 
     def leaf(self, block: int):

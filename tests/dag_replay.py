@@ -18,8 +18,10 @@ DYN_ROWS, DYN_COLS = 1, 2
 class Replay:
     def __init__(self, dag, eps, max_rank):
         self.d = dag
-        self.f64 = np.zeros(max(1, dag["n_f64"]))
-        self.f32 = np.zeros(max(1, dag["n_f32"]), np.float32)
+        # unwritten storage holds NaN, so a task that reads before its producer
+        # (a missing edge) or past what was written shows up in the result
+        self.f64 = np.full(max(1, dag["n_f64"]), np.nan)
+        self.f32 = np.full(max(1, dag["n_f32"]), np.nan, np.float32)
         self.piv = np.zeros(max(1, dag["n_piv"]), np.int32)
         self.ranks = np.zeros(dag["nranks"], np.int32)
         self.eps = eps
@@ -40,6 +42,8 @@ class Replay:
         off = int(v["off"])
         if rows == 0 or cols == 0:
             return np.zeros((rows, cols), arena.dtype)
+        last = off + (rows - 1) * int(v["rs"]) + (cols - 1) * int(v["cs"])
+        assert off >= 0 and last < arena.size, ("view out of its arena", off, rows, cols, v["rs"], v["cs"], arena.size)
         isz = arena.itemsize
         base = arena[off:]
         return np.lib.stride_tricks.as_strided(base, (rows, cols), (int(v["rs"]) * isz, int(v["cs"]) * isz))

@@ -1,0 +1,147 @@
+"""GPU parity of the H-LU path against the FP64 oracle (through the C-ABI).
+
+Bars (written in each test):
+  * trees: exact integers (CPU test) ; leaf getrf on identical input:
+    interchanges bit-exact, values within 1e-13 relative (same FP64 steps,
+    different summation order);
+  * assembly: ranks within +-2 of the oracle's truncated SVD; block error
+    ||A_b - U V^T||_2 <= 2 eps sigma_1 (ACA + recompression vs exact SVD);
+  * H-LU: ||P A - L U||_2 / ||A||_2 <= 10 eps, factor ranks within +-2 of the
+    oracle's, solve relative residuals <= 2x the oracle's (+ 1e-12 slack);
+  * matvec: equal to the densified exported matrix times x, 1e-13 relative;
+  * executors: the level-by-level and dataflow replays give bit-identical
+    factors (every conflicting pair of tasks is ordered by the DAG).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import hmatrix as H
+from paper_1911_07531_amd import hm, inputs
+from tests.gpu_common import Problem, device_rhs, require_gpu, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.mark.parametrize("m", [1, 7, 32, 64])
+def test_getrf_single_leaf_bit_exact_pivots(m):
+    # one diagonal leaf: the whole matrix is one dense block
+    p = Problem(m, 64, 1e-6, oracle=False)
+    f = hm.LU(p.A, p.opts)
+    kind, a, _ = p.A.leaf(0)
+    assert kind == "D"
+    kind, lu, piv = f.leaf(0)
+    lu_ref, piv_ref = sla.lu_factor(a)
+    assert np.array_equal(piv, piv_ref)
+    assert np.max(np.abs(lu - lu_ref)) <= 1e-13 * np.abs(a).max() * max(1, m)
+
+
+def test_singular_leaf_reports_row():
+    # two points at distance 1 with the log kernel and a zero diagonal: the
+    # single leaf is the zero matrix, so the first pivot is an exact zero
+    pts = np.array([[0.0, 0.0], [1.0, 0.0]])
+    opts = hm.make_opts(leaf=4, eta=2.0, eps=1e-6)
+    t = hm.Tree(pts, opts)
+    a = hm.Matrix(t, hm.LOG2D, 0.0, opts)
+    with pytest.raises(hm.HmError) as ei:
+        hm.LU(a, opts)
+    assert ei.value.code == hm.HM_ESINGULAR and ei.value.info == 0
+
+
+@pytest.fixture(scope="module")
+def c1():
+    """n = 2048, leaf 32, eta = 2, eps = 1e-6 (the small sphere workload)."""
+    p = Problem(2048, 32, 1e-6)
+    f = hm.LU(p.A, p.opts)
+    of = H.hlu(p.oa)
+    return p, f, of
+
+
+def test_assembly_ranks_and_error_c1(c1):
+    p, _, _ = c1
+    ga = p.gpu_as_oracle(0, p.A.h)
+    orank = H.rank_table(p.oa)
+    grank = H.rank_table(ga)
+    d = np.array([grank[k] - orank[k] for k in orank])
+    assert np.max(np.abs(d)) <= 2, np.unique(d, return_counts=True)
+    rng = np.random.default_rng(0)
+    lr = [b for b in H.leaf_blocks(ga.root) if b.kind == "R"]
+    for b in rng.choice(lr, 40, replace=False):
+        exact = H.kernel_block(p.pts, ga.perm, b.tau, b.sigma, p.diag)
+        s1 = np.linalg.norm(exact, 2)
+        assert np.linalg.norm(exact - b.U @ b.V.T, 2) <= 2 * p.eps * s1
+    for b in H.leaf_blocks(ga.root):
+        if b.kind == "D":
+            exact = H.kernel_block(p.pts, ga.perm, b.tau, b.sigma, p.diag)
+            assert np.array_equal(b.D, exact) or np.max(np.abs(b.D - exact)) <= 1e-15 * np.abs(exact).max()
+
+
+def test_hlu_error_bound_and_ranks_c1(c1):
+    p, f, of = c1
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    err = H.lu_error_2norm(dense, gf, exact=True)
+    oerr = H.lu_error_2norm(dense, of, exact=True)
+    print(f"gpu ||PA-LU||/||A|| = {err:.3e}, oracle {oerr:.3e}")
+    assert err <= 10 * p.eps
+    orank = H.rank_table(of)
+    grank = H.rank_table(gf)
+    d = np.array([grank[k] - orank[k] for k in orank])
+    assert np.max(np.abs(d)) <= 2, np.unique(d, return_counts=True)
+
+
+def test_solve_residuals_c1(c1):
+    p, f, of = c1
+    b = inputs.rhs(p.n, 16, seed=1)
+    xg = to_host(f.solve(device_rhs(b))[0])
+    xo = H.solve(of, b)
+    dense = p.dense_exact()
+    a_user = np.empty_like(dense)
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = dense
+    rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
+    ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    print("residual gpu / oracle", rg.max(), ro.max())
+    assert np.all(rg <= 2 * ro + 1e-12)
+
+
+def test_matvec_c1(c1):
+    p, _, _ = c1
+    ga = p.gpu_as_oracle(0, p.A.h)
+    x = inputs.rhs(p.n, 20, seed=5)
+    y0 = inputs.rhs(p.n, 20, seed=6)
+    ah = np.empty((p.n, p.n))
+    ah[np.ix_(ga.perm, ga.perm)] = H.densify(ga.root)
+    y = to_host(p.A.matvec(device_rhs(x), device_rhs(y0), alpha=-0.5, beta=2.0))
+    ref = -0.5 * ah @ x + 2.0 * y0
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_level_and_dataflow_executors_identical():
+    p = Problem(1024, 32, 1e-6, oracle=False)
+    f1 = hm.LU(p.A, hm.make_opts(leaf=32, eta=2.0, eps=1e-6, exec_mode=hm.DATAFLOW))
+    f2 = hm.LU(p.A, hm.make_opts(leaf=32, eta=2.0, eps=1e-6, exec_mode=hm.LEVEL))
+    _, _, _, bl = p.tree.tables()
+    for bi in np.nonzero(bl[:, 2] != 0)[0]:
+        r1, r2 = f1.leaf(int(bi)), f2.leaf(int(bi))
+        assert r1[0] == r2[0]
+        assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
+
+
+def test_edge_sizes():
+    # n = 1, n below the leaf size, ragged leaves
+    for n, leaf in [(1, 32), (5, 32), (100, 32), (257, 16)]:
+        p = Problem(n, leaf, 1e-8, oracle=False)
+        f = hm.LU(p.A, p.opts)
+        b = inputs.rhs(n, 3, seed=2)
+        x = to_host(f.solve(device_rhs(b))[0])
+        dense = p.dense_exact()
+        perm = p.tree.tables()[0]
+        a_user = np.empty_like(dense)
+        a_user[np.ix_(perm, perm)] = dense
+        res = np.linalg.norm(b - a_user @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(res <= 1e-6), (n, res)
