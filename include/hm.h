@@ -77,6 +77,12 @@ typedef struct {
   int max_rank;     /* rank cap, 0 = none (then the capacity 64 bounds it) */
   int prec;         /* hm_precision */
   int exec;         /* hm_exec */
+  int lazy;         /* 0: truncate every update of a low-rank leaf when it is
+                       produced, in the sequential order of Algorithm 1;
+                       1: collect the updates of a low-rank leaf and add them
+                       with a balanced tree of truncations when the leaf is
+                       next read (the accumulator arithmetic of Sec. 2.3,
+                       applied per leaf) */
 } hm_opts;
 
 typedef struct hm_tree_s* hm_tree;
@@ -85,13 +91,13 @@ typedef struct hm_lu_s* hm_lu;
 
 typedef struct {
   int64_t ntasks, nedges, nlevels;
-  int64_t tasks_by_op[10];
+  int64_t tasks_by_op[12];
   int64_t bytes_alg;   /* algorithmic bytes of the executed tasks (run-time ranks) */
   int64_t flops_alg;
   double exec_ms;      /* device time of the executor launch(es), HIP events */
   int64_t temp_bytes;  /* temporaries of the traced DAG */
   int64_t rank_overflows;
-  double op_busy_ms[10];  /* summed workgroup-busy time per task kind (index = task kind) */
+  double op_busy_ms[12];  /* summed workgroup-busy time per task kind (index = task kind) */
   double trunc_phase_ms[6]; /* truncation phases: Gram, Cholesky, core, SVD, solve, rebuild */
   double trunc_mean_k, trunc_mean_mn; /* mean stacked rank K and mean m + n of truncations */
 } hm_lu_stats;
@@ -149,6 +155,12 @@ hm_status hm_footprint(const void* handle, int kind, size_t* bytes);
  * (call with data = NULL first to learn the rank).  Diagonal leaves of
  * factors also fill piv (m int32, LAPACK interchanges, 0-based) if non-NULL. */
 hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* data, int32_t* rank, int32_t* piv);
+
+/* Per-task timeline of the last h_lu on F, recorded only when the
+ * environment variable HM_DEBUG_TRACE=1 was set before h_lu: out (may be
+ * NULL to query sizes) receives ntasks x 3 uint64 (start tick, end tick,
+ * workgroup) in trace order; ticks count at clock_khz kHz. */
+hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz);
 
 /* Statistics of the last h_lu on F. */
 hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out);

@@ -34,6 +34,11 @@ Readings where the paper is silent (each one is listed in the design notes):
       updates with U01, both solves with U11.
   R5  adm(t, s) = dist(t, s) > 0 and min(diam t, diam s) <= eta * dist(t, s)
       with axis-aligned bounding boxes.
+  R6  collected updates (hlu(..., lazy=True)): following the accumulator
+      arithmetic of Sec. 2.3 (hmul as add_upd followed by apply_upd), each
+      top-level hmul call collects the exact low-rank terms it produces for
+      every low-rank leaf and applies them in one truncation,
+      C <- T_eps(C + sum of terms), when it returns.
 
 Parity is pinned in tests/test_oracle_*.py against: scipy's getrf on the same
 leaf block, Eckart-Young for compression, brute-force tiling of the block
@@ -155,6 +160,7 @@ class Block:
     U: np.ndarray | None = None
     V: np.ndarray | None = None
     piv: np.ndarray | None = None  # diagonal dense leaves after hlu
+    pending: list = field(default_factory=list)  # collected updates (Reading R6)
 
     @property
     def rows(self) -> int:
@@ -324,6 +330,7 @@ def assemble(points, perm, clusters, root: Block, diag: float, eps: float, max_r
 # ---------------------------------------------------------------------------
 def hmat_mul(b: Block, x: np.ndarray) -> np.ndarray:
     """B x for a block of any kind; x has b.cols rows."""
+    _use(b)
     if b.kind == "D":
         return b.D @ x
     if b.kind == "R":
@@ -340,6 +347,7 @@ def hmat_mul(b: Block, x: np.ndarray) -> np.ndarray:
 
 def hmat_tmul(b: Block, x: np.ndarray) -> np.ndarray:
     """B^T x for a block of any kind; x has b.rows rows."""
+    _use(b)
     if b.kind == "D":
         return b.D.T @ x
     if b.kind == "R":
@@ -357,6 +365,49 @@ def hmat_tmul(b: Block, x: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Sec. 2.3: truncated low-rank addition
 # ---------------------------------------------------------------------------
+def truncated_add_terms(c: Block, terms: list, eps: float, max_rank: int):
+    """C <- T_eps(U_C V_C^T + sum of zero-padded terms (r0, c0, U_p, V_p)), one truncation."""
+    m, n = c.rows, c.cols
+    kc = c.rank
+    ks = [u.shape[1] for (_, _, u, _) in terms]
+    k = kc + sum(ks)
+    if k == 0:
+        return
+    us = np.zeros((m, k))
+    vs = np.zeros((n, k))
+    if kc:
+        us[:, :kc] = c.U
+        vs[:, :kc] = c.V
+    col = kc
+    for (r0, c0, up, vp) in terms:
+        kp = up.shape[1]
+        us[r0:r0 + up.shape[0], col:col + kp] = up
+        vs[c0:c0 + vp.shape[0], col:col + kp] = vp
+        col += kp
+    qu, ru = np.linalg.qr(us)
+    qv, rv = np.linalg.qr(vs)
+    w, s, zt = np.linalg.svd(ru @ rv.T)
+    kk = truncation_rank(s, eps, max_rank, min(m, n))
+    c.U = qu @ (w[:, :kk] * s[:kk])
+    c.V = qv @ zt[:kk].T
+
+
+class _Mode:
+    """Whether updates of low-rank leaves are collected (Reading R6) during hlu."""
+    lazy = False
+    eps = 0.0
+    max_rank = 0
+    depth = 0          # nesting of hmul calls
+    touched: list = []  # leaves with collected terms in the current top-level call
+
+
+def _use(b: Block) -> None:
+    """Apply the collected updates of a leaf before it is read (Reading R6)."""
+    if b.kind == "R" and b.pending:
+        terms, b.pending = b.pending, []
+        truncated_add_terms(b, terms, _Mode.eps, _Mode.max_rank)
+
+
 def truncated_add(c: Block, r0: int, c0: int, up: np.ndarray, vp: np.ndarray, eps: float, max_rank: int):
     """C <- T_eps(U_C V_C^T + pad(U_p) pad(V_p)^T).
 
@@ -401,6 +452,8 @@ def product_terms(alpha: float, a: Block, b: Block) -> list:
       A dense, B structured (row leaf):  U = alpha I, V = B^T A^T
       A structured, B dense (col leaf):  U = alpha A B, V = I
     """
+    _use(a)
+    _use(b)
     if a.kind == "S" and b.kind == "S":
         out = []
         for i in range(2):
@@ -437,6 +490,11 @@ def _restrict(term, r_lo, r_hi, c_lo, c_hi):
 
 def _add_term_to_leaf(c: Block, term, eps, max_rank):
     r0, c0, u, v = term
+    if c.kind == "R" and _Mode.lazy and _Mode.depth > 0:
+        if not c.pending:
+            _Mode.touched.append(c)
+        c.pending.append(term)
+        return
     if c.kind == "D":
         c.D[r0:r0 + u.shape[0], c0:c0 + v.shape[0]] += u @ v.T
     else:
@@ -460,14 +518,26 @@ def _leaf_update(alpha, a: Block, b: Block, c: Block, eps, max_rank):
 
 
 def hmul(alpha, a: Block, b: Block, c: Block, eps, max_rank):
-    """Algorithm 1: C := C + alpha A B; recurse while none of the three blocks is a leaf."""
-    if a.kind == "S" and b.kind == "S" and c.kind == "S":
-        for i in range(2):
-            for j in range(2):
-                for l in range(2):
-                    hmul(alpha, a.sons[i][l], b.sons[l][j], c.sons[i][j], eps, max_rank)
-    else:
-        _leaf_update(alpha, a, b, c, eps, max_rank)
+    """Algorithm 1: C := C + alpha A B; recurse while none of the three blocks is a leaf.
+
+    With collected updates (Reading R6) the outermost call applies the terms
+    it collected for each low-rank leaf when it returns."""
+    top = _Mode.depth == 0
+    _Mode.depth += 1
+    try:
+        if a.kind == "S" and b.kind == "S" and c.kind == "S":
+            for i in range(2):
+                for j in range(2):
+                    for l in range(2):
+                        hmul(alpha, a.sons[i][l], b.sons[l][j], c.sons[i][j], eps, max_rank)
+        else:
+            _leaf_update(alpha, a, b, c, eps, max_rank)
+    finally:
+        _Mode.depth -= 1
+    if top:
+        leaves, _Mode.touched = _Mode.touched, []
+        for x in leaves:
+            _use(x)
 
 
 # ---------------------------------------------------------------------------
@@ -541,6 +611,7 @@ def panel_solve_upper(d: Block, x: np.ndarray) -> None:
 
 def htrsl(ld: Block, m: Block, eps, max_rank):
     """Algorithm 3: L X = M for M on rows of ld; X overwrites M."""
+    _use(m)
     if m.kind == "S":
         for j in range(2):
             htrsl(ld.sons[0][0], m.sons[0][j], eps, max_rank)
@@ -556,6 +627,7 @@ def htrsl(ld: Block, m: Block, eps, max_rank):
 
 def htrsu(ud: Block, m: Block, eps, max_rank):
     """Mirror of Algorithm 3 (Reading R4): X U = M for M on columns of ud; X overwrites M."""
+    _use(m)
     if m.kind == "S":
         for j in range(2):
             htrsu(ud.sons[0][0], m.sons[j][0], eps, max_rank)
@@ -594,12 +666,20 @@ def _copy_block(b: Block) -> Block:
     return c
 
 
-def hlu(a: HMatrix, eps: float | None = None, max_rank: int | None = None) -> HMatrix:
-    """H-LU of a copy of ``a`` (Algorithm 2); the input is not modified."""
+def hlu(a: HMatrix, eps: float | None = None, max_rank: int | None = None, lazy: bool = False) -> HMatrix:
+    """H-LU of a copy of ``a`` (Algorithm 2); the input is not modified.
+
+    lazy=True collects the updates of low-rank leaves (Reading R6)."""
     eps = a.eps if eps is None else eps
     max_rank = a.max_rank if max_rank is None else max_rank
     f = HMatrix(_copy_block(a.root), a.perm, a.clusters, a.n, eps, max_rank)
-    _hlu_rec(f.root, eps, max_rank)
+    _Mode.lazy, _Mode.eps, _Mode.max_rank, _Mode.depth, _Mode.touched = lazy, eps, max_rank, 0, []
+    try:
+        _hlu_rec(f.root, eps, max_rank)
+        for b in leaf_blocks(f.root):
+            _use(b)
+    finally:
+        _Mode.lazy = False
     return f
 
 

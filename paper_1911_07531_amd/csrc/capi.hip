@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -142,7 +143,7 @@ struct PlanEntry {
 struct hm_tree_s {
   Tree t;
   hm_opts opts;
-  std::map<std::pair<int, int>, std::unique_ptr<PlanEntry>> plans;  // (prec, max_rank)
+  std::map<std::tuple<int, int, int>, std::unique_ptr<PlanEntry>> plans;  // (prec, max_rank, lazy)
   std::mutex mu;
   std::vector<int64_t> leaf_begin;  // leaf clusters in order
   std::vector<int32_t> leaf_size;
@@ -166,7 +167,7 @@ struct hm_matrix_s {
 };
 
 struct ExecState {
-  DevBuf deps, queue, qctl, status, counters;
+  DevBuf deps, queue, qctl, status, counters, trace;
 };
 
 struct hm_lu_s {
@@ -219,11 +220,18 @@ static const int64_t kScratchPerWg = kScratchDoubles;
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
-static const int64_t kTempBudget = int64_t(4) << 30;
+// Device bytes the ring of temporaries of one traced DAG may span (per size
+// class an eighth); a larger ring means fewer orderings from reuse.
+// HM_TEMP_BUDGET_GB overrides it.
+static int64_t temp_budget() {
+  int64_t gb = 16;
+  if (const char* e = getenv("HM_TEMP_BUDGET_GB")) gb = std::max(1, atoi(e));
+  return gb << 30;
+}
 
-static hm_status get_plan(hm_tree t, int prec, int max_rank, bool need_trace, PlanEntry** out) {
+static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out) {
   std::lock_guard<std::mutex> lk(t->mu);
-  auto key = std::make_pair(prec, max_rank);
+  auto key = std::make_tuple(prec, max_rank, lazy);
   auto it = t->plans.find(key);
   PlanEntry* pe;
   if (it == t->plans.end()) {
@@ -235,7 +243,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, bool need_trace, Pl
     pe = it->second.get();
   }
   if (need_trace && !pe->traced) {
-    if (!trace_lu(pe->plan, kTempBudget)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_lu(pe->plan, temp_budget(), lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
     if (!trace_solve(pe->plan)) return fail(HM_EINVAL, pe->plan.err);
     pe->traced = true;
   }
@@ -273,12 +281,13 @@ static hm_status ensure_uploaded(PlanEntry* pe, hipStream_t s) {
 static hm_status exec_state_alloc(ExecState& es, int64_t ntasks, hipStream_t s) {
   if (!dev_alloc(es.deps, std::max<int64_t>(1, ntasks) * 4, s) ||
       !dev_alloc(es.queue, std::max<int64_t>(1, ntasks) * 4, s) || !dev_alloc(es.qctl, 64, s) ||
-      !dev_alloc(es.status, 64, s) || !dev_alloc(es.counters, 32 * 8, s))
+      !dev_alloc(es.status, 64, s) || !dev_alloc(es.counters, kCtrSize * 8, s))
     return fail(HM_ENOMEM, "device allocation failed (executor state)");
   return HM_OK;
 }
 
 static void exec_state_free(ExecState& es) {
+  dev_free(es.trace);
   dev_free(es.deps);
   dev_free(es.queue);
   dev_free(es.qctl);
@@ -301,10 +310,11 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.qctl = (int32_t*)es.qctl.p;
   a.status = (int32_t*)es.status.p;
   a.counters = (unsigned long long*)es.counters.p;
+  a.trace = (uint64_t*)es.trace.p;
   a.nwg = g_nwg;
   a.spin_limit = g_clock_khz * 1000 * 30;  // 30 s of wall clock
   hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
-  HIPCHK(hipMemsetAsync(es.counters.p, 0, 32 * 8, s));
+  HIPCHK(hipMemsetAsync(es.counters.p, 0, kCtrSize * 8, s));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -353,7 +363,8 @@ static ExecArgs base_args(double* f64, float* f32, int32_t* piv, int32_t* ranks,
 
 static bool valid_opts(const hm_opts* o) {
   return o && o->leaf >= 1 && o->eta > 0 && o->eps >= 0 && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
-         (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL);
+         (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL) &&
+         (o->lazy == 0 || o->lazy == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +462,7 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
   if (!t || !opts || !sizes || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
   if (opts->max_rank < 0 || opts->max_rank > kMaxCap) return fail(HM_EINVAL, "max_rank must be in [0, 64]");
   PlanEntry* pe;
-  hm_status st = get_plan(t, opts->prec, opts->max_rank, true, &pe);
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
   if (st) return st;
   const Dag& d = which == 0 ? pe->plan.lu : pe->plan.solve;
   sizes[0] = (int64_t)d.tasks.size();
@@ -470,7 +481,7 @@ hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, 
                         int32_t* level, int64_t* block_off, int64_t* lr) {
   if (!t || !opts || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
   PlanEntry* pe;
-  hm_status st = get_plan(t, opts->prec, opts->max_rank, true, &pe);
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
   if (st) return st;
   const Plan& p = pe->plan;
   const Dag& d = which == 0 ? p.lu : p.solve;
@@ -506,7 +517,7 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   PlanEntry* pe;
-  if ((st = get_plan(t, HM_FP64, opts->max_rank, false, &pe))) return st;
+  if ((st = get_plan(t, HM_FP64, opts->max_rank, 0, false, &pe))) return st;
   const Plan& p = pe->plan;
   const Tree& tr = t->t;
   auto A = std::make_unique<hm_matrix_s>();
@@ -517,10 +528,10 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
   A->eps = opts->eps;
   A->max_rank = opts->max_rank;
   // A's arena: blocks only (no temporaries, no panel)
-  if (!dev_alloc(A->f64, p.blocks_f64 * 8, s) || !dev_alloc(A->ranks, p.nranks * 4, s) ||
+  if (!dev_alloc(A->f64, p.blocks_f64 * 8, s) || !dev_alloc(A->ranks, ((size_t)p.nlr_leaf + 1) * 4, s) ||
       !dev_alloc(A->status, 64, s))
     return fail(HM_ENOMEM, "device allocation failed (matrix)");
-  HIPCHK(hipMemsetAsync(A->ranks.p, 0, p.nranks * 4, s));
+  HIPCHK(hipMemsetAsync(A->ranks.p, 0, ((size_t)p.nlr_leaf + 1) * 4, s));
   HIPCHK(hipMemsetAsync(A->status.p, 0, 64, s));
   if ((st = upload(A->pts, tr.pts_perm, s))) return st;
   if ((st = upload(A->perm, tr.perm, s))) return st;
@@ -707,7 +718,7 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   hipStream_t s = (hipStream_t)stream;
   hm_tree t = A->tree;
   PlanEntry* pe;
-  if ((st = get_plan(t, opts->prec, opts->max_rank, true, &pe))) return st;
+  if ((st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe))) return st;
   if ((st = ensure_uploaded(pe, s))) return st;
   const Plan& p = pe->plan;
   const Plan& pa = A->pe->plan;
@@ -724,9 +735,14 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
     return fail(HM_ENOMEM, "device allocation failed (factors)");
   if ((st = upload(F->perm, t->t.perm, s))) return st;
   if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
+  // HM_DEBUG_TRACE=1 records (start, end, workgroup) of every H-LU task
+  if (const char* e = getenv("HM_DEBUG_TRACE"))
+    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * 24, s))
+      return fail(HM_ENOMEM, "device allocation failed (trace)");
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
   // copy A into the factor layout
-  HIPCHK(hipMemcpyAsync(F->ranks.p, A->ranks.p, p.nranks * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(F->ranks.p, 0, p.nranks * 4, s));
+  HIPCHK(hipMemcpyAsync(F->ranks.p, A->ranks.p, (size_t)p.nlr_leaf * 4, hipMemcpyDeviceToDevice, s));
   if (opts->prec == HM_FP64) {
     HIPCHK(hipMemcpyAsync(F->f64.p, A->f64.p, pa.blocks_f64 * 8, hipMemcpyDeviceToDevice, s));
   } else {
@@ -765,19 +781,19 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   HIPCHK(hipStreamSynchronize(s));
   dev_free(scratch);
   int32_t stv[4];
-  unsigned long long ctr[32];
+  unsigned long long ctr[kCtrSize];
   HIPCHK(hipMemcpy(stv, F->lu_st.status.p, 16, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(ctr, F->lu_st.counters.p, sizeof(ctr), hipMemcpyDeviceToHost));
-  for (int k = 0; k < 10; ++k) F->stats.op_busy_ms[k] = (double)ctr[2 + k] / (double)g_clock_khz;
-  for (int k = 0; k < 6; ++k) F->stats.trunc_phase_ms[k] = (double)ctr[22 + k] / (double)g_clock_khz;
-  double ntr = (double)std::max<unsigned long long>(1, ctr[12 + OP_TRUNC]);
-  F->stats.trunc_mean_k = ctr[28] / ntr;
-  F->stats.trunc_mean_mn = ctr[29] / ntr;
+  for (int k = 0; k < OP_COUNT; ++k) F->stats.op_busy_ms[k] = (double)ctr[kCtrBusy + k] / (double)g_clock_khz;
+  for (int k = 0; k < 6; ++k) F->stats.trunc_phase_ms[k] = (double)ctr[kCtrPhase + k] / (double)g_clock_khz;
+  double ntr = (double)std::max<unsigned long long>(1, ctr[kCtrCount + OP_TRUNC] + ctr[kCtrCount + OP_TRUNC2]);
+  F->stats.trunc_mean_k = ctr[kCtrK] / ntr;
+  F->stats.trunc_mean_mn = ctr[kCtrMN] / ntr;
   F->stats.ntasks = pe->lu.ntasks;
   F->stats.nedges = pe->lu.nedges;
   F->stats.nlevels = pe->lu.nlevels;
   for (const Task& tk : p.lu.tasks)
-    if (tk.op >= 0 && tk.op < 10) F->stats.tasks_by_op[tk.op]++;
+    if (tk.op >= 0 && tk.op < OP_COUNT) F->stats.tasks_by_op[tk.op]++;
   F->stats.bytes_alg = (int64_t)ctr[0];
   F->stats.flops_alg = (int64_t)ctr[1];
   F->stats.exec_ms = ms;
@@ -802,6 +818,16 @@ void hm_lu_free(hm_lu F) {
   exec_state_free(F->lu_st);
   exec_state_free(F->solve_st);
   delete F;
+}
+
+hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz) {
+  if (!F) return fail(HM_EINVAL, "null pointer");
+  if (ntasks) *ntasks = F->pe->lu.ntasks;
+  if (clock_khz) *clock_khz = g_clock_khz;
+  if (!out) return HM_OK;
+  if (!F->lu_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
+  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * 24, hipMemcpyDeviceToHost));
+  return HM_OK;
 }
 
 hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out) {

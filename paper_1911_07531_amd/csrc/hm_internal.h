@@ -17,7 +17,10 @@ constexpr int kMaxK = 128;         // widest stacked rank in a truncated additio
 constexpr int kMaxCap = 64;        // widest stored rank of a low-rank leaf
 constexpr int kMaxLeaf = 128;      // largest diagonal leaf the getrf/trsm kernels take
 constexpr int kLdsBytes = 76 * 1024;  // dynamic LDS per workgroup (two workgroups per CU)
-constexpr int kNrhsSlotOffset = 0; // rank slot that carries the current nrhs of a solve
+// Relative accuracy of the inner truncations that combine collected updates
+// (in units of eps): tighter than the final one so that their rounding of the
+// partial sums stays below the final truncation threshold.
+constexpr double kInnerEps = 0.1;
 
 enum ViewType : int32_t { VT_F64 = 0, VT_F32 = 1, VT_IDENT = 2, VT_NONE = 3 };
 enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2 };
@@ -46,14 +49,16 @@ enum Op : int32_t {
   OP_TRUNC = 7,    // low-rank leaf lr <- T_eps(U V^T + alpha pad(a) pad(b)^T)
   OP_ZERO = 8,     // y <- 0
   OP_COPY = 9,     // y <- a (element type conversion allowed)
+  OP_TRUNC2 = 10,  // accumulator lr <- T_eps(alpha pad(a) pad(b)^T + beta pad(x) pad(y)^T)
+  OP_COUNT = 11,
 };
 
 struct Task {
   int32_t op;
-  int32_t lr;        // OP_TRUNC: low-rank leaf index
-  int32_t r0, c0;    // OP_TRUNC: offsets of the term inside the leaf
-  int32_t row0;      // OP_GETRF: first permuted row of the leaf (error report)
-  int32_t pad_;
+  int32_t lr;        // OP_TRUNC / OP_TRUNC2: low-rank leaf or accumulator index
+  int32_t r0, c0;    // OP_TRUNC / OP_TRUNC2: offsets of the (first) term inside the target
+  int32_t row0;      // OP_GETRF: first permuted row of the leaf; OP_TRUNC2: row offset of the second term
+  int32_t c1;        // OP_TRUNC2: column offset of the second term
   int64_t piv;       // OP_GETRF / OP_TRSM_L: offset into the int32 pivot arena
   double alpha, beta;
   View y, a, b, x;
@@ -89,10 +94,12 @@ struct ExecArgs {
   int32_t* queue;      // ready queue (ntasks slots, -1 = empty)
   int32_t* qctl;       // [0] head, [1] tail, [2] done, [3] abort
   int64_t spin_limit;  // wall-clock ticks a waiting workgroup polls before giving up
-  // [0] algorithmic bytes, [1] algorithmic flops, [2 + op] busy wall-clock ticks
-  // of each task kind, [12 + op] task count, [22..27] ticks of the truncation
-  // phases, [28] sum of stacked ranks K, [29] sum of m + n (null: off)
+  // [0] algorithmic bytes, [1] algorithmic flops, [kCtrBusy + op] busy
+  // wall-clock ticks of each task kind, [kCtrCount + op] task count,
+  // [kCtrPhase ..+5] ticks of the truncation phases, [kCtrK] sum of stacked
+  // ranks K, [kCtrMN] sum of m + n (null: off)
   unsigned long long* counters;
+  uint64_t* trace;  // optional: per task (start tick, end tick, workgroup)
 };
 
 
@@ -127,6 +134,9 @@ struct CopyDesc {
 };
 
 constexpr int64_t kScratchDoubles = 4 * kMaxK * kMaxK + 4 * kMaxK * kMaxCap + 6 * kMaxK + 64;
+
+constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COUNT, kCtrK = kCtrPhase + 6,
+              kCtrMN = kCtrK + 1, kCtrSize = kCtrMN + 1;
 
 enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4 };
 

@@ -210,6 +210,7 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p) {
   p.n_f64 = p.panel_off + t.n * (int64_t)nrhs_cap;
   p.n_f32 = p.blocks_f32;
   p.n_piv = piv;
+  p.nlr_leaf = (int)p.lr.size();
   p.nrhs_slot = (int)p.lr.size();
   p.nranks = p.nrhs_slot + 1;
   return true;
@@ -237,6 +238,7 @@ struct HView {
   int obj;
   Rect rect;
   bool tr;
+  int32_t pool_cls = -1, pool_slot = -1;  // temporaries: ring slot
 };
 
 struct Term {
@@ -269,8 +271,14 @@ class Tracer {
       if (t_.bl[b].kind == BK_LOWRANK) {
         obj_a_[b] = new_obj();
         obj_b_[b] = new_obj();
+        owner_[obj_a_[b]] = (int)b;
+        owner_[obj_b_[b]] = (int)b;
       }
     }
+    lr_obj_.assign(p.lr.size(), {-1, -1});
+    for (size_t i = 0; i < p.lr_block.size(); ++i)
+      if (p.lr_block[i] >= 0) lr_obj_[i] = {obj_a_[p.lr_block[i]], obj_b_[p.lr_block[i]]};
+    pending_.resize(nb);
     temp_base_ = p.prec == 1 ? p.blocks_f32 : p.n_f64;
     temp_top_ = temp_base_;
   }
@@ -361,12 +369,19 @@ class Tracer {
     if ((int)pools_.size() <= cls) pools_.resize(cls + 1);
     Pool& pool = pools_[cls];
     if (pool.limit == 0) pool.limit = std::max<int64_t>(64, std::min<int64_t>(1 << 16, temp_budget_ / 8 / sz));
-    int64_t slot = pool.next % pool.limit;
-    pool.next++;
-    if (slot >= (int64_t)pool.off.size()) {
+    // next slot of the ring that no collected update still refers to
+    int64_t slot = 0;
+    for (int64_t tries = 0;; ++tries) {
+      if (tries >= pool.limit) pool.limit *= 2;
+      slot = pool.next % pool.limit;
+      pool.next++;
+      if (slot >= (int64_t)pool.off.size() || pool.pins[slot] == 0) break;
+    }
+    while (slot >= (int64_t)pool.off.size()) {
       temp_top_ = align_up(temp_top_, 32);
       pool.off.push_back(temp_top_);
       pool.obj.push_back(new_obj());
+      pool.pins.push_back(0);
       temp_top_ += sz;
     }
     HView h;
@@ -374,6 +389,8 @@ class Tracer {
     h.obj = pool.obj[slot];
     h.rect = Rect{0, r, 0, cols};
     h.tr = false;
+    h.pool_cls = cls;
+    h.pool_slot = (int32_t)slot;
     return h;
   }
   HView panel() {
@@ -388,18 +405,25 @@ class Tracer {
 
   // ---- task emission with dependency tracking (Def. 3.2 + WAR/WAW) -----------
   void emit(Task tk, std::initializer_list<std::pair<const HView*, int>> acc) {
+    // a low-rank leaf with collected updates gets them applied before any
+    // other task touches it
+    for (auto& a : acc)
+      if (a.first->obj >= 0) {
+        int b = owner_[a.first->obj];
+        if (b >= 0 && !pending_[b].empty()) flush(b);
+      }
     int id = (int)d_.tasks.size();
     d_.tasks.push_back(tk);
     preds_.clear();
-    // A view whose extent follows a low-rank leaf's rank must be ordered after
-    // the truncations that set that rank: the task must also access the leaf's
-    // U or V factor (a truncation rewrites both together with the rank).
+    // A view whose extent follows a rank must be ordered after the truncation
+    // that set it: the task must also access that low-rank leaf's (or
+    // accumulator's) U or V storage, which the truncation rewrites.
     for (auto& a : acc) {
       const View& v = a.first->v;
-      if (!v.dyn || v.rank_id < 0 || v.rank_id >= (int)p_.lr_block.size()) continue;
-      int b = p_.lr_block[v.rank_id];
+      if (!v.dyn || v.rank_id < 0 || v.rank_id >= (int)lr_obj_.size()) continue;
+      auto ob = lr_obj_[v.rank_id];
       bool backed = false;
-      for (auto& c : acc) backed |= c.first->obj == obj_a_[b] || c.first->obj == obj_b_[b];
+      for (auto& c : acc) backed |= c.first->obj == ob.first || c.first->obj == ob.second;
       if (!backed) fail("internal: a run-time extent follows a rank the task does not read");
     }
     for (auto& a : acc)
@@ -664,6 +688,13 @@ class Tracer {
 
   void add_term_to_leaf(int c, const Term& tm) {
     const BlockNode& C = t_.bl[c];
+    if (C.kind == BK_LOWRANK && lazy_ && scope_ > 0) {
+      pin(tm.u, 1);
+      pin(tm.v, 1);
+      if (pending_[c].empty()) touched_.push_back(c);
+      pending_[c].push_back(tm);
+      return;
+    }
     if (C.kind == BK_DENSE) {
       HView y = dense(c);
       HView ys = rows(y, tm.r0, tm.r0 + tm.u.v.rows);
@@ -707,8 +738,93 @@ class Tracer {
     visit(c);
   }
 
-  // Algorithm 1
+  // New accumulator: a low-rank buffer with the target's shape and capacity,
+  // its own rank slot, storage from the temporaries.
+  int new_accumulator(int c, HView& u, HView& v) {
+    const LrDesc& dc = p_.lr[p_.lr_index[c]];
+    int li = (int)p_.lr.size();
+    u = temp(dc.m, dc.cap, -1);
+    v = temp(dc.n, dc.cap, -1);
+    LrDesc d;
+    d.u_off = u.v.off;
+    d.v_off = v.v.off;
+    d.m = dc.m;
+    d.n = dc.n;
+    d.cap = dc.cap;
+    d.type = temp_type_;
+    p_.lr.push_back(d);
+    p_.lr_block.push_back(-1);
+    lr_obj_.push_back({u.obj, v.obj});
+    u.v.dyn = v.v.dyn = DYN_COLS;
+    u.v.rank_id = v.v.rank_id = li;
+    return li;
+  }
+  // acc <- T(t1 + t2), returned as a term
+  Term combine(int c, const Term& t1, const Term& t2) {
+    HView u, v;
+    int li = new_accumulator(c, u, v);
+    int kb = t1.u.v.cols + t2.u.v.cols;
+    if (kb > kMaxK) fail("stacked rank above 128 in a combined truncation");
+    Task t = blank(OP_TRUNC2);
+    t.lr = li;
+    t.a = t1.u.v;
+    t.b = t1.v.v;
+    t.r0 = t1.r0;
+    t.c0 = t1.c0;
+    t.alpha = t1.alpha;
+    t.x = t2.u.v;
+    t.y = t2.v.v;
+    t.row0 = t2.r0;
+    t.c1 = t2.c0;
+    t.beta = t2.alpha;
+    emit(t, {{&t1.u, ACC_R}, {&t1.v, ACC_R}, {&t2.u, ACC_R}, {&t2.v, ACC_R}, {&u, ACC_W}, {&v, ACC_W}});
+    Term r;
+    r.u = u;
+    r.v = v;
+    r.r0 = r.c0 = 0;
+    r.alpha = 1.0;
+    pin(u, 1);
+    pin(v, 1);
+    return r;
+  }
+  // Apply the collected updates of low-rank leaf c: pairwise truncated
+  // additions in a balanced tree, then one truncated addition into c.
+  void flush(int c) {
+    std::vector<Term> terms;
+    terms.swap(pending_[c]);
+    std::vector<Term> made;
+    std::vector<Term> level = terms;
+    while (level.size() > 1) {
+      std::vector<Term> next;
+      for (size_t i = 0; i + 1 < level.size(); i += 2) {
+        next.push_back(combine(c, level[i], level[i + 1]));
+        made.push_back(next.back());
+      }
+      if (level.size() % 2) next.push_back(level.back());
+      level.swap(next);
+    }
+    if (!level.empty()) trunc(c, level[0]);
+    for (auto& tm : terms) {
+      pin(tm.u, -1);
+      pin(tm.v, -1);
+    }
+    for (auto& tm : made) {
+      pin(tm.u, -1);
+      pin(tm.v, -1);
+    }
+  }
+  void flush_all() {
+    for (size_t b = 0; b < pending_.size(); ++b)
+      if (!pending_[b].empty()) flush((int)b);
+  }
+  void set_lazy(bool v) { lazy_ = v; }
+
+  // Algorithm 1.  With lazy updates a top-level call collects the updates it
+  // makes to each low-rank leaf and applies them when it returns (hmul as
+  // add_upd followed by apply_upd, Sec. 2.3).
   void hmul(double alpha, int a, int b, int c) {
+    const bool top = scope_ == 0;
+    ++scope_;
     const BlockNode& A = t_.bl[a];
     const BlockNode& B = t_.bl[b];
     const BlockNode& C = t_.bl[c];
@@ -718,6 +834,13 @@ class Tracer {
           for (int l = 0; l < 2; ++l) hmul(alpha, A.son[2 * i + l], B.son[2 * l + j], C.son[2 * i + j]);
     } else {
       leaf_update(alpha, a, b, c);
+    }
+    --scope_;
+    if (top) {
+      std::vector<int> leaves;
+      leaves.swap(touched_);
+      for (int x : leaves)
+        if (!pending_[x].empty()) flush(x);
     }
   }
 
@@ -811,9 +934,14 @@ class Tracer {
     int64_t next = 0;
     std::vector<int64_t> off;
     std::vector<int> obj;
+    std::vector<int> pins;  // collected updates still referring to the slot
   };
+  void pin(const HView& h, int d) {
+    if (h.pool_cls >= 0) pools_[h.pool_cls].pins[h.pool_slot] += d;
+  }
   int new_obj() {
     objs_.emplace_back();
+    owner_.push_back(-1);
     return (int)objs_.size() - 1;
   }
   void access(int task, int obj, const Rect& r, bool write) {
@@ -843,6 +971,12 @@ class Tracer {
   int panel_obj_ = -1;
   std::vector<int> obj_a_, obj_b_;
   std::vector<ObjState> objs_;
+  std::vector<int> owner_;                     // low-rank leaf owning an object, or -1
+  std::vector<std::pair<int, int>> lr_obj_;    // U / V objects of every low-rank index
+  std::vector<std::vector<Term>> pending_;     // collected updates per low-rank leaf
+  std::vector<int> touched_;                   // leaves with collected updates in this call
+  int scope_ = 0;                              // depth of nested hmul calls
+  bool lazy_ = false;
   std::vector<Pool> pools_;
   std::vector<int> preds_;
   std::vector<std::pair<int, int>> edges_;
@@ -851,15 +985,21 @@ class Tracer {
 
 }  // namespace
 
-bool trace_lu(Plan& p, int64_t temp_budget_bytes) {
+bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
   p.lu = Dag();
+  p.lr.resize(p.nlr_leaf);
+  p.lr_block.resize(p.nlr_leaf);
   Tracer tr(p, p.lu, temp_budget_bytes);
+  tr.set_lazy(lazy);
   tr.hlu(0);
+  tr.flush_all();
   if (!tr.ok()) {
     p.err = tr.err();
     return false;
   }
   tr.finish();
+  p.nrhs_slot = (int)p.lr.size();
+  p.nranks = p.nrhs_slot + 1;
   int64_t end = tr.temp_end();
   if (p.prec == 1) {
     p.temp_bytes = (end - p.blocks_f32) * 4;

@@ -68,8 +68,9 @@ struct Plan {
   int64_t n_f64 = 0, n_f32 = 0, n_piv = 0;
   int64_t blocks_f64 = 0, blocks_f32 = 0;  // arena prefix that holds block data
   int64_t panel_off = -1;  // solve panel (f64 arena), n x nrhs_cap
-  int nranks = 0;          // rank slots (low-rank leaves + nrhs slot)
+  int nranks = 0;          // rank slots (low-rank leaves, accumulators, nrhs slot)
   int nrhs_slot = 0;
+  int nlr_leaf = 0;        // low-rank leaves (the first entries of lr); the rest are accumulators
   Dag lu, solve;
   int64_t temp_bytes = 0;
   std::string err;
@@ -79,7 +80,9 @@ struct Plan {
 // leaves FP64, all other blocks FP32.
 bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
 // Trace the H-LU (Algorithm 2) and the forward/backward solve into task DAGs.
-bool trace_lu(Plan& p, int64_t temp_budget_bytes);
+// lazy: collect the updates of each low-rank leaf and add them with a balanced
+// tree of truncations when the leaf is next read (accumulator arithmetic).
+bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy);
 bool trace_solve(Plan& p);
 
 }  // namespace hm

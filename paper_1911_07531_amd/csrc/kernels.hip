@@ -104,7 +104,7 @@ __device__ void gemm_tiles(int m, int n, int k, LA la, LB lb, ST st, bool a_kcon
           sB[kk * (TN + TP) + jj] = (gj < n && gk < k) ? (CT)lb(gk, gj) : CT(0);
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 2
         for (int kk = 0; kk < TK; ++kk) {
           CT av[4], bv[4];
 #pragma unroll
@@ -363,18 +363,26 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
 // in FP64, and the kept singular triplets are written back as
 //   U <- U_s T_U,  V <- V_s T_V   (Sigma folded into U).
 // ---------------------------------------------------------------------------
-struct Stack {  // one side of the stack: rows [0, m), columns [0, kc) from C and
-  RV c;         // columns [kc, kc+kp) from the term (rows offset by r0, zero outside)
-  RV t;
-  const double* tptr;  // term factor outside the arenas (column-major, ld t.cs), or null
-  int m, kc, kp, r0;
-  double alpha;
+struct Stack {  // one side of the stack: rows [0, m); columns [0, kc) from C, then
+  RV c;         // [kc, kc+kp) from term 1 (rows offset by r0, zero outside), then
+  RV t;         // [kc+kp, kc+kp+kp2) from term 2 (rows offset by r2)
+  RV t2;
+  const double* tptr;  // term 1 outside the arenas (column-major, ld t.cs), or null
+  int m, kc, kp, r0, kp2, r2;
+  double alpha, alpha2;
   __device__ __forceinline__ double operator()(const ExecArgs& a, int r, int i) const {
     if (i < kc) return vld(a, c, r, i);
-    int rr = r - r0;
-    if (rr < 0 || rr >= t.rows) return 0.0;
-    if (tptr) return alpha * tptr[rr + (int64_t)(i - kc) * t.cs];
-    return alpha * vld(a, t, rr, i - kc);
+    i -= kc;
+    if (i < kp) {
+      int rr = r - r0;
+      if (rr < 0 || rr >= t.rows) return 0.0;
+      if (tptr) return alpha * tptr[rr + (int64_t)i * t.cs];
+      return alpha * vld(a, t, rr, i);
+    }
+    i -= kp;
+    int rr = r - r2;
+    if (rr < 0 || rr >= t2.rows) return 0.0;
+    return alpha2 * vld(a, t2, rr, i);
   }
 };
 
@@ -505,7 +513,7 @@ __device__ TruncScratch trunc_scratch(double* p) {
 // One-sided Jacobi (Hestenes) on B (p x q, column-major, ld p): orthogonalise the
 // columns; Z (q x q, column-major) accumulates the rotations.  Round-robin
 // pairing, all pairs of a round in parallel.
-__device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag) {
+__device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, double eps) {
   const int tid = threadIdx.x;
   for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   __syncthreads();
@@ -515,8 +523,24 @@ __device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag) {
   int tpp = 1;
   while (tpp * 2 * npairs <= (int)blockDim.x && tpp < 64) tpp *= 2;
   const int pair = tid / tpp, lane = tid % tpp;
-  const double tol = 4e-15;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  // columns count as orthogonal once |x.y| <= tol ||x|| ||y||, with tol at the
+  // rounding level of a length-p dot product (a tighter test never settles);
+  // columns below the noise level (u ||B||_F)^2 count as converged
+  const double tol = fmax(2.0 * (p > 16 ? p : 16) * 2.220446049250313e-16, 1e-4 * eps);
+  if (tid == 0) s_flag[1] = 0;
+  __syncthreads();
+  double* fro_s = (double*)(s_flag + 2);
+  if (tid == 0) *fro_s = 0.0;
+  __syncthreads();
+  {
+    double f = 0.0;
+    for (int e = tid; e < p * q; e += blockDim.x) f += B[e] * B[e];
+    for (int off = 32; off >= 1; off >>= 1) f += __shfl_xor(f, off);
+    if ((tid & 63) == 0) atomicAdd(fro_s, f);
+  }
+  __syncthreads();
+  const double tiny = *fro_s * fmax(1e-4 * eps * eps, 4.930380657631324e-32 * (p > 16 ? p : 16));
+  for (int sweep = 0; sweep < 30; ++sweep) {
     if (tid == 0) s_flag[0] = 0;
     __syncthreads();
     for (int rnd = 0; rnd < N - 1; ++rnd) {
@@ -545,7 +569,7 @@ __device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag) {
         be += __shfl_xor(be, off);
         ga += __shfl_xor(ga, off);
       }
-      if (ci >= 0 && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
         if (lane == 0) s_flag[0] = 1;
         double zeta = (be - al) / (2.0 * ga);
         double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -591,11 +615,368 @@ __device__ __forceinline__ void phase_tick(const ExecArgs& a, int slot, uint64_t
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Truncation for stacked ranks K <= 32: every K x K work matrix in LDS, the
+// two Cholesky factorisations and the Jacobi SVD each run inside one
+// wavefront (no workgroup barrier per step), the Gram matrices and the
+// rebuild stream the factor panels with many loads in flight.
+// ---------------------------------------------------------------------------
+constexpr int kSmallK = 32;
+
+// Wavefront-level ordering of LDS accesses (all lanes of a wavefront).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// G = X^T X (K x K, row-major) for X = the stacked panel st (m x K), staged
+// through LDS in chunks of up to `cap_rows` rows.
+__device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, double* G, double* buf, int cap_rows) {
+  const int tid = threadIdx.x;
+  const int ld = cap_rows | 1;  // odd stride: conflict-free column reads
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // K*K <= 1024 entries: at most 4 per thread
+  for (int r0 = 0; r0 < m; r0 += cap_rows) {
+    const int rows = min(cap_rows, m - r0);
+    for (int e = tid; e < rows * K; e += blockDim.x) {
+      int i = e % rows, c = e / rows;
+      buf[c * ld + i] = st(a, r0 + i, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      if (e < K * K) {
+        const double* xi = buf + (e / K) * ld;
+        const double* xj = buf + (e % K) * ld;
+        double s = 0.0;
+        for (int t = 0; t < rows; ++t) s += xi[t] * xj[t];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * 256;
+    if (e < K * K) G[e] = acc[q];
+  }
+}
+
+// Scaled, diagonally pivoted Cholesky of G (K x K, K <= 64) by the calling
+// wavefront alone; same results as pivoted_cholesky.  Returns the rank.
+__device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
+  const int lane = threadIdx.x & 63;
+  if (lane < K) {
+    double d = G[lane * K + lane];
+    dsc[lane] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    perm[lane] = lane;
+  }
+  wave_sync();
+  for (int e = lane; e < K * K; e += 64) G[e] *= dsc[e / K] * dsc[e % K];
+  wave_sync();
+  const double tol = 8.0 * K * 2.220446049250313e-16;
+  for (int s = 0; s < K; ++s) {
+    double best = -1.0;
+    int bi = K;
+    if (lane >= s && lane < K) {
+      best = G[lane * K + lane];
+      bi = lane;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      double ob = __shfl_xor(best, off);
+      int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (bi >= K || !(best > tol)) return s;
+    const int p = bi;
+    if (p != s) {
+      if (lane < K) {  // swap rows s and p
+        double x = G[s * K + lane];
+        G[s * K + lane] = G[p * K + lane];
+        G[p * K + lane] = x;
+      }
+      wave_sync();
+      if (lane < K) {  // swap columns s and p
+        double x = G[lane * K + s];
+        G[lane * K + s] = G[lane * K + p];
+        G[lane * K + p] = x;
+      }
+      if (lane == 0) {
+        int x = perm[s];
+        perm[s] = perm[p];
+        perm[p] = x;
+      }
+      wave_sync();
+    }
+    const double d = sqrt(G[s * K + s]);
+    wave_sync();
+    if (lane >= s && lane < K) G[s * K + lane] = (lane == s) ? d : G[s * K + lane] / d;
+    wave_sync();
+    const int rem = K - s - 1;
+    for (int e = lane; e < rem * rem; e += 64) {
+      int i = s + 1 + e / rem, j = s + 1 + e % rem;
+      G[i * K + j] -= G[s * K + i] * G[s * K + j];
+    }
+    wave_sync();
+  }
+  return K;
+}
+
+// One-sided Jacobi on B (p x q, column-major, q <= 64) by the calling wavefront.
+__device__ void jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < q * q; e += 64) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
+  wave_sync();
+  if (q < 2) return;
+  const int N = q + (q & 1);
+  const int npairs = N / 2;
+  int tpp = 1;
+  while (tpp * 2 * npairs <= 64 && tpp < 64) tpp *= 2;
+  const int pair = lane / tpp, sub = lane % tpp;
+  // Only singular triplets near or above the truncation threshold
+  // eps * sigma_1 matter: a pair counts as converged once its cosine is below
+  // max(rounding level, 1e-4 eps), and a column whose norm is below
+  // 0.01 eps ||B||_F (< 0.1 eps sigma_1 for q <= 64) is discarded anyway and
+  // is not rotated.
+  const double tol = fmax(2.0 * (p > 16 ? p : 16) * 2.220446049250313e-16, 1e-4 * eps);
+  double fro = 0.0;
+  for (int e = lane; e < p * q; e += 64) fro += B[e] * B[e];
+  for (int off = 32; off >= 1; off >>= 1) fro += __shfl_xor(fro, off);
+  const double tiny = fro * fmax(1e-4 * eps * eps, 4.930380657631324e-32 * (p > 16 ? p : 16));
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    int rotated = 0;
+    for (int rnd = 0; rnd < N - 1; ++rnd) {
+      int ci = -1, cj = -1;
+      if (pair < npairs) {
+        const int mm = N - 1;
+        if (pair == 0) {
+          ci = mm;
+          cj = rnd;
+        } else {
+          ci = (rnd + pair) % mm;
+          cj = (rnd - pair + mm) % mm;
+        }
+        if (ci >= q || cj >= q) ci = cj = -1;
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (ci >= 0)
+        for (int r = sub; r < p; r += tpp) {
+          double x = B[ci * p + r], y = B[cj * p + r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+      for (int off = tpp / 2; off >= 1; off >>= 1) {
+        al += __shfl_xor(al, off);
+        be += __shfl_xor(be, off);
+        ga += __shfl_xor(ga, off);
+      }
+      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+        rotated = 1;
+        double zeta = (be - al) / (2.0 * ga);
+        double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int r = sub; r < p; r += tpp) {
+          double x = B[ci * p + r], y = B[cj * p + r];
+          B[ci * p + r] = cs * x - sn * y;
+          B[cj * p + r] = sn * x + cs * y;
+        }
+        for (int r = sub; r < q; r += tpp) {
+          double x = Z[ci * q + r], y = Z[cj * q + r];
+          Z[ci * q + r] = cs * x - sn * y;
+          Z[cj * q + r] = sn * x + cs * y;
+        }
+      }
+      wave_sync();
+    }
+    // any lane rotated -> another sweep
+    unsigned long long anyrot = __ballot(rotated);
+    if (anyrot == 0ull) break;
+  }
+}
+
+// out (m x kk) = X T for the stacked panel X = st (m x K, K <= 32) and T
+// (K x kk, column-major, LDS).  Rows are staged through LDS in chunks; a
+// chunk is read completely before any of its rows is written, so out may
+// alias the panel's C columns.
+__device__ void rebuild_stream(const ExecArgs& a, const Stack& st, int K, int m, const double* T, int kk, RV out,
+                               double* buf, int cap_rows) {
+  const int tid = threadIdx.x;
+  const int ld = cap_rows | 1;
+  for (int r0 = 0; r0 < m; r0 += cap_rows) {
+    const int rows = min(cap_rows, m - r0);
+    for (int e = tid; e < rows * K; e += blockDim.x) {
+      int i = e % rows, c = e / rows;
+      buf[c * ld + i] = st(a, r0 + i, c);
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * kk; e += blockDim.x) {
+      int i = e % rows, c = e / rows;
+      const double* tc = T + c * K;
+      double acc = 0.0;
+      for (int l = 0; l < K; ++l) acc += buf[l * ld + i] * tc[l];
+      vst(a, out, r0 + i, c, acc);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+                                char* lds, double eps) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int K = su.kc + su.kp + su.kp2;
+  const int m = su.m, n = sv.m;
+  int* s_int = (int*)(lds + kLdsBytes - 64);
+  uint64_t tph = tid == 0 ? wall_clock64() : 0;
+  if (a.counters && tid == 0) {
+    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
+    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
+  }
+  // LDS: [G_U | G_V | B | Z | T_U | T_V] (K*K each), vectors at the end, the
+  // Gram staging buffer over B..T_V and beyond
+  double* GU = (double*)lds;
+  double* GV = GU + K * K;
+  double* B = GV + K * K;
+  double* Z = B + K * K;
+  double* TU = Z + K * K;
+  double* TV = TU + K * K;
+  char* vend = lds + kLdsBytes - 64;
+  double* dU = (double*)(vend - 3 * kSmallK * 8 - 5 * kSmallK * 4);
+  double* dV = dU + kSmallK;
+  double* sig = dV + kSmallK;
+  int* pU = (int*)(sig + kSmallK);
+  int* pV = pU + kSmallK;
+  int* sel = pV + kSmallK;
+  int* posU = sel + kSmallK;
+  int* posV = posU + kSmallK;
+  double* buf = B;
+  const int cap_rows = (int)(((char*)dU - (char*)buf) / 8 / K) - 1;
+  // 1. Gram matrices
+  gram_stream(a, su, K, m, GU, buf, cap_rows);
+  gram_stream(a, sv, K, n, GV, buf, cap_rows);
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 0, &tph);
+  // 2. R factors: wavefront 0 factors G_U, wavefront 1 factors G_V
+  if (wave == 0) {
+    int r = pivoted_cholesky_wave(GU, K, pU, dU);
+    if ((tid & 63) == 0) s_int[0] = r;
+  } else if (wave == 1) {
+    int r = pivoted_cholesky_wave(GV, K, pV, dV);
+    if ((tid & 63) == 0) s_int[1] = r;
+  }
+  __syncthreads();
+  const int rU = s_int[0], rV = s_int[1];
+  phase_tick(a, kCtrPhase + 1, &tph);
+  if (rU == 0 || rV == 0) {
+    if (tid == 0) a.ranks[lr_index] = 0;
+    __syncthreads();
+    return 0;
+  }
+  for (int q = tid; q < K; q += blockDim.x) {
+    posU[pU[q]] = q;
+    posV[pV[q]] = q;
+  }
+  for (int e = tid; e < rU * K; e += blockDim.x)
+    if (e % K < e / K) GU[e] = 0.0;
+  for (int e = tid; e < rV * K; e += blockDim.x)
+    if (e % K < e / K) GV[e] = 0.0;
+  for (int l = tid; l < K; l += blockDim.x) sig[l] = (dU[l] == 0.0 || dV[l] == 0.0) ? 0.0 : 1.0 / (dU[l] * dV[l]);
+  __syncthreads();
+  // 3. core B = Rt_U Rt_V^T (as in trunc_core)
+  for (int e = tid; e < rU * rV; e += blockDim.x) {
+    const int i = e % rU, j = e / rU;
+    const double* ru = GU + i * K;
+    const double* rv = GV + j * K;
+    double s = 0.0;
+    for (int l = 0; l < K; ++l) s += ru[posU[l]] * rv[posV[l]] * sig[l];
+    B[j * rU + i] = s;
+  }
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 2, &tph);
+  // 4. SVD of the core by wavefront 0
+  if (wave == 0) jacobi_svd_wave(B, Z, rU, rV, eps);
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 3, &tph);
+  // 5. order, truncation rank
+  for (int j = tid; j < rV; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
+    sig[j] = sqrt(s);
+  }
+  if (tid == 0) s_int[2] = 0;
+  __syncthreads();
+  double smax = 0.0;
+  for (int j = 0; j < rV; ++j) smax = fmax(smax, sig[j]);
+  for (int j = tid; j < rV; j += blockDim.x) {
+    int rk = 0;
+    for (int l = 0; l < rV; ++l)
+      if (sig[l] > sig[j] || (sig[l] == sig[j] && l < j)) ++rk;
+    sel[rk] = j;
+    if (smax > 0.0 && sig[j] > eps * smax) atomicAdd(&s_int[2], 1);
+  }
+  __syncthreads();
+  int kk = s_int[2];
+  const int limit = min(d.cap, min(d.m, d.n));
+  if (kk > limit) {
+    if (tid == 0 && a.max_rank == 0) atomicAdd(&a.status[2], 1);
+    kk = limit;
+  }
+  if (kk == 0) {
+    if (tid == 0) a.ranks[lr_index] = 0;
+    __syncthreads();
+    return 0;
+  }
+  // 6. T_U = D_U P_U E_r R'_U^{-1} (B Z)_sel, T_V = D_V P_V E_r R'_V^{-1} Z_sel;
+  //    the selected columns are solved in T_U / T_V's space, then scattered
+  //    into rows by permutation and scale in place of B / Z
+  double* yu = TU;
+  double* yv = TV;
+  for (int e = tid; e < rU * kk; e += blockDim.x) {
+    int i = e % rU, c = e / rU;
+    yu[c * rU + i] = B[sel[c] * rU + i];
+  }
+  for (int e = tid; e < rV * kk; e += blockDim.x) {
+    int i = e % rV, c = e / rV;
+    yv[c * rV + i] = Z[sel[c] * rV + i];
+  }
+  __syncthreads();
+  upper_solve(GU, K, rU, yu, kk);
+  upper_solve(GV, K, rV, yv, kk);
+  __syncthreads();
+  double* T_U = B;  // K x kk <= K x K
+  double* T_V = Z;
+  for (int e = tid; e < K * kk; e += blockDim.x) {
+    int l = e % K, c = e / K;
+    int qu = posU[l], qv = posV[l];
+    T_U[c * K + l] = qu < rU ? dU[l] * yu[c * rU + qu] : 0.0;
+    T_V[c * K + l] = qv < rV ? dV[l] * yv[c * rV + qv] : 0.0;
+  }
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 4, &tph);
+  // 7. rebuild in place (staging buffer after T_U / T_V in the B / Z region)
+  {
+    double* rbuf = Z + K * K;
+    const int rcap = (int)(((char*)dU - (char*)rbuf) / 8 / K) - 1;
+    rebuild_stream(a, su, K, m, T_U, kk, RV{d.u_off, m, kk, 1, m, d.type}, rbuf, rcap);
+    rebuild_stream(a, sv, K, n, T_V, kk, RV{d.v_off, n, kk, 1, n, d.type}, rbuf, rcap);
+  }
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 5, &tph);
+  if (tid == 0) a.ranks[lr_index] = kk;
+  __syncthreads();
+  return kk;
+}
+
 // Returns the new rank.
 __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
-                          char* lds, double* scratch) {
+                          char* lds, double* scratch, double eps) {
   const int tid = threadIdx.x;
-  const int K = su.kc + su.kp;
+  const int K = su.kc + su.kp + su.kp2;
   const int m = su.m, n = sv.m;
   int* s_int = (int*)(lds + kLdsBytes - 64);
   if (K == 0) {
@@ -603,10 +984,11 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     __syncthreads();
     return 0;
   }
+  if (K <= kSmallK) return trunc_core_small(a, d, lr_index, su, sv, lds, eps);
   uint64_t tph = threadIdx.x == 0 ? wall_clock64() : 0;
   if (a.counters && tid == 0) {
-    atomicAdd(&a.counters[28], (unsigned long long)K);
-    atomicAdd(&a.counters[29], (unsigned long long)(m + n));
+    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
+    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
   }
   TruncScratch S = trunc_scratch(scratch);
   double* sA = (double*)lds;
@@ -642,11 +1024,11 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
       [&](int i, int j, double v) { S.GV[i * K + j] = v; }, true, true, sA, sB);
   __syncthreads();
-  phase_tick(a, 22, &tph);
+  phase_tick(a, kCtrPhase + 0, &tph);
   // 2. R factors
   const int rU = pivoted_cholesky(S.GU, K, S.pU, S.dU, s_int);
   const int rV = pivoted_cholesky(S.GV, K, S.pV, S.dV, s_int);
-  phase_tick(a, 23, &tph);
+  phase_tick(a, kCtrPhase + 1, &tph);
   if (rU == 0 || rV == 0) {
     if (tid == 0) a.ranks[lr_index] = 0;
     __syncthreads();
@@ -661,8 +1043,14 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
   //    (rU x rV, column-major).  R' is upper trapezoidal in pivoted order:
   //    clear what lies left of its diagonal, then B[i][j] =
   //    sum_l R'_U[i][posU l] R'_V[j][posV l] w[l], w[l] = ||u_l|| ||v_l||.
+  //    The core and its rotations go to LDS after the index vectors when they
+  //    fit there.
   double* B = S.B;
   double* Z = S.Z;
+  if (!small && (int64_t)kTileBytes + kVecBytes + (int64_t)(rU * rV + rV * rV) * 8 + 128 <= kLdsBytes) {
+    B = (double*)(lds + kTileBytes + kVecBytes);
+    Z = B + rU * rV;
+  }
   for (int e = tid; e < rU * K; e += blockDim.x)
     if (e % K < e / K) S.GU[e] = 0.0;
   for (int e = tid; e < rV * K; e += blockDim.x)
@@ -678,10 +1066,15 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     B[j * rU + i] = s;
   }
   __syncthreads();
-  phase_tick(a, 24, &tph);
+  phase_tick(a, kCtrPhase + 2, &tph);
   // 4. SVD of the core: columns of B Z are W_j sigma_j
-  jacobi_svd(B, Z, rU, rV, s_int + 4);
-  phase_tick(a, 25, &tph);
+  if (rV <= 64) {
+    if (tid < 64) jacobi_svd_wave(B, Z, rU, rV, eps);
+    __syncthreads();
+  } else {
+    jacobi_svd(B, Z, rU, rV, s_int + 4, eps);
+  }
+  phase_tick(a, kCtrPhase + 3, &tph);
   for (int j = tid; j < rV; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
@@ -697,7 +1090,7 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     for (int l = 0; l < rV; ++l)
       if (S.sig[l] > S.sig[j] || (S.sig[l] == S.sig[j] && l < j)) ++rk;
     S.sel[rk] = j;
-    if (smax > 0.0 && S.sig[j] > a.eps * smax) atomicAdd(&s_int[2], 1);
+    if (smax > 0.0 && S.sig[j] > eps * smax) atomicAdd(&s_int[2], 1);
   }
   __syncthreads();
   int kk = s_int[2];
@@ -737,7 +1130,7 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     S.TV[c * K + l] = qv < rV ? S.dV[l] * yv[c * rV + qv] : 0.0;
   }
   __syncthreads();
-  phase_tick(a, 26, &tph);
+  phase_tick(a, kCtrPhase + 4, &tph);
   // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile since
   //    kk <= 64, so every row tile is read completely before it is overwritten)
   RV uc{d.u_off, m, kk, 1, m, d.type};
@@ -749,36 +1142,50 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       n, kk, K, [&](int r, int l) { return sv(a, r, l); }, [&](int l, int c) { return S.TV[c * K + l]; },
       [&](int r, int c, double v) { vst(a, vc, r, c, v); }, false, true, sA, sB);
   __syncthreads();
-  phase_tick(a, 27, &tph);
+  phase_tick(a, kCtrPhase + 5, &tph);
   if (tid == 0) a.ranks[lr_index] = kk;
   __syncthreads();
   return kk;
 }
 
+// OP_TRUNC:  C <- T(C + alpha pad(a) pad(b)^T)
+// OP_TRUNC2: C <- T(alpha pad(a) pad(b)^T + beta pad(x) pad(y)^T)  (C's old content ignored)
 __device__ void op_trunc(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
   const LrDesc d = a.lr[t.lr];
-  const int kc = a.ranks[t.lr];
+  const bool two = t.op == OP_TRUNC2;
+  const int kc = two ? 0 : a.ranks[t.lr];
   RV A = resolve(a, t.a), B = resolve(a, t.b);
+  RV X{0, 0, 0, 1, 1, VT_NONE}, Y{0, 0, 0, 1, 1, VT_NONE};
+  if (two) {
+    X = resolve(a, t.x);
+    Y = resolve(a, t.y);
+  }
   Stack su, sv;
   su.c = RV{d.u_off, d.m, kc, 1, d.m, d.type};
   sv.c = RV{d.v_off, d.n, kc, 1, d.n, d.type};
   su.t = A;
   sv.t = B;
+  su.t2 = X;
+  sv.t2 = Y;
   su.tptr = sv.tptr = nullptr;
   su.m = d.m;
   sv.m = d.n;
   su.kc = sv.kc = kc;
   su.kp = sv.kp = A.cols;
+  su.kp2 = sv.kp2 = two ? X.cols : 0;
   su.r0 = t.r0;
   sv.r0 = t.c0;
+  su.r2 = t.row0;
+  sv.r2 = t.c1;
   su.alpha = t.alpha;
-  sv.alpha = 1.0;
+  su.alpha2 = t.beta;
+  sv.alpha = sv.alpha2 = 1.0;
   __syncthreads();
-  const int kn = trunc_core(a, d, t.lr, su, sv, lds, scratch);
+  const int kn = trunc_core(a, d, t.lr, su, sv, lds, scratch, two ? a.eps * kInnerEps : a.eps);
   if (threadIdx.x == 0 && a.counters) {
     int64_t s = d.type == VT_F64 ? 8 : 4;
-    int64_t K = kc + A.cols;
-    int64_t bytes = (int64_t)(d.m + d.n) * (kc + kn) * s + vbytes(A) + vbytes(B);
+    int64_t K = kc + A.cols + su.kp2;
+    int64_t bytes = (int64_t)(d.m + d.n) * (kc + kn) * s + vbytes(A) + vbytes(B) + vbytes(X) + vbytes(Y);
     int64_t flops = 4 * (int64_t)(d.m + d.n) * K * K + 2 * (int64_t)(d.m + d.n) * K * kn + 20 * K * K * K;
     atomicAdd(&a.counters[0], (unsigned long long)bytes);
     atomicAdd(&a.counters[1], (unsigned long long)flops);
@@ -791,7 +1198,7 @@ __device__ void op_trunc(const ExecArgs& a, const Task& t, char* lds, double* sc
 // Algorithmic bytes (every operand read once, every output written once, at
 // run-time extents) and flops of one task; the truncation counts itself.
 __device__ void count_task(const ExecArgs& a, const Task& t) {
-  if (!a.counters || t.op == OP_TRUNC || t.op == OP_NOP) return;
+  if (!a.counters || t.op == OP_TRUNC || t.op == OP_TRUNC2 || t.op == OP_NOP) return;
   int64_t bytes = 0, flops = 0;
   if (t.op == OP_GETRF) {
     int64_t m = t.a.rows;
@@ -832,9 +1239,22 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
   run_task_body(a, t, lds, scratch);
   if (a.counters) {
     __syncthreads();
-    if (threadIdx.x == 0 && t.op >= 0 && t.op < 10) {
-      atomicAdd(&a.counters[2 + t.op], (unsigned long long)(wall_clock64() - t0));
-      atomicAdd(&a.counters[12 + t.op], 1ull);
+    if (threadIdx.x == 0 && t.op >= 0 && t.op < OP_COUNT) {
+      const uint64_t t1 = wall_clock64();
+      atomicAdd(&a.counters[kCtrBusy + t.op], (unsigned long long)(t1 - t0));
+      atomicAdd(&a.counters[kCtrCount + t.op], 1ull);
+      if (a.trace) {
+        a.trace[3 * (int64_t)id] = t0;
+        a.trace[3 * (int64_t)id + 1] = t1;
+        uint64_t info = blockIdx.x & 0xffff;
+        if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
+          const LrDesc d = a.lr[t.lr];
+          uint64_t K = (uint64_t)resolve(a, t.a).cols;
+          if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
+          info |= (K & 0xffff) << 16 | (uint64_t)(d.m + d.n) << 32;
+        }
+        a.trace[3 * (int64_t)id + 2] = info;
+      }
     }
   }
 }
@@ -866,6 +1286,7 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
         op_lrgemm_ct<double>(a, t, lds);
       break;
     case OP_TRUNC:
+    case OP_TRUNC2:
       op_trunc(a, t, lds, scratch);
       break;
     case OP_ZERO:
@@ -880,7 +1301,7 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
 }
 
 // One launch per DAG level: workgroup w runs tasks order[begin + w], order[begin + w + grid], ...
-__global__ void __launch_bounds__(kThreads) exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end) {
+__global__ void __launch_bounds__(kThreads, 2) exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end) {
   extern __shared__ __align__(16) char lds[];
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
@@ -909,7 +1330,7 @@ __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_
 // to zero.  Every slot below ntasks is filled exactly once for an acyclic DAG;
 // a workgroup that waits longer than spin_limit wall-clock ticks raises ST_TIMEOUT and
 // every workgroup then leaves.
-__global__ void __launch_bounds__(kThreads) exec_dataflow_kernel(ExecArgs a) {
+__global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_task;
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
@@ -1145,13 +1566,15 @@ __global__ void __launch_bounds__(kThreads) assemble_aca_kernel(ExecArgs a, AsmA
   sv.t = RV{0, n, k, 1, n, VT_F64};
   su.tptr = U;
   sv.tptr = V;
+  su.t2 = sv.t2 = RV{0, 0, 0, 1, 1, VT_NONE};
   su.m = m;
   sv.m = n;
   su.kc = sv.kc = 0;
   su.kp = sv.kp = k;
-  su.r0 = sv.r0 = 0;
-  su.alpha = sv.alpha = 1.0;
-  trunc_core(a, d, blk.lr, su, sv, lds, a.scratch + (int64_t)blockIdx.x * a.scratch_stride);
+  su.kp2 = sv.kp2 = 0;
+  su.r0 = sv.r0 = su.r2 = sv.r2 = 0;
+  su.alpha = sv.alpha = su.alpha2 = sv.alpha2 = 1.0;
+  trunc_core(a, d, blk.lr, su, sv, lds, a.scratch + (int64_t)blockIdx.x * a.scratch_stride, a.eps);
 }
 
 // ---------------------------------------------------------------------------

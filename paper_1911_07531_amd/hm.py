@@ -20,7 +20,7 @@ FP64, MIXED = 0, 1
 LAPLACE3D, LOG2D = 0, 1
 DATAFLOW, LEVEL = 0, 1
 
-OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy"]
+OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy", "trunc2"]
 
 
 class HmError(RuntimeError):
@@ -32,14 +32,14 @@ class HmError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("leaf", C.c_int), ("eta", C.c_double), ("eps", C.c_double), ("max_rank", C.c_int),
-                ("prec", C.c_int), ("exec", C.c_int)]
+                ("prec", C.c_int), ("exec", C.c_int), ("lazy", C.c_int)]
 
 
 class LuStats(C.Structure):
     _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
-                ("tasks_by_op", C.c_int64 * 10), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
+                ("tasks_by_op", C.c_int64 * 12), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
                 ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64),
-                ("op_busy_ms", C.c_double * 10), ("trunc_phase_ms", C.c_double * 6),
+                ("op_busy_ms", C.c_double * 12), ("trunc_phase_ms", C.c_double * 6),
                 ("trunc_mean_k", C.c_double), ("trunc_mean_mn", C.c_double)]
 
 
@@ -47,7 +47,7 @@ class LuStats(C.Structure):
 VIEW_DTYPE = np.dtype([("off", "<i8"), ("rows", "<i4"), ("cols", "<i4"), ("rs", "<i4"), ("cs", "<i4"),
                        ("type", "<i4"), ("dyn", "<i4"), ("rank_id", "<i4"), ("pad", "<i4")])
 TASK_DTYPE = np.dtype([("op", "<i4"), ("lr", "<i4"), ("r0", "<i4"), ("c0", "<i4"), ("row0", "<i4"),
-                       ("pad", "<i4"), ("piv", "<i8"), ("alpha", "<f8"), ("beta", "<f8"),
+                       ("c1", "<i4"), ("piv", "<i8"), ("alpha", "<f8"), ("beta", "<f8"),
                        ("y", VIEW_DTYPE), ("a", VIEW_DTYPE), ("b", VIEW_DTYPE), ("x", VIEW_DTYPE)])
 
 _lib = None
@@ -57,7 +57,7 @@ def exported_symbols():
     """Names every build of libhm.so must export (the entry points of include/hm.h)."""
     return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
-            "hm_dag_export", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
+            "hm_dag_export", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
 
 
 def lib():
@@ -89,6 +89,7 @@ def lib():
         "hm_lu_stats_get": [vp, C.POINTER(LuStats)],
         "hm_dag_sizes": [vp, C.POINTER(Opts), ip, vp],
         "hm_dag_export": [vp, C.POINTER(Opts), ip, vp, vp, vp, vp, vp, vp],
+        "hm_lu_trace": [vp, vp, C.POINTER(i64), C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -140,8 +141,8 @@ def _check(code: int, info: int = 0):
         raise HmError(code, lib().hm_last_error().decode(), info)
 
 
-def make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=FP64, exec_mode=DATAFLOW) -> Opts:
-    return Opts(int(leaf), float(eta), float(eps), int(max_rank), int(prec), int(exec_mode))
+def make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=FP64, exec_mode=DATAFLOW, lazy=1) -> Opts:
+    return Opts(int(leaf), float(eta), float(eps), int(max_rank), int(prec), int(exec_mode), int(lazy))
 
 
 def _stream_ptr(stream):
@@ -288,12 +289,20 @@ class LU:
         d = {f: getattr(s, f) for f, _ in LuStats._fields_ if f not in ("tasks_by_op", "op_busy_ms", "trunc_phase_ms")}
         d["trunc_phase_ms"] = dict(zip(["gram", "cholesky", "core", "svd", "solve", "rebuild"],
                                        [float(x) for x in s.trunc_phase_ms]))
-        d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(10) if s.tasks_by_op[i]}
-        d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(10) if s.tasks_by_op[i]}
+        d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(11) if s.tasks_by_op[i]}
+        d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(11) if s.tasks_by_op[i]}
         return d
 
     def leaf(self, block: int):
         return export_leaf(self.h, 1, block, self.tree)
+
+    def timeline(self):
+        """(ntasks, 3) uint64 (start, end, workgroup) and the tick rate in kHz (needs HM_DEBUG_TRACE=1)."""
+        n, khz = C.c_int64(), C.c_int64()
+        _check(lib().hm_lu_trace(self.h, None, C.byref(n), C.byref(khz)))
+        out = np.zeros((n.value, 3), np.uint64)
+        _check(lib().hm_lu_trace(self.h, out.ctypes.data, C.byref(n), C.byref(khz)))
+        return out, khz.value
 
     def footprint(self, kind=1) -> int:
         b = C.c_size_t()

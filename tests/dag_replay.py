@@ -26,6 +26,7 @@ class Replay:
         self.ranks = np.zeros(dag["nranks"], np.int32)
         self.eps = eps
         self.max_rank = max_rank
+        self.inner = 0.1  # relative accuracy of inner (combining) truncations, in units of eps
 
     # -- views ---------------------------------------------------------------
     def dims(self, v):
@@ -126,18 +127,23 @@ class Replay:
             self.view(t["y"])[:] = 0.0
         elif op == 9:
             self.view(t["y"])[:] = self.view(t["a"])
+        elif op == 10:
+            self.trunc(t, two=True)
         else:
             raise ValueError(op)
 
-    def trunc(self, t):
+    def trunc(self, t, two=False):
         li = int(t["lr"])
         u_off, v_off, m, n, cap, typ = (int(x) for x in self.d["lr"][li])
         arena = self.f64 if typ == VT_F64 else self.f32
-        kc = int(self.ranks[li])
+        kc = 0 if two else int(self.ranks[li])
         a = np.asarray(self.view(t["a"]), np.float64)
         b = np.asarray(self.view(t["b"]), np.float64)
         kp = a.shape[1]
-        K = kc + kp
+        x = np.asarray(self.view(t["x"]), np.float64) if two else np.zeros((0, 0))
+        y = np.asarray(self.view(t["y"]), np.float64) if two else np.zeros((0, 0))
+        kp2 = x.shape[1] if two else 0
+        K = kc + kp + kp2
         if K == 0:
             self.ranks[li] = 0
             return
@@ -146,12 +152,17 @@ class Replay:
         us[:, :kc] = np.asarray(arena[u_off:u_off + m * kc], np.float64).reshape(kc, m).T
         vs[:, :kc] = np.asarray(arena[v_off:v_off + n * kc], np.float64).reshape(kc, n).T
         r0, c0 = int(t["r0"]), int(t["c0"])
-        us[r0:r0 + a.shape[0], kc:] = t["alpha"] * a
-        vs[c0:c0 + b.shape[0], kc:] = b
+        us[r0:r0 + a.shape[0], kc:kc + kp] = t["alpha"] * a
+        vs[c0:c0 + b.shape[0], kc:kc + kp] = b
+        if two:
+            r1, c1 = int(t["row0"]), int(t["c1"])
+            us[r1:r1 + x.shape[0], kc + kp:] = t["beta"] * x
+            vs[c1:c1 + y.shape[0], kc + kp:] = y
         qu, ru = np.linalg.qr(us)
         qv, rv = np.linalg.qr(vs)
         w, s, zt = np.linalg.svd(ru @ rv.T)
-        k = 0 if s.size == 0 or s[0] <= 0 else int(np.count_nonzero(s > self.eps * s[0]))
+        eps = self.eps * (self.inner if two else 1.0)
+        k = 0 if s.size == 0 or s[0] <= 0 else int(np.count_nonzero(s > eps * s[0]))
         k = min(k, cap, m, n)
         unew = qu @ (w[:, :k] * s[:k])
         vnew = qv @ zt[:k].T

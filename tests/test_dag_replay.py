@@ -13,9 +13,9 @@ from paper_1911_07531_amd import hm, inputs
 from tests.dag_replay import Replay
 
 
-def _setup(n, leaf, eta, eps, max_rank, prec=hm.FP64, seed=0):
+def _setup(n, leaf, eta, eps, max_rank, prec=hm.FP64, seed=0, lazy=0):
     pts, diag = inputs.sphere_problem(n, seed)
-    opts = hm.make_opts(leaf=leaf, eta=eta, eps=eps, max_rank=max_rank, prec=prec)
+    opts = hm.make_opts(leaf=leaf, eta=eta, eps=eps, max_rank=max_rank, prec=prec, lazy=lazy)
     t = hm.Tree(pts, opts)
     perm, cl = H.build_cluster_tree(pts, leaf)
     root = H.build_block_tree(cl[0], eta)
@@ -95,3 +95,26 @@ def test_replay_solve_matches_oracle():
     x[a.perm] = rs.f64[po:po + n * 5].reshape(5, n).T
     ref_x = H.solve(ref, b)
     assert np.allclose(x, ref_x, rtol=0, atol=1e-9 * np.abs(ref_x).max())
+
+
+@pytest.mark.parametrize("n,leaf,eps,max_rank", [(1024, 32, 1e-6, 0), (2048, 32, 1e-4, 16)])
+def test_replay_lazy_updates_within_bounds(n, leaf, eps, max_rank):
+    """Collected updates (balanced tree of truncations) stay within the parity
+    bounds of the sequential H-LU: ||PA - LU||_2/||A||_2 <= 10 eps against the
+    exact matrix, ranks within +-2 of the oracle's."""
+    t, opts, a = _setup(n, leaf, 2.0, eps, max_rank, lazy=1)
+    dag = t.dag(opts, 0)
+    assert (dag["tasks"]["op"] == 10).any()
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    rp = Replay(dag, eps, max_rank)
+    rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+    rp.run(np.random.default_rng(7))
+    f = _factors_from_replay(rp, t, a, dag)
+    pts, diag = inputs.sphere_problem(n, 0)
+    dense = H.kernel_block(pts, a.perm, a.clusters[0], a.clusters[0], diag)
+    err = H.lu_error_2norm(dense, f, exact=True)
+    assert err <= 10 * eps
+    ref = H.hlu(a, lazy=True)
+    rr, rg = H.rank_table(ref), H.rank_table(f)
+    assert max(abs(rg[i] - rr[i]) for i in rr) <= 2
+    assert H.lu_error_2norm(dense, ref, exact=True) <= 10 * eps

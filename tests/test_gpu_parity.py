@@ -55,10 +55,11 @@ def test_singular_leaf_reports_row():
 
 @pytest.fixture(scope="module")
 def c1():
-    """n = 2048, leaf 32, eta = 2, eps = 1e-6 (the small sphere workload)."""
+    """n = 2048, leaf 32, eta = 2, eps = 1e-6 (the small sphere workload);
+    updates collected per hmul call on both sides (Reading R6)."""
     p = Problem(2048, 32, 1e-6)
     f = hm.LU(p.A, p.opts)
-    of = H.hlu(p.oa)
+    of = H.hlu(p.oa, lazy=True)
     return p, f, of
 
 
@@ -119,6 +120,19 @@ def test_matvec_c1(c1):
     y = to_host(p.A.matvec(device_rhs(x), device_rhs(y0), alpha=-0.5, beta=2.0))
     ref = -0.5 * ah @ x + 2.0 * y0
     assert np.max(np.abs(y - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_sequential_updates_match_sequential_oracle():
+    """lazy = 0: every update truncated as produced, in Algorithm 1's order."""
+    p = Problem(1024, 32, 1e-6)
+    opts = hm.make_opts(leaf=32, eta=2.0, eps=1e-6, lazy=0)
+    f = hm.LU(p.A, opts)
+    of = H.hlu(p.oa)
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    assert H.lu_error_2norm(dense, gf, exact=True) <= 10 * p.eps
+    orank, grank = H.rank_table(of), H.rank_table(gf)
+    assert max(abs(grank[k] - orank[k]) for k in orank) <= 2
 
 
 def test_level_and_dataflow_executors_identical():

@@ -80,7 +80,7 @@ def test_dag_is_forward_and_levels_consistent(prec):
         assert np.all(lv[si] >= lv[src] + 1)    # levels are a valid schedule
         assert lv.max() + 1 == d["nlevels"]
         ops = d["tasks"]["op"]
-        assert set(np.unique(ops)) <= set(range(1, 10))
+        assert set(np.unique(ops)) <= set(range(1, 11))
     # every diagonal leaf is factored exactly once, in order along the diagonal
     d = t.dag(opts, 0)
     getrf = d["tasks"][d["tasks"]["op"] == 1]

@@ -287,3 +287,25 @@ def test_refinement_converges_c1(c1):
     x, it, rel = H.refine(a, f, b, rtol=1e-10, max_iter=30)
     assert np.all(rel <= 1e-10)
     assert it <= 10
+
+
+def test_hlu_lazy_eps0_equals_dense_block_lu():
+    """Collected updates (Reading R6) change only the grouping of truncations:
+    at eps = 0 the factors still equal the dense leaf-pivoted block LU."""
+    a, dense = _problem(512, 32, 2.0, 0.0)
+    f = H.hlu(a, lazy=True)
+    leaves = sorted({(c.begin, c.end) for c in a.clusters if c.is_leaf})
+    ref, pivs = _dense_block_lu(dense, leaves)
+    assert np.max(np.abs(H.densify(f.root) - ref)) <= 1e-11 * np.abs(dense).max()
+    assert all(not b.pending for b in H.leaf_blocks(f.root))
+
+
+def test_hlu_lazy_error_bound_c1(c1):
+    a, dense, _ = c1
+    f = H.hlu(a, lazy=True)
+    assert H.lu_error_2norm(dense, f, exact=True) <= 10 * 1e-6
+    # one truncation per collected batch: the truncation of an exact sum is at
+    # least as accurate as the sequential chain, so ranks are never much lower
+    seq = H.rank_table(H.hlu(a))
+    lz = H.rank_table(f)
+    assert min(lz[i] - seq[i] for i in seq) >= -2
