@@ -44,10 +44,30 @@ def parse():
     ap.add_argument("--solves", type=int, default=20, help="solve requests timed for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")
     return ap.parse_args()
 
 
-def cpu_baseline(n_sample, leaf, eps, max_rank, flops_full):
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1911_07531_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, executor):
+    """HBM bytes per launch of the executor from a committed counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"hlu_{workload}_{executor}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_sample, leaf, eps, max_rank, lazy):
     """Time the FP64 oracle's H-LU on a bounded sample of the same workload."""
     from oracle import hmatrix as H
     from paper_1911_07531_amd import inputs
@@ -56,7 +76,7 @@ def cpu_baseline(n_sample, leaf, eps, max_rank, flops_full):
     root = H.build_block_tree(cl[0], 2.0)
     a = H.assemble(pts, perm, cl, root, diag, eps, max_rank)
     t0 = time.perf_counter()
-    H.hlu(a)
+    H.hlu(a, lazy=bool(lazy))
     dt = time.perf_counter() - t0
     return dt
 
@@ -68,6 +88,16 @@ def main():
                                    "notes), run with --gpus 1"}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        return
 
     from paper_1911_07531_amd import hm, inputs
 
@@ -148,7 +178,8 @@ def main():
     ach = st["bytes_alg"] / (med_exec * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:
-        t_cpu = cpu_baseline(args.cpu_sample_n, leaf, eps, max_rank, st["flops_alg"])
+        print("# cpu baseline: oracle H-LU on the sample ...", file=sys.stderr, flush=True)
+        t_cpu = cpu_baseline(args.cpu_sample_n, leaf, eps, max_rank, opts.lazy)
         # scale the sample by the ratio of algorithmic flops (n log^2 n growth measured on the GPU side)
         f_s = None
         try:
@@ -190,7 +221,7 @@ def main():
                 "by_op": st["tasks_by_op"], "busy_ms_by_op": {k: round(v, 2) for k, v in st["op_busy_ms"].items()}},
         "setup_s": {"tree": t_tree, "assemble": t_asm, "trace": t_trace},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "exec_dataflow_kernel" if exec_mode == hm.DATAFLOW else
+                     "traffic": measured_traffic(args.workload, args.exec_mode), "kernel": "exec_dataflow_kernel" if exec_mode == hm.DATAFLOW else
                      "exec_level_kernel", "bytes_alg_per_launch": st["bytes_alg"],
                      "flops_alg_per_launch": st["flops_alg"],
                      "fp64_flop_frac": st["flops_alg"] / (med_exec * 1e-3) / (FP64_PEAK_TFS * 1e12)},

@@ -182,8 +182,9 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p) {
       p.data_type[b] = type;
       cur += m * n;
       if (diag) {
+        // LAPACK interchanges (m) followed by the resulting row permutation (m)
         p.piv_off[b] = piv;
-        piv += m;
+        piv += 2 * m;
         p.diag_leaves.push_back((int)b);
       }
     } else {

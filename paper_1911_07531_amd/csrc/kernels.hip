@@ -220,13 +220,15 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
 #pragma clang fp contract(off)
   const int m = t.a.rows;
   double* g = a.f64 + t.a.off;
-  const bool in_lds = (int64_t)m * (m + 1) * 8 + 64 <= kLdsBytes;
+  const bool in_lds = (int64_t)m * (m + 1) * 8 + 64 + 4 * kMaxLeaf <= kLdsBytes;
   const int ld = in_lds ? m + 1 : m;
   double* A = in_lds ? (double*)lds : g;
   int* s_piv = (int*)(lds + kLdsBytes - 16);
+  int* s_perm = (int*)(lds + kLdsBytes - 16 - 4 * kMaxLeaf);
   const int tid = threadIdx.x;
   if (in_lds)
     for (int e = tid; e < m * m; e += blockDim.x) A[(e / m) * ld + (e % m)] = g[e];
+  for (int i = tid; i < m; i += blockDim.x) s_perm[i] = i;
   __syncthreads();
   for (int j = 0; j < m; ++j) {
     if (tid < 64) {
@@ -255,12 +257,18 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
     }
     __syncthreads();
     const int p = s_piv[0];
-    if (p != j)
+    if (p != j) {
       for (int c = tid; c < m; c += blockDim.x) {
         double x = A[c * ld + j];
         A[c * ld + j] = A[c * ld + p];
         A[c * ld + p] = x;
       }
+      if (tid == 0) {
+        int x = s_perm[j];
+        s_perm[j] = s_perm[p];
+        s_perm[p] = x;
+      }
+    }
     __syncthreads();
     const double pv = A[j * ld + j];
     if (pv == 0.0) {
@@ -282,6 +290,8 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
   }
   if (in_lds)
     for (int e = tid; e < m * m; e += blockDim.x) g[e] = A[(e / m) * ld + (e % m)];
+  // row permutation after all interchanges: (P x)[i] = x[perm[i]]
+  for (int i = tid; i < m; i += blockDim.x) a.piv[t.piv + m + i] = s_perm[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -304,50 +314,46 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
   const int tid = threadIdx.x;
   if (tri_lds)
     for (int e = tid; e < m * m; e += blockDim.x) sL[e] = g[e];
-  const int32_t* piv = a.piv + t.piv;
+  const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
   for (int j0 = 0; j0 < c; j0 += CC) {
-    int cc = min(CC, c - j0);
+    const int cc = min(CC, c - j0);
+    // load (rows gathered through the leaf's permutation for L^{-1} P)
     for (int e = tid; e < m * cc; e += blockDim.x) {
       int i = X.rs == 1 ? e % m : e / cc;
       int j = X.rs == 1 ? e / m : e % cc;
-      sX[i * CC + j] = vld(a, X, i, j0 + j);
+      int src = kind == 0 ? perm[i] : i;
+      sX[i * CC + j] = vld(a, X, src, j0 + j);
     }
     __syncthreads();
-    if (tid < cc) {
-      const int j = tid;
-      if (kind == 0) {
-        for (int r = 0; r < m; ++r) {
-          int p = piv[r];
-          if (p != r) {
-            double x = sX[r * CC + j];
-            sX[r * CC + j] = sX[p * CC + j];
-            sX[p * CC + j] = x;
-          }
+    // right-looking substitution: step k finalises row k (up to the diagonal
+    // scale for U) and updates the rows after it; the scale is applied at the end
+    if (kind == 0 || kind == 1) {
+      for (int k = 0; k < m - 1; ++k) {
+        const double sc = kind == 0 ? 1.0 : 1.0 / T[k * m + k];
+        const int rows = m - 1 - k;
+        for (int e = tid; e < rows * cc; e += blockDim.x) {
+          const int i = k + 1 + e / cc, j = e % cc;
+          const double lik = kind == 0 ? T[k * m + i] : T[i * m + k];
+          sX[i * CC + j] -= lik * (sX[k * CC + j] * sc);
         }
-        for (int i = 1; i < m; ++i) {
-          double s = sX[i * CC + j];
-          for (int q = 0; q < i; ++q) s -= T[q * m + i] * sX[q * CC + j];
-          sX[i * CC + j] = s;
+        __syncthreads();
+      }
+    } else {
+      for (int k = m - 1; k > 0; --k) {
+        const double sc = 1.0 / T[k * m + k];
+        for (int e = tid; e < k * cc; e += blockDim.x) {
+          const int i = e / cc, j = e % cc;
+          sX[i * CC + j] -= T[k * m + i] * (sX[k * CC + j] * sc);
         }
-      } else if (kind == 1) {
-        for (int i = 0; i < m; ++i) {
-          double s = sX[i * CC + j];
-          for (int q = 0; q < i; ++q) s -= T[i * m + q] * sX[q * CC + j];
-          sX[i * CC + j] = s / T[i * m + i];
-        }
-      } else {
-        for (int i = m - 1; i >= 0; --i) {
-          double s = sX[i * CC + j];
-          for (int q = i + 1; q < m; ++q) s -= T[q * m + i] * sX[q * CC + j];
-          sX[i * CC + j] = s / T[i * m + i];
-        }
+        __syncthreads();
       }
     }
-    __syncthreads();
     for (int e = tid; e < m * cc; e += blockDim.x) {
       int i = X.rs == 1 ? e % m : e / cc;
       int j = X.rs == 1 ? e / m : e % cc;
-      vst(a, X, i, j0 + j, sX[i * CC + j]);
+      double v = sX[i * CC + j];
+      if (kind != 0) v *= 1.0 / T[i * m + i];
+      vst(a, X, i, j0 + j, v);
     }
     __syncthreads();
   }
@@ -650,9 +656,15 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, do
       if (e < K * K) {
         const double* xi = buf + (e / K) * ld;
         const double* xj = buf + (e % K) * ld;
-        double s = 0.0;
-        for (int t = 0; t < rows; ++t) s += xi[t] * xj[t];
-        acc[q] += s;
+        double s0 = 0.0, s1 = 0.0;
+        int t = 0;
+#pragma unroll 4
+        for (; t + 1 < rows; t += 2) {
+          s0 += xi[t] * xj[t];
+          s1 += xi[t + 1] * xj[t + 1];
+        }
+        if (t < rows) s0 += xi[t] * xj[t];
+        acc[q] += s0 + s1;
       }
     }
     __syncthreads();
@@ -664,14 +676,14 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, do
   }
 }
 
-// Scaled, diagonally pivoted Cholesky of G (K x K, K <= 64) by the calling
+// Scaled, diagonally pivoted Cholesky of G (K x K, K <= 128) by the calling
 // wavefront alone; same results as pivoted_cholesky.  Returns the rank.
 __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
   const int lane = threadIdx.x & 63;
-  if (lane < K) {
-    double d = G[lane * K + lane];
-    dsc[lane] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-    perm[lane] = lane;
+  for (int l = lane; l < K; l += 64) {
+    double d = G[l * K + l];
+    dsc[l] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    perm[l] = l;
   }
   wave_sync();
   for (int e = lane; e < K * K; e += 64) G[e] *= dsc[e / K] * dsc[e % K];
@@ -680,9 +692,12 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
   for (int s = 0; s < K; ++s) {
     double best = -1.0;
     int bi = K;
-    if (lane >= s && lane < K) {
-      best = G[lane * K + lane];
-      bi = lane;
+    for (int l = s + lane; l < K; l += 64) {
+      double v = G[l * K + l];
+      if (v > best) {
+        best = v;
+        bi = l;
+      }
     }
     for (int off = 32; off >= 1; off >>= 1) {
       double ob = __shfl_xor(best, off);
@@ -695,16 +710,16 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
     if (bi >= K || !(best > tol)) return s;
     const int p = bi;
     if (p != s) {
-      if (lane < K) {  // swap rows s and p
-        double x = G[s * K + lane];
-        G[s * K + lane] = G[p * K + lane];
-        G[p * K + lane] = x;
+      for (int l = lane; l < K; l += 64) {  // swap rows s and p
+        double x = G[s * K + l];
+        G[s * K + l] = G[p * K + l];
+        G[p * K + l] = x;
       }
       wave_sync();
-      if (lane < K) {  // swap columns s and p
-        double x = G[lane * K + s];
-        G[lane * K + s] = G[lane * K + p];
-        G[lane * K + p] = x;
+      for (int l = lane; l < K; l += 64) {  // swap columns s and p
+        double x = G[l * K + s];
+        G[l * K + s] = G[l * K + p];
+        G[l * K + p] = x;
       }
       if (lane == 0) {
         int x = perm[s];
@@ -715,7 +730,7 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
     }
     const double d = sqrt(G[s * K + s]);
     wave_sync();
-    if (lane >= s && lane < K) G[s * K + lane] = (lane == s) ? d : G[s * K + lane] / d;
+    for (int l = s + lane; l < K; l += 64) G[s * K + l] = (l == s) ? d : G[s * K + l] / d;
     wave_sync();
     const int rem = K - s - 1;
     for (int e = lane; e < rem * rem; e += 64) {
@@ -727,7 +742,7 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
   return K;
 }
 
-// One-sided Jacobi on B (p x q, column-major, q <= 64) by the calling wavefront.
+// One-sided Jacobi on B (p x q, column-major, q <= 128) by the calling wavefront.
 __device__ void jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
   const int lane = threadIdx.x & 63;
   for (int e = lane; e < q * q; e += 64) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
@@ -1025,9 +1040,16 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       [&](int i, int j, double v) { S.GV[i * K + j] = v; }, true, true, sA, sB);
   __syncthreads();
   phase_tick(a, kCtrPhase + 0, &tph);
-  // 2. R factors
-  const int rU = pivoted_cholesky(S.GU, K, S.pU, S.dU, s_int);
-  const int rV = pivoted_cholesky(S.GV, K, S.pV, S.dV, s_int);
+  // 2. R factors: wavefront 0 factors G_U, wavefront 1 factors G_V
+  if ((tid >> 6) == 0) {
+    int r = pivoted_cholesky_wave(S.GU, K, S.pU, S.dU);
+    if (tid == 0) s_int[0] = r;
+  } else if ((tid >> 6) == 1) {
+    int r = pivoted_cholesky_wave(S.GV, K, S.pV, S.dV);
+    if ((tid & 63) == 0) s_int[1] = r;
+  }
+  __syncthreads();
+  const int rU = s_int[0], rV = s_int[1];
   phase_tick(a, kCtrPhase + 1, &tph);
   if (rU == 0 || rV == 0) {
     if (tid == 0) a.ranks[lr_index] = 0;
@@ -1068,12 +1090,8 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
   __syncthreads();
   phase_tick(a, kCtrPhase + 2, &tph);
   // 4. SVD of the core: columns of B Z are W_j sigma_j
-  if (rV <= 64) {
-    if (tid < 64) jacobi_svd_wave(B, Z, rU, rV, eps);
-    __syncthreads();
-  } else {
-    jacobi_svd(B, Z, rU, rV, s_int + 4, eps);
-  }
+  if (tid < 64) jacobi_svd_wave(B, Z, rU, rV, eps);
+  __syncthreads();
   phase_tick(a, kCtrPhase + 3, &tph);
   for (int j = tid; j < rV; j += blockDim.x) {
     double s = 0.0;
@@ -1352,22 +1370,29 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
           }
           __builtin_amdgcn_s_sleep(1);
         }
+        if (t >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       s_task = t;
     }
     __syncthreads();
     const int t = s_task;
     if (t < 0) break;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     run_task(a, t, lds, scratch);
-    __threadfence();
+    // Publication: every thread's stores precede the workgroup barrier; one
+    // agent-scope release fence then makes them visible across XCDs before
+    // any successor count drops.  The workgroup that releases a successor
+    // (its count reaches zero) orders the push after an acq_rel fence, so the
+    // consumer's acquire covers every predecessor's data.
+    __syncthreads();
+    if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid < 64) {
       const int b = a.succ_ptr[t], e = a.succ_ptr[t + 1];
       for (int k = b + tid; k < e; k += 64) {
         const int s = a.succ_idx[k];
-        int prev = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int prev = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 1) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
           int pos = atomicAdd(&a.qctl[1], 1);
           if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
