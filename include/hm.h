@@ -98,7 +98,8 @@ typedef struct {
   int64_t temp_bytes;  /* temporaries of the traced DAG */
   int64_t rank_overflows;
   double op_busy_ms[12];  /* summed workgroup-busy time per task kind (index = task kind) */
-  double trunc_phase_ms[6]; /* truncation phases: Gram, Cholesky, core, SVD, solve, rebuild */
+  double trunc_phase_ms[12]; /* truncation phases Gram, Cholesky, core, SVD, solve, rebuild:
+                                [0..5] stacked rank <= 32, [6..11] larger */
   double trunc_mean_k, trunc_mean_mn; /* mean stacked rank K and mean m + n of truncations */
 } hm_lu_stats;
 
@@ -158,8 +159,13 @@ hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* da
 
 /* Per-task timeline of the last h_lu on F, recorded only when the
  * environment variable HM_DEBUG_TRACE=1 was set before h_lu: out (may be
- * NULL to query sizes) receives ntasks x 3 uint64 (start tick, end tick,
- * workgroup) in trace order; ticks count at clock_khz kHz. */
+ * NULL to query sizes) receives ntasks x 4 uint64 (start tick, end tick,
+ * info, info2) in trace order; ticks count at clock_khz kHz.  info bits 0-15
+ * hold the workgroup; for truncations bits 16-31 the width of the added
+ * terms and bits 32-47 / 48-63 the rows m / columns n of the low-rank leaf,
+ * and info2 the route (bits 0-7: 1 small-rank, 2 dense, 3 / 4 Gram with the
+ * core in LDS / global memory), the SVD operand's rows p and columns q (bits
+ * 8-19, 20-31), the Jacobi sweeps (32-39) and the new rank (40-47). */
 hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz);
 
 /* Statistics of the last h_lu on F. */

@@ -737,7 +737,7 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
   // HM_DEBUG_TRACE=1 records (start, end, workgroup) of every H-LU task
   if (const char* e = getenv("HM_DEBUG_TRACE"))
-    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * 24, s))
+    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * 32, s))
       return fail(HM_ENOMEM, "device allocation failed (trace)");
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
   // copy A into the factor layout
@@ -785,7 +785,7 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   HIPCHK(hipMemcpy(stv, F->lu_st.status.p, 16, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(ctr, F->lu_st.counters.p, sizeof(ctr), hipMemcpyDeviceToHost));
   for (int k = 0; k < OP_COUNT; ++k) F->stats.op_busy_ms[k] = (double)ctr[kCtrBusy + k] / (double)g_clock_khz;
-  for (int k = 0; k < 6; ++k) F->stats.trunc_phase_ms[k] = (double)ctr[kCtrPhase + k] / (double)g_clock_khz;
+  for (int k = 0; k < 12; ++k) F->stats.trunc_phase_ms[k] = (double)ctr[kCtrPhase + k] / (double)g_clock_khz;
   double ntr = (double)std::max<unsigned long long>(1, ctr[kCtrCount + OP_TRUNC] + ctr[kCtrCount + OP_TRUNC2]);
   F->stats.trunc_mean_k = ctr[kCtrK] / ntr;
   F->stats.trunc_mean_mn = ctr[kCtrMN] / ntr;
@@ -826,7 +826,7 @@ hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_kh
   if (clock_khz) *clock_khz = g_clock_khz;
   if (!out) return HM_OK;
   if (!F->lu_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
-  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * 24, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * 32, hipMemcpyDeviceToHost));
   return HM_OK;
 }
 

@@ -96,7 +96,8 @@ struct ExecArgs {
   int64_t spin_limit;  // wall-clock ticks a waiting workgroup polls before giving up
   // [0] algorithmic bytes, [1] algorithmic flops, [kCtrBusy + op] busy
   // wall-clock ticks of each task kind, [kCtrCount + op] task count,
-  // [kCtrPhase ..+5] ticks of the truncation phases, [kCtrK] sum of stacked
+  // [kCtrPhase ..+11] ticks of the truncation phases (+0..5 small-rank path,
+  // +6..11 large-rank path), [kCtrK] sum of stacked
   // ranks K, [kCtrMN] sum of m + n (null: off)
   unsigned long long* counters;
   uint64_t* trace;  // optional: per task (start tick, end tick, workgroup)
@@ -135,7 +136,7 @@ struct CopyDesc {
 
 constexpr int64_t kScratchDoubles = 4 * kMaxK * kMaxK + 4 * kMaxK * kMaxCap + 6 * kMaxK + 64;
 
-constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COUNT, kCtrK = kCtrPhase + 6,
+constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COUNT, kCtrK = kCtrPhase + 12,
               kCtrMN = kCtrK + 1, kCtrSize = kCtrMN + 1;
 
 enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4 };

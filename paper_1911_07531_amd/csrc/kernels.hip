@@ -519,11 +519,11 @@ __device__ TruncScratch trunc_scratch(double* p) {
 // One-sided Jacobi (Hestenes) on B (p x q, column-major, ld p): orthogonalise the
 // columns; Z (q x q, column-major) accumulates the rotations.  Round-robin
 // pairing, all pairs of a round in parallel.
-__device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, double eps) {
+__device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, double eps) {
   const int tid = threadIdx.x;
   for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   __syncthreads();
-  if (q < 2) return;
+  if (q < 2) return 0;
   const int N = q + (q & 1);
   const int npairs = N / 2;
   int tpp = 1;
@@ -546,7 +546,8 @@ __device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doub
   }
   __syncthreads();
   const double tiny = *fro_s * fmax(1e-4 * eps * eps, 4.930380657631324e-32 * (p > 16 ? p : 16));
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
     if (tid == 0) s_flag[0] = 0;
     __syncthreads();
     for (int rnd = 0; rnd < N - 1; ++rnd) {
@@ -597,6 +598,7 @@ __device__ void jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doub
     __syncthreads();
     if (!again) break;
   }
+  return sweep + 1;
 }
 
 // Solve the r x r upper triangle of R' (rows of G, stride K) against rhs columns
@@ -743,11 +745,11 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
 }
 
 // One-sided Jacobi on B (p x q, column-major, q <= 128) by the calling wavefront.
-__device__ void jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
+__device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
   const int lane = threadIdx.x & 63;
   for (int e = lane; e < q * q; e += 64) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   wave_sync();
-  if (q < 2) return;
+  if (q < 2) return 0;
   const int N = q + (q & 1);
   const int npairs = N / 2;
   int tpp = 1;
@@ -763,7 +765,8 @@ __device__ void jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) 
   for (int e = lane; e < p * q; e += 64) fro += B[e] * B[e];
   for (int off = 32; off >= 1; off >>= 1) fro += __shfl_xor(fro, off);
   const double tiny = fro * fmax(1e-4 * eps * eps, 4.930380657631324e-32 * (p > 16 ? p : 16));
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
     int rotated = 0;
     for (int rnd = 0; rnd < N - 1; ++rnd) {
       int ci = -1, cj = -1;
@@ -813,6 +816,7 @@ __device__ void jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) 
     unsigned long long anyrot = __ballot(rotated);
     if (anyrot == 0ull) break;
   }
+  return sweep + 1;
 }
 
 // out (m x kk) = X T for the stacked panel X = st (m x K, K <= 32) and T
@@ -838,6 +842,18 @@ __device__ void rebuild_stream(const ExecArgs& a, const Stack& st, int K, int m,
       vst(a, out, r0 + i, c, acc);
     }
     __syncthreads();
+  }
+}
+
+// Debug note of a truncation for the per-task trace (thread 0, LDS flag
+// words 12..14): route (1 small-rank, 2 dense, 3 Gram with the core in LDS,
+// 4 Gram with the core in global memory), SVD operand p x q, sweeps, rank.
+__device__ __forceinline__ void trunc_note(char* lds, int route, int p, int q, int sweeps, int kk) {
+  if (threadIdx.x == 0) {
+    int* s_int = (int*)(lds + kLdsBytes - 64);
+    s_int[12] = route;
+    s_int[13] = (p & 0xffff) | (q << 16);
+    s_int[14] = (sweeps & 0xffff) | (kk << 16);
   }
 }
 
@@ -914,7 +930,10 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   __syncthreads();
   phase_tick(a, kCtrPhase + 2, &tph);
   // 4. SVD of the core by wavefront 0
-  if (wave == 0) jacobi_svd_wave(B, Z, rU, rV, eps);
+  if (wave == 0) {
+    const int sw = jacobi_svd_wave(B, Z, rU, rV, eps);
+    trunc_note(lds, 1, rU, rV, sw, 0);
+  }
   __syncthreads();
   phase_tick(a, kCtrPhase + 3, &tph);
   // 5. order, truncation rank
@@ -987,128 +1006,216 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   return kk;
 }
 
-// Returns the new rank.
-__device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
-                          char* lds, double* scratch, double eps) {
+// ---------------------------------------------------------------------------
+// Truncation with K > kSmallK stacked columns.  LDS: a work area from offset 0
+// (GEMM tiles, Gram matrices, the SVD operand and its rotations, a triangle),
+// then the per-column vectors, then 64 bytes of flags.
+// ---------------------------------------------------------------------------
+constexpr int kLargeVecBytes = 5 * kMaxK * 8 + 5 * kMaxK * 4;
+constexpr int kLargeWork = (kLdsBytes - 64 - kLargeVecBytes) / 8;  // doubles
+constexpr int kTileDoubles = kTileBytes / 8;
+
+struct LargeVecs {
+  double *dU, *dV, *eU, *eV, *sig;
+  int *pU, *pV, *sel, *posU, *posV;
+};
+
+__device__ LargeVecs large_vecs(char* lds) {
+  LargeVecs v;
+  double* p = (double*)(lds + kLdsBytes - 64 - kLargeVecBytes);
+  v.dU = p;
+  v.dV = p + kMaxK;
+  v.eU = p + 2 * kMaxK;
+  v.eV = p + 3 * kMaxK;
+  v.sig = p + 4 * kMaxK;
+  int* ip = (int*)(p + 5 * kMaxK);
+  v.pU = ip;
+  v.pV = ip + kMaxK;
+  v.sel = ip + 2 * kMaxK;
+  v.posU = ip + 3 * kMaxK;
+  v.posV = ip + 4 * kMaxK;
+  return v;
+}
+
+// Scaled, diagonally pivoted Cholesky of two Gram matrices (K x K, row-major,
+// K <= kMaxK), one per half of the workgroup, in left-looking order: step s
+// takes the largest remaining diagonal entry of the scaled Schur complement
+// (e[]: 1 at the start, -1 once pivoted) and forms row s of the factor from
+// that pivot's row of G and the rows found before.  Row s of the factor, in
+// the original column order and zero at earlier pivots, overwrites row
+// perm[s] of G.  dsc[l] = 1/||column l|| (0 for a zero column).  The ranks go
+// to s_int[0] (G_U) and s_int[1] (G_V).
+__device__ void pivoted_cholesky_pair(double* GU, double* GV, int K, const LargeVecs& v, int* s_int) {
+  const int tid = threadIdx.x, h = tid >> 7, t = tid & 127;
+  double* G = h ? GV : GU;
+  double* e = h ? v.eV : v.eU;
+  double* dsc = h ? v.dV : v.dU;
+  int* perm = h ? v.pV : v.pU;
+  int* slot = s_int + 4 + 4 * h;  // [0] pivot, [1] go, [2..3] the pivot's Schur entry (double)
+  const double tol = 8.0 * K * 2.220446049250313e-16;
+  if (t < K) {
+    const double g = G[t * K + t];
+    dsc[t] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+    e[t] = g > 0.0 ? 1.0 : 0.0;
+  }
+  if (t == 0) slot[1] = 1;
+  __syncthreads();
+  int r = 0;
+  for (int s = 0; s < K; ++s) {
+    if (slot[1] && t < 64) {
+      double best = -1.0;
+      int bi = K;
+      for (int l = t; l < K; l += 64) {
+        const double x = e[l];
+        if (x > best) {
+          best = x;
+          bi = l;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        const bool go = bi < K && best > tol;
+        slot[0] = bi;
+        slot[1] = go ? 1 : 0;
+        *(double*)(slot + 2) = best;
+        if (go) perm[s] = bi;
+      }
+    }
+    __syncthreads();
+    if (!s_int[5] && !s_int[9]) break;
+    if (slot[1]) {
+      r = s + 1;
+      const int p = slot[0];
+      const double piv = sqrt(*(const double*)(slot + 2));
+      if (t < K) {
+        const double et = e[t];
+        double val = 0.0;
+        if (t == p) {
+          val = piv;
+        } else if (et >= 0.0) {
+          double x = G[p * K + t] * dsc[p] * dsc[t];
+          for (int u = 0; u < s; ++u) {
+            const double* ru = G + (int64_t)perm[u] * K;
+            x -= ru[p] * ru[t];
+          }
+          val = x / piv;
+        }
+        G[p * K + t] = val;
+        e[t] = t == p ? -1.0 : (et >= 0.0 ? et - val * val : et);
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) s_int[h] = r;
+  __syncthreads();
+}
+
+// Back substitution y <- R^{-1} y with the r x r upper triangle R(i, j) =
+// F[perm[i] * K + perm[j]] of a factor from pivoted_cholesky_pair (copied to
+// LDS, column-major, when r * r <= buf_cap), for kk <= kMaxCap right-hand
+// sides Y (r x kk, column-major).  Each column is held in registers by a group
+// of tpc lanes of one wavefront (row j in lane j % tpc), so no workgroup
+// barrier is needed between the steps; groups of columns are taken in passes.
+// The solution rows are scattered into T (K x kk, column-major):
+// T[perm[j]][c] = dsc[perm[j]] y[j][c]; rows of non-pivot columns are zero.
+template <int NR>
+__device__ void tri_solve_rows(const double* R, int ldr, bool lds_tri, const double* F, int K, int r,
+                               const int* perm, const double* Y, int c, int kk, int tpc, double* T,
+                               const double* dsc) {
+  const int t = threadIdx.x % tpc;
+  const bool on = c < kk;
+  double x[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int j = t + k * tpc;
+    x[k] = (on && j < r) ? Y[c * r + j] : 0.0;
+  }
+  for (int i = r - 1; i >= 0; --i) {
+    const int owner = i % tpc, sl = i / tpc;
+    double xi = 0.0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k == sl) xi = x[k];
+    xi = __shfl(xi, owner, tpc);
+    const double yi = xi / (lds_tri ? R[i * ldr + i] : F[(int64_t)perm[i] * K + perm[i]]);
+    const int pi = perm[i];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int j = t + k * tpc;
+      if (k == sl && t == owner)
+        x[k] = yi;
+      else if (j < i)
+        x[k] -= (lds_tri ? R[i * ldr + j] : F[(int64_t)perm[j] * K + pi]) * yi;
+    }
+  }
+  if (on) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int j = t + k * tpc;
+      if (j < r) {
+        const int l = perm[j];
+        T[c * K + l] = dsc[l] * x[k];
+      }
+    }
+  }
+}
+
+__device__ void tri_solve_scatter(const double* F, int K, int r, const int* perm, const int* pos, const double* Y,
+                                  int kk, double* T, const double* dsc, double* buf, int buf_cap) {
   const int tid = threadIdx.x;
-  const int K = su.kc + su.kp + su.kp2;
-  const int m = su.m, n = sv.m;
-  int* s_int = (int*)(lds + kLdsBytes - 64);
-  if (K == 0) {
-    if (tid == 0) a.ranks[lr_index] = 0;
-    __syncthreads();
-    return 0;
-  }
-  if (K <= kSmallK) return trunc_core_small(a, d, lr_index, su, sv, lds, eps);
-  uint64_t tph = threadIdx.x == 0 ? wall_clock64() : 0;
-  if (a.counters && tid == 0) {
-    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
-    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
-  }
-  TruncScratch S = trunc_scratch(scratch);
-  double* sA = (double*)lds;
-  double* sB = sA + TK * (TM + TP);
-  // index and scale vectors always in LDS after the GEMM tiles
-  {
-    double* v = (double*)(lds + kTileBytes);
-    S.dU = v;
-    S.dV = v + kMaxK;
-    S.sig = v + 2 * kMaxK;
-    int* ip = (int*)(v + 3 * kMaxK);
-    S.pU = ip;
-    S.pV = ip + kMaxK;
-    S.sel = ip + 2 * kMaxK;
-    S.posU = ip + 3 * kMaxK;
-    S.posV = ip + 4 * kMaxK;
-  }
-  constexpr int kVecBytes = 3 * kMaxK * 8 + 5 * kMaxK * 4;
-  // K x K work matrices in LDS too when they fit
-  const bool small = (int64_t)kTileBytes + kVecBytes + (int64_t)4 * K * K * 8 + 64 <= kLdsBytes;
-  if (small) {
-    double* w = (double*)(lds + kTileBytes + kVecBytes);
-    S.GU = w;
-    S.GV = w + K * K;
-    S.B = w + 2 * K * K;
-    S.Z = w + 3 * K * K;
-  }
-  // 1. Gram matrices G_U = U_s^T U_s, G_V = V_s^T V_s (FP64)
-  gemm_tiles<double>(
-      K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
-      [&](int i, int j, double v) { S.GU[i * K + j] = v; }, true, true, sA, sB);
-  gemm_tiles<double>(
-      K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
-      [&](int i, int j, double v) { S.GV[i * K + j] = v; }, true, true, sA, sB);
+  const bool lds_tri = r * r <= buf_cap;
+  if (lds_tri)
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int i = e % r, j = e / r;  // column-major: buf[j * r + i] = R(i, j)
+      buf[e] = i <= j ? F[(int64_t)perm[i] * K + perm[j]] : 0.0;
+    }
+  for (int e = tid; e < K * kk; e += blockDim.x)
+    if (pos[e % K] >= r) T[e] = 0.0;
   __syncthreads();
-  phase_tick(a, kCtrPhase + 0, &tph);
-  // 2. R factors: wavefront 0 factors G_U, wavefront 1 factors G_V
-  if ((tid >> 6) == 0) {
-    int r = pivoted_cholesky_wave(S.GU, K, S.pU, S.dU);
-    if (tid == 0) s_int[0] = r;
-  } else if ((tid >> 6) == 1) {
-    int r = pivoted_cholesky_wave(S.GV, K, S.pV, S.dV);
-    if ((tid & 63) == 0) s_int[1] = r;
+  // lanes per column: enough that each holds at most 8 rows, more when few
+  // columns leave lanes idle
+  int tpc = 1;
+  while (tpc * 8 < r) tpc *= 2;
+  while (tpc < 64 && tpc * 2 * kk <= (int)blockDim.x) tpc *= 2;
+  const int per_pass = blockDim.x / tpc;
+  for (int c0 = 0; c0 < kk; c0 += per_pass) {
+    const int c = c0 + tid / tpc;
+    if ((r + tpc - 1) / tpc <= 4)
+      tri_solve_rows<4>(buf, r, lds_tri, F, K, r, perm, Y, c, kk, tpc, T, dsc);
+    else
+      tri_solve_rows<8>(buf, r, lds_tri, F, K, r, perm, Y, c, kk, tpc, T, dsc);
   }
   __syncthreads();
-  const int rU = s_int[0], rV = s_int[1];
-  phase_tick(a, kCtrPhase + 1, &tph);
-  if (rU == 0 || rV == 0) {
-    if (tid == 0) a.ranks[lr_index] = 0;
-    __syncthreads();
-    return 0;
-  }
-  for (int q = tid; q < K; q += blockDim.x) {
-    S.posU[S.pU[q]] = q;
-    S.posV[S.pV[q]] = q;
-  }
-  __syncthreads();
-  // 3. core B = Rt_U Rt_V^T with Rt[i][l] = R'[i][pos(l)] * ||column l||
-  //    (rU x rV, column-major).  R' is upper trapezoidal in pivoted order:
-  //    clear what lies left of its diagonal, then B[i][j] =
-  //    sum_l R'_U[i][posU l] R'_V[j][posV l] w[l], w[l] = ||u_l|| ||v_l||.
-  //    The core and its rotations go to LDS after the index vectors when they
-  //    fit there.
-  double* B = S.B;
-  double* Z = S.Z;
-  if (!small && (int64_t)kTileBytes + kVecBytes + (int64_t)(rU * rV + rV * rV) * 8 + 128 <= kLdsBytes) {
-    B = (double*)(lds + kTileBytes + kVecBytes);
-    Z = B + rU * rV;
-  }
-  for (int e = tid; e < rU * K; e += blockDim.x)
-    if (e % K < e / K) S.GU[e] = 0.0;
-  for (int e = tid; e < rV * K; e += blockDim.x)
-    if (e % K < e / K) S.GV[e] = 0.0;
-  for (int l = tid; l < K; l += blockDim.x) S.sig[l] = (S.dU[l] == 0.0 || S.dV[l] == 0.0) ? 0.0 : 1.0 / (S.dU[l] * S.dV[l]);
-  __syncthreads();
-  for (int e = tid; e < rU * rV; e += blockDim.x) {
-    const int i = e % rU, j = e / rU;
-    const double* ru = S.GU + i * K;
-    const double* rv = S.GV + j * K;
+}
+
+// Column norms of the rotated operand (p x q) give the singular values; the
+// selection sel[] lists the columns by decreasing value; returns the kept
+// count (sigma > eps sigma_1, then capped at the leaf's capacity).
+__device__ int select_kept(const ExecArgs& a, const LrDesc& d, const double* Bp, int p, int q, double* sig, int* sel,
+                           int* s_int, double eps) {
+  const int tid = threadIdx.x;
+  for (int j = tid; j < q; j += blockDim.x) {
     double s = 0.0;
-    for (int l = 0; l < K; ++l) s += ru[S.posU[l]] * rv[S.posV[l]] * S.sig[l];
-    B[j * rU + i] = s;
-  }
-  __syncthreads();
-  phase_tick(a, kCtrPhase + 2, &tph);
-  // 4. SVD of the core: columns of B Z are W_j sigma_j
-  if (tid < 64) jacobi_svd_wave(B, Z, rU, rV, eps);
-  __syncthreads();
-  phase_tick(a, kCtrPhase + 3, &tph);
-  for (int j = tid; j < rV; j += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
-    S.sig[j] = sqrt(s);
+    for (int r = 0; r < p; ++r) s += Bp[j * p + r] * Bp[j * p + r];
+    sig[j] = sqrt(s);
   }
   if (tid == 0) s_int[2] = 0;
   __syncthreads();
-  // 5. descending order and truncation rank: keep sigma > eps * sigma_1, then cap
   double smax = 0.0;
-  for (int j = 0; j < rV; ++j) smax = fmax(smax, S.sig[j]);
-  for (int j = tid; j < rV; j += blockDim.x) {
+  for (int j = 0; j < q; ++j) smax = fmax(smax, sig[j]);
+  for (int j = tid; j < q; j += blockDim.x) {
     int rk = 0;
-    for (int l = 0; l < rV; ++l)
-      if (S.sig[l] > S.sig[j] || (S.sig[l] == S.sig[j] && l < j)) ++rk;
-    S.sel[rk] = j;
-    if (smax > 0.0 && S.sig[j] > eps * smax) atomicAdd(&s_int[2], 1);
+    for (int l = 0; l < q; ++l)
+      if (sig[l] > sig[j] || (sig[l] == sig[j] && l < j)) ++rk;
+    sel[rk] = j;
+    if (smax > 0.0 && sig[j] > eps * smax) atomicAdd(&s_int[2], 1);
   }
   __syncthreads();
   int kk = s_int[2];
@@ -1117,53 +1224,201 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     if (tid == 0 && a.max_rank == 0) atomicAdd(&a.status[2], 1);
     kk = limit;
   }
-  if (kk == 0) {
-    if (tid == 0) a.ranks[lr_index] = 0;
-    __syncthreads();
-    return 0;
+  return kk;
+}
+
+__device__ int set_rank(const ExecArgs& a, int lr_index, int kk) {
+  if (threadIdx.x == 0) a.ranks[lr_index] = kk;
+  __syncthreads();
+  return kk;
+}
+
+// Dense route for a small leaf (p q + q^2 <= kLargeWork with p = max(m, n),
+// q = min(m, n)): M = U_s V_s^T is formed explicitly and its columns (or those
+// of M^T when n > m) are orthogonalised by one-sided Jacobi in LDS.  With
+// M' Z = W Sigma the kept triplets are written back directly: for M' = M,
+// U <- (M Z)_sel and V <- Z_sel; for M' = M^T, U <- Z_sel and V <- (M^T Z)_sel.
+__device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+                           char* lds, double* scratch, double eps, uint64_t* tph) {
+  const int tid = threadIdx.x;
+  const int K = su.kc + su.kp + su.kp2;
+  const int m = su.m, n = sv.m;
+  const bool tr = n > m;
+  const int p = tr ? n : m, q = tr ? m : n;
+  int* s_int = (int*)(lds + kLdsBytes - 64);
+  const LargeVecs v = large_vecs(lds);
+  double* sA = (double*)lds;
+  double* sB = sA + TK * (TM + TP);
+  double* Mg = scratch;  // p x q staging in global scratch
+  // 1. M' (p x q, column-major) = X Y^T with (X, Y) = (U_s, V_s) or (V_s, U_s)
+  if (!tr)
+    gemm_tiles<double>(
+        m, n, K, [&](int i, int l) { return su(a, i, l); }, [&](int l, int j) { return sv(a, j, l); },
+        [&](int i, int j, double x) { Mg[j * p + i] = x; }, false, false, sA, sB);
+  else
+    gemm_tiles<double>(
+        n, m, K, [&](int i, int l) { return sv(a, i, l); }, [&](int l, int j) { return su(a, j, l); },
+        [&](int i, int j, double x) { Mg[j * p + i] = x; }, false, false, sA, sB);
+  __syncthreads();
+  double* Mp = (double*)lds;
+  double* Z = Mp + p * q;
+  for (int e = tid; e < p * q; e += blockDim.x) Mp[e] = Mg[e];
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 6, tph);
+  // 2. one-sided Jacobi on M'
+  const int sw = jacobi_svd(Mp, Z, p, q, s_int, eps);
+  phase_tick(a, kCtrPhase + 9, tph);
+  // 3. kept triplets
+  const int kk = select_kept(a, d, Mp, p, q, v.sig, v.sel, s_int, eps);
+  trunc_note(lds, 2, p, q, sw, kk);
+  if (kk == 0) return set_rank(a, lr_index, 0);
+  RV uc{d.u_off, m, kk, 1, m, d.type};
+  RV vc{d.v_off, n, kk, 1, n, d.type};
+  for (int e = tid; e < m * kk; e += blockDim.x) {
+    const int i = e % m, c = e / m;
+    const int j = v.sel[c];
+    vst(a, uc, i, c, tr ? Z[j * q + i] : Mp[j * p + i]);
   }
-  // 6. T_U = D_U P_U E_r R'_U^{-1} (B Z)_sel,  T_V = D_V P_V E_r R'_V^{-1} Z_sel
+  for (int e = tid; e < n * kk; e += blockDim.x) {
+    const int i = e % n, c = e / n;
+    const int j = v.sel[c];
+    vst(a, vc, i, c, tr ? Mp[j * p + i] : Z[j * q + i]);
+  }
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 11, tph);
+  return set_rank(a, lr_index, kk);
+}
+
+// Gram route: R factors of U_s and V_s from their Gram matrices (pivoted
+// Cholesky), the core B = Rt_U W Rt_V^T (rU x rV, W = diag(||u_l|| ||v_l||)),
+// one-sided Jacobi on B or B^T (whichever has fewer columns), then
+//   U <- U_s D_U P_U R_U11^{-1} Y_U,  V <- V_s D_V P_V R_V11^{-1} Y_V
+// with (Y_U, Y_V) = ((B Z)_sel, Z_sel) or (Z_sel, (B^T Z)_sel).
+__device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+                          char* lds, double* scratch, double eps, uint64_t* tph) {
+  const int tid = threadIdx.x;
+  const int K = su.kc + su.kp + su.kp2;
+  const int m = su.m, n = sv.m;
+  int* s_int = (int*)(lds + kLdsBytes - 64);
+  const LargeVecs v = large_vecs(lds);
+  TruncScratch S = trunc_scratch(scratch);
+  double* sA = (double*)lds;
+  double* sB = sA + TK * (TM + TP);
+  double* W = (double*)lds;
+  // 1. Gram matrices, in LDS after the GEMM tiles when both fit
+  const bool g_lds = kTileDoubles + 2 * K * K <= kLargeWork;
+  double* GU = g_lds ? W + kTileDoubles : S.GU;
+  double* GV = g_lds ? GU + K * K : S.GV;
+  gemm_tiles<double>(
+      K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
+      [&](int i, int j, double x) { GU[i * K + j] = x; }, true, true, sA, sB);
+  gemm_tiles<double>(
+      K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
+      [&](int i, int j, double x) { GV[i * K + j] = x; }, true, true, sA, sB);
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 6, tph);
+  // 2. R factors
+  pivoted_cholesky_pair(GU, GV, K, v, s_int);
+  const int rU = s_int[0], rV = s_int[1];
+  if (g_lds) {  // the factors move to global scratch to free the work area
+    for (int e = tid; e < K * K; e += blockDim.x) {
+      S.GU[e] = GU[e];
+      S.GV[e] = GV[e];
+    }
+    GU = S.GU;
+    GV = S.GV;
+  }
+  for (int l = tid; l < K; l += blockDim.x) {
+    v.posU[l] = K;
+    v.posV[l] = K;
+  }
+  __syncthreads();
+  phase_tick(a, kCtrPhase + 7, tph);
+  if (rU == 0 || rV == 0) return set_rank(a, lr_index, 0);
+  for (int j = tid; j < rU; j += blockDim.x) v.posU[v.pU[j]] = j;
+  for (int j = tid; j < rV; j += blockDim.x) v.posV[v.pV[j]] = j;
+  for (int l = tid; l < K; l += blockDim.x)
+    v.sig[l] = (v.dU[l] == 0.0 || v.dV[l] == 0.0) ? 0.0 : 1.0 / (v.dU[l] * v.dV[l]);
+  __syncthreads();
+  // 3. core, oriented so that the SVD operand B' (p x q) has q = min(rU, rV)
+  const bool tr = rV > rU;
+  const int p = tr ? rV : rU, q = tr ? rU : rV;
+  const bool b_lds = p * q + q * q <= kLargeWork;
+  double* Bg = S.B;
+  gemm_tiles<double>(
+      rU, rV, K, [&](int i, int l) { return GU[(int64_t)v.pU[i] * K + l] * v.sig[l]; },
+      [&](int l, int j) { return GV[(int64_t)v.pV[j] * K + l]; },
+      [&](int i, int j, double x) {
+        if (tr)
+          Bg[i * p + j] = x;
+        else
+          Bg[j * p + i] = x;
+      },
+      true, true, sA, sB);
+  __syncthreads();
+  double* Bp = Bg;
+  double* Z = S.Z;
+  if (b_lds) {
+    Bp = W;
+    Z = W + p * q;
+    for (int e = tid; e < p * q; e += blockDim.x) Bp[e] = Bg[e];
+    __syncthreads();
+  }
+  phase_tick(a, kCtrPhase + 8, tph);
+  // 4. SVD of the core
+  const int sw = jacobi_svd(Bp, Z, p, q, s_int, eps);
+  phase_tick(a, kCtrPhase + 9, tph);
+  const int kk = select_kept(a, d, Bp, p, q, v.sig, v.sel, s_int, eps);
+  trunc_note(lds, b_lds ? 3 : 4, p, q, sw, kk);
+  if (kk == 0) return set_rank(a, lr_index, 0);
+  // 5. Y_U (rU x kk), Y_V (rV x kk)
   for (int e = tid; e < rU * kk; e += blockDim.x) {
-    int i = e % rU, c = e / rU;
-    S.YU[c * rU + i] = B[S.sel[c] * rU + i];
+    const int i = e % rU, c = e / rU, j = v.sel[c];
+    S.YU[e] = tr ? Z[j * q + i] : Bp[j * p + i];
   }
   for (int e = tid; e < rV * kk; e += blockDim.x) {
-    int i = e % rV, c = e / rV;
-    S.YV[c * rV + i] = Z[S.sel[c] * rV + i];
+    const int i = e % rV, c = e / rV, j = v.sel[c];
+    S.YV[e] = tr ? Bp[j * p + i] : Z[j * q + i];
   }
   __syncthreads();
-  // the core and its rotations are no longer needed: solve in their place
-  double* yu = B;  // rU x kk <= rU x rV
-  double* yv = Z;  // rV x kk <= rV x rV
-  for (int e = tid; e < rU * kk; e += blockDim.x) yu[e] = S.YU[e];
-  for (int e = tid; e < rV * kk; e += blockDim.x) yv[e] = S.YV[e];
-  __syncthreads();
-  upper_solve(S.GU, K, rU, yu, kk);
-  upper_solve(S.GV, K, rV, yv, kk);
-  __syncthreads();
-  for (int e = tid; e < K * kk; e += blockDim.x) {
-    int l = e % K, c = e / K;
-    int qu = S.posU[l], qv = S.posV[l];
-    S.TU[c * K + l] = qu < rU ? S.dU[l] * yu[c * rU + qu] : 0.0;
-    S.TV[c * K + l] = qv < rV ? S.dV[l] * yv[c * rV + qv] : 0.0;
-  }
-  __syncthreads();
-  phase_tick(a, kCtrPhase + 4, &tph);
-  // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile since
-  //    kk <= 64, so every row tile is read completely before it is overwritten)
+  // 6. T_U, T_V (K x kk) by back substitution with the pivoted triangles
+  tri_solve_scatter(GU, K, rU, v.pU, v.posU, S.YU, kk, S.TU, v.dU, W, kLargeWork);
+  tri_solve_scatter(GV, K, rV, v.pV, v.posV, S.YV, kk, S.TV, v.dV, W, kLargeWork);
+  phase_tick(a, kCtrPhase + 10, tph);
+  // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile
+  //    since kk <= 64, so every row tile is read completely before it is
+  //    overwritten)
   RV uc{d.u_off, m, kk, 1, m, d.type};
   RV vc{d.v_off, n, kk, 1, n, d.type};
   gemm_tiles<double>(
       m, kk, K, [&](int r, int l) { return su(a, r, l); }, [&](int l, int c) { return S.TU[c * K + l]; },
-      [&](int r, int c, double v) { vst(a, uc, r, c, v); }, false, true, sA, sB);
+      [&](int r, int c, double x) { vst(a, uc, r, c, x); }, false, true, sA, sB);
   gemm_tiles<double>(
       n, kk, K, [&](int r, int l) { return sv(a, r, l); }, [&](int l, int c) { return S.TV[c * K + l]; },
-      [&](int r, int c, double v) { vst(a, vc, r, c, v); }, false, true, sA, sB);
+      [&](int r, int c, double x) { vst(a, vc, r, c, x); }, false, true, sA, sB);
   __syncthreads();
-  phase_tick(a, kCtrPhase + 5, &tph);
-  if (tid == 0) a.ranks[lr_index] = kk;
-  __syncthreads();
-  return kk;
+  phase_tick(a, kCtrPhase + 11, tph);
+  return set_rank(a, lr_index, kk);
+}
+
+// Returns the new rank.
+__device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+                          char* lds, double* scratch, double eps) {
+  const int tid = threadIdx.x;
+  const int K = su.kc + su.kp + su.kp2;
+  const int m = su.m, n = sv.m;
+  trunc_note(lds, 0, 0, 0, 0, 0);
+  if (K == 0) return set_rank(a, lr_index, 0);
+  if (K <= kSmallK) return trunc_core_small(a, d, lr_index, su, sv, lds, eps);
+  uint64_t tph = tid == 0 ? wall_clock64() : 0;
+  if (a.counters && tid == 0) {
+    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
+    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
+  }
+  const int p = max(m, n), q = min(m, n);
+  if ((int64_t)p * q + (int64_t)q * q <= kLargeWork && 4 * K >= 3 * q)
+    return trunc_dense(a, d, lr_index, su, sv, lds, scratch, eps, &tph);
+  return trunc_gram(a, d, lr_index, su, sv, lds, scratch, eps, &tph);
 }
 
 // OP_TRUNC:  C <- T(C + alpha pad(a) pad(b)^T)
@@ -1262,16 +1517,24 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
       atomicAdd(&a.counters[kCtrBusy + t.op], (unsigned long long)(t1 - t0));
       atomicAdd(&a.counters[kCtrCount + t.op], 1ull);
       if (a.trace) {
-        a.trace[3 * (int64_t)id] = t0;
-        a.trace[3 * (int64_t)id + 1] = t1;
+        a.trace[4 * (int64_t)id] = t0;
+        a.trace[4 * (int64_t)id + 1] = t1;
         uint64_t info = blockIdx.x & 0xffff;
         if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
           const LrDesc d = a.lr[t.lr];
           uint64_t K = (uint64_t)resolve(a, t.a).cols;
           if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
-          info |= (K & 0xffff) << 16 | (uint64_t)(d.m + d.n) << 32;
+          info |= (K & 0xffff) << 16 | (uint64_t)(d.m & 0xffff) << 32 | (uint64_t)(d.n & 0xffff) << 48;
         }
-        a.trace[3 * (int64_t)id + 2] = info;
+        a.trace[4 * (int64_t)id + 2] = info;
+        uint64_t info2 = 0;
+        if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
+          const int* s_int = (const int*)(lds + kLdsBytes - 64);
+          info2 = (uint64_t)(s_int[12] & 0xff) | (uint64_t)(s_int[13] & 0xfff) << 8 |
+                  (uint64_t)((s_int[13] >> 16) & 0xfff) << 20 | (uint64_t)(s_int[14] & 0xff) << 32 |
+                  (uint64_t)((s_int[14] >> 16) & 0xff) << 40;
+        }
+        a.trace[4 * (int64_t)id + 3] = info2;
       }
     }
   }

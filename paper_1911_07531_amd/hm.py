@@ -39,7 +39,7 @@ class LuStats(C.Structure):
     _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
                 ("tasks_by_op", C.c_int64 * 12), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
                 ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64),
-                ("op_busy_ms", C.c_double * 12), ("trunc_phase_ms", C.c_double * 6),
+                ("op_busy_ms", C.c_double * 12), ("trunc_phase_ms", C.c_double * 12),
                 ("trunc_mean_k", C.c_double), ("trunc_mean_mn", C.c_double)]
 
 
@@ -287,7 +287,8 @@ class LU:
         s = LuStats()
         _check(lib().hm_lu_stats_get(self.h, C.byref(s)))
         d = {f: getattr(s, f) for f, _ in LuStats._fields_ if f not in ("tasks_by_op", "op_busy_ms", "trunc_phase_ms")}
-        d["trunc_phase_ms"] = dict(zip(["gram", "cholesky", "core", "svd", "solve", "rebuild"],
+        ph = ["gram", "cholesky", "core", "svd", "solve", "rebuild"]
+        d["trunc_phase_ms"] = dict(zip([f"{x}_small" for x in ph] + [f"{x}_large" for x in ph],
                                        [float(x) for x in s.trunc_phase_ms]))
         d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(11) if s.tasks_by_op[i]}
         d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(11) if s.tasks_by_op[i]}
@@ -297,10 +298,13 @@ class LU:
         return export_leaf(self.h, 1, block, self.tree)
 
     def timeline(self):
-        """(ntasks, 3) uint64 (start, end, workgroup) and the tick rate in kHz (needs HM_DEBUG_TRACE=1)."""
+        """(ntasks, 4) uint64 (start, end, info, info2) and the tick rate in kHz (needs HM_DEBUG_TRACE=1);
+        info: workgroup in bits 0-15, for truncations term width / m / n in bits 16-31 / 32-47 / 48-63;
+        info2 (truncations): route / SVD rows / SVD columns / sweeps / rank in bits 0-7 / 8-19 / 20-31 /
+        32-39 / 40-47."""
         n, khz = C.c_int64(), C.c_int64()
         _check(lib().hm_lu_trace(self.h, None, C.byref(n), C.byref(khz)))
-        out = np.zeros((n.value, 3), np.uint64)
+        out = np.zeros((n.value, 4), np.uint64)
         _check(lib().hm_lu_trace(self.h, out.ctypes.data, C.byref(n), C.byref(khz)))
         return out, khz.value
 
