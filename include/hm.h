@@ -159,13 +159,17 @@ hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* da
 
 /* Per-task timeline of the last h_lu on F, recorded only when the
  * environment variable HM_DEBUG_TRACE=1 was set before h_lu: out (may be
- * NULL to query sizes) receives ntasks x 4 uint64 (start tick, end tick,
- * info, info2) in trace order; ticks count at clock_khz kHz.  info bits 0-15
+ * NULL to query sizes) receives ntasks x 8 uint64 (start tick, end tick,
+ * info, info2, three words of truncation-phase ticks, spare) in trace order;
+ * ticks count at clock_khz kHz.  info bits 0-15
  * hold the workgroup; for truncations bits 16-31 the width of the added
  * terms and bits 32-47 / 48-63 the rows m / columns n of the low-rank leaf,
- * and info2 the route (bits 0-7: 1 small-rank, 2 dense, 3 / 4 Gram with the
- * core in LDS / global memory), the SVD operand's rows p and columns q (bits
- * 8-19, 20-31), the Jacobi sweeps (32-39) and the new rank (40-47). */
+ * and info2 the route (bits 0-7: 1 small-rank, 2 / 3 dense / Gram with a
+ * QR-reduced core SVD, 4 / 5 dense / Gram with a full core SVD), the SVD
+ * operand's rows p and columns q (bits 8-19, 20-31), the Jacobi sweeps
+ * (32-39) and the new rank (40-47).  Words 4-6 hold the ticks of the six
+ * truncation phases (Gram, factor, core, SVD, solve, rebuild), two 32-bit
+ * counts per word, low half first. */
 hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz);
 
 /* Statistics of the last h_lu on F. */

@@ -197,12 +197,12 @@ static hm_status device_setup() {
   int rate = 0;
   if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate <= 0) rate = 100000;
   g_clock_khz = rate;
-  (void)hipFuncSetAttribute((const void*)exec_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  (void)hipFuncSetAttribute((const void*)exec_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)exec_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsBytes);
+                            kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)exec_dataflow_kernel, kThreads, kLdsBytes) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)exec_dataflow_kernel, kThreads, kLdsExecBytes) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -224,9 +224,9 @@ static const int64_t kScratchPerWg = kScratchDoubles;
 // class an eighth); a larger ring means fewer orderings from reuse.
 // HM_TEMP_BUDGET_GB overrides it.
 static int64_t temp_budget() {
-  int64_t gb = 16;
-  if (const char* e = getenv("HM_TEMP_BUDGET_GB")) gb = std::max(1, atoi(e));
-  return gb << 30;
+  double gb = 16.0;
+  if (const char* e = getenv("HM_TEMP_BUDGET_GB")) gb = std::max(1e-4, atof(e));
+  return (int64_t)(gb * (double)(1ll << 30));
 }
 
 static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out) {
@@ -323,7 +323,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     for (int64_t l = 0; l < dd.nlevels; ++l) {
       int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
       int grid = std::min(e - b, g_nwg);
-      hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsBytes, s, a,
+      hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
                          (const int32_t*)dd.order.p, b, e);
     }
     HIPCHK(hipGetLastError());
@@ -334,7 +334,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
                        (const int32_t*)dd.roots.p, dd.nroots);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsBytes, s, a);
+    hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, s));
   }
@@ -737,7 +737,7 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
   // HM_DEBUG_TRACE=1 records (start, end, workgroup) of every H-LU task
   if (const char* e = getenv("HM_DEBUG_TRACE"))
-    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * 32, s))
+    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * kTraceWords * 8, s))
       return fail(HM_ENOMEM, "device allocation failed (trace)");
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
   // copy A into the factor layout
@@ -826,7 +826,7 @@ hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_kh
   if (clock_khz) *clock_khz = g_clock_khz;
   if (!out) return HM_OK;
   if (!F->lu_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
-  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * 32, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * kTraceWords * 8, hipMemcpyDeviceToHost));
   return HM_OK;
 }
 

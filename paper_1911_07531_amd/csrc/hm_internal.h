@@ -138,6 +138,13 @@ constexpr int64_t kScratchDoubles = 4 * kMaxK * kMaxK + 4 * kMaxK * kMaxCap + 6 
 
 constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COUNT, kCtrK = kCtrPhase + 12,
               kCtrMN = kCtrK + 1, kCtrSize = kCtrMN + 1;
+// dynamic LDS of the executor kernels: the task work area, then the
+// workgroup's statistics counters (flushed to ExecArgs::counters at exit),
+// then the current task's six truncation-phase tick counts (trace only)
+constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8;
+// words per task of the debug trace: start, end, info, info2, three words of
+// phase ticks (two 32-bit counts each), spare
+constexpr int kTraceWords = 8;
 
 enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4 };
 

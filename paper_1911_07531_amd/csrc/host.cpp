@@ -254,6 +254,11 @@ struct Rec {
 };
 struct ObjState {
   std::vector<Rec> writes, reads;
+  // temporaries: accesses of the slot's earlier occupants (rectangles in
+  // their own shapes, so they are kept whole: every access of this object
+  // orders after them until a write covers the object's full extent)
+  std::vector<Rec> inh_w, inh_r;
+  Rect full{0, 0, 0, 0};
 };
 
 enum { ACC_R = 1, ACC_W = 2, ACC_RW = 3 };
@@ -381,13 +386,32 @@ class Tracer {
     while (slot >= (int64_t)pool.off.size()) {
       temp_top_ = align_up(temp_top_, 32);
       pool.off.push_back(temp_top_);
-      pool.obj.push_back(new_obj());
+      pool.obj.push_back(-1);
       pool.pins.push_back(0);
       temp_top_ += sz;
     }
+    // a fresh object per occupant; the previous occupant (possibly of another
+    // shape, so its rectangles do not compare with ours) hands over its
+    // accesses, and any it had inherited itself
+    const int ob = new_obj();
+    const int prev = pool.obj[slot];
+    if (prev >= 0) {
+      ObjState& po = objs_[prev];
+      ObjState& no = objs_[ob];
+      no.inh_w = std::move(po.inh_w);
+      no.inh_r = std::move(po.inh_r);
+      no.inh_w.insert(no.inh_w.end(), po.writes.begin(), po.writes.end());
+      no.inh_r.insert(no.inh_r.end(), po.reads.begin(), po.reads.end());
+      std::vector<Rec>().swap(po.writes);
+      std::vector<Rec>().swap(po.reads);
+      std::vector<Rec>().swap(po.inh_w);
+      std::vector<Rec>().swap(po.inh_r);
+    }
+    objs_[ob].full = Rect{0, r, 0, cols};
+    pool.obj[slot] = ob;
     HView h;
     h.v = View{pool.off[slot], r, cols, 1, r, temp_type_, dyn_rank_id >= 0 ? DYN_COLS : 0, dyn_rank_id, 0};
-    h.obj = pool.obj[slot];
+    h.obj = ob;
     h.rect = Rect{0, r, 0, cols};
     h.tr = false;
     h.pool_cls = cls;
@@ -947,6 +971,18 @@ class Tracer {
   }
   void access(int task, int obj, const Rect& r, bool write) {
     ObjState& o = objs_[obj];
+    if (!o.inh_w.empty() || !o.inh_r.empty()) {
+      for (auto& w : o.inh_w)
+        if (w.task != task) preds_.push_back(w.task);
+      if (write) {
+        for (auto& rd : o.inh_r)
+          if (rd.task != task) preds_.push_back(rd.task);
+        if (covers(r, o.full)) {
+          std::vector<Rec>().swap(o.inh_w);
+          std::vector<Rec>().swap(o.inh_r);
+        }
+      }
+    }
     for (auto& w : o.writes)
       if (w.task != task && overlap(w.r, r)) preds_.push_back(w.task);
     if (write) {

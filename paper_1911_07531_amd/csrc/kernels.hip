@@ -614,15 +614,19 @@ __device__ void upper_solve(const double* R, int K, int r, double* X, int kk) {
   }
 }
 
-// Adds the wall-clock ticks since *t0 to counters[slot] (thread 0) and restarts *t0.
-__device__ __forceinline__ void phase_tick(const ExecArgs& a, int slot, uint64_t* t0) {
+// Statistics counters of the workgroup (after the task work area in LDS);
+// only touched when ExecArgs::counters is set, by thread 0.
+__device__ __forceinline__ unsigned long long* wg_ctr(char* lds) { return (unsigned long long*)(lds + kLdsBytes); }
+
+// Adds the wall-clock ticks since *t0 to counter slot (thread 0) and restarts *t0.
+__device__ __forceinline__ void phase_tick(const ExecArgs& a, char* lds, int slot, uint64_t* t0) {
   if (a.counters && threadIdx.x == 0) {
     uint64_t t1 = wall_clock64();
-    atomicAdd(&a.counters[slot], (unsigned long long)(t1 - *t0));
+    wg_ctr(lds)[slot] += t1 - *t0;
+    if (a.trace) wg_ctr(lds)[kCtrSize + (slot - kCtrPhase) % 6] += t1 - *t0;
     *t0 = t1;
   }
 }
-
 
 // ---------------------------------------------------------------------------
 // Truncation for stacked ranks K <= 32: every K x K work matrix in LDS, the
@@ -639,6 +643,75 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One column of a stacked panel resolved once: stack row r reads element
+// (r - lo) of the column at `base` with row stride rs (zero outside
+// [lo, hi)), times `scale`; an identity column is `scale` at row `one`.
+struct ColRef {
+  const double* p64;
+  const float* p32;
+  int64_t base;
+  int rs, lo, hi, one;
+  double scale;
+  __device__ __forceinline__ double operator()(int r) const {
+    if (r < lo || r >= hi) return 0.0;
+    if (one >= 0) return r == one ? scale : 0.0;
+    const int64_t k = base + (int64_t)(r - lo) * rs;
+    return scale * (p64 ? p64[k] : (double)p32[k]);
+  }
+};
+
+__device__ __forceinline__ ColRef col_of(const RV& v, const ExecArgs& a, int j, int lo, int hi, double scale) {
+  ColRef c;
+  c.p64 = v.type == VT_F64 ? a.f64 : nullptr;
+  c.p32 = v.type == VT_F32 ? a.f32 : nullptr;
+  c.base = v.off + (int64_t)j * v.cs;
+  c.rs = v.rs;
+  c.lo = lo;
+  c.hi = (v.type == VT_F64 || v.type == VT_F32 || v.type == VT_IDENT) ? hi : lo;
+  c.one = v.type == VT_IDENT ? lo + j : -1;
+  c.scale = scale;
+  return c;
+}
+
+__device__ __forceinline__ ColRef stack_col(const ExecArgs& a, const Stack& st, int i) {
+  if (i < st.kc) return col_of(st.c, a, i, 0, st.m, 1.0);
+  i -= st.kc;
+  if (i < st.kp) {
+    ColRef c = col_of(st.t, a, i, st.r0, min(st.m, st.r0 + st.t.rows), st.alpha);
+    if (st.tptr) {  // term 1 outside the arenas (column-major, ld t.cs)
+      c.p64 = st.tptr;
+      c.p32 = nullptr;
+      c.base = (int64_t)i * st.t.cs;
+      c.rs = 1;
+      c.hi = min(st.m, st.r0 + st.t.rows);
+      c.one = -1;
+    }
+    return c;
+  }
+  i -= st.kp;
+  return col_of(st.t2, a, i, st.r2, min(st.m, st.r2 + st.t2.rows), st.alpha2);
+}
+
+// Copies rows [r0, r0 + rows) of the stacked panel st (K columns) into buf
+// (column c at buf + c * ld), four columns at a time so that several loads
+// per thread are in flight.
+__device__ __forceinline__ void stage_rows(const ExecArgs& a, const Stack& st, int K, int r0, int rows, double* buf,
+                                           int ld) {
+  for (int c0 = 0; c0 < K; c0 += 4) {
+    ColRef cr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cr[u] = stack_col(a, st, min(c0 + u, K - 1));
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = cr[u](r0 + i);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c0 + u < K) buf[(c0 + u) * ld + i] = v[u];
+    }
+  }
+}
+
 // G = X^T X (K x K, row-major) for X = the stacked panel st (m x K), staged
 // through LDS in chunks of up to `cap_rows` rows.
 __device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, double* G, double* buf, int cap_rows) {
@@ -647,10 +720,7 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, do
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // K*K <= 1024 entries: at most 4 per thread
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    for (int e = tid; e < rows * K; e += blockDim.x) {
-      int i = e % rows, c = e / rows;
-      buf[c * ld + i] = st(a, r0 + i, c);
-    }
+    stage_rows(a, st, K, r0, rows, buf, ld);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -829,10 +899,7 @@ __device__ void rebuild_stream(const ExecArgs& a, const Stack& st, int K, int m,
   const int ld = cap_rows | 1;
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    for (int e = tid; e < rows * K; e += blockDim.x) {
-      int i = e % rows, c = e / rows;
-      buf[c * ld + i] = st(a, r0 + i, c);
-    }
+    stage_rows(a, st, K, r0, rows, buf, ld);
     __syncthreads();
     for (int e = tid; e < rows * kk; e += blockDim.x) {
       int i = e % rows, c = e / rows;
@@ -846,8 +913,9 @@ __device__ void rebuild_stream(const ExecArgs& a, const Stack& st, int K, int m,
 }
 
 // Debug note of a truncation for the per-task trace (thread 0, LDS flag
-// words 12..14): route (1 small-rank, 2 dense, 3 Gram with the core in LDS,
-// 4 Gram with the core in global memory), SVD operand p x q, sweeps, rank.
+// words 12..14): route (1 small-rank, 2 dense with QR, 3 Gram with QR,
+// 4 dense with a full SVD, 5 Gram with a full SVD), SVD operand p x q,
+// sweeps, rank.
 __device__ __forceinline__ void trunc_note(char* lds, int route, int p, int q, int sweeps, int kk) {
   if (threadIdx.x == 0) {
     int* s_int = (int*)(lds + kLdsBytes - 64);
@@ -865,8 +933,8 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   int* s_int = (int*)(lds + kLdsBytes - 64);
   uint64_t tph = tid == 0 ? wall_clock64() : 0;
   if (a.counters && tid == 0) {
-    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
-    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
+    wg_ctr(lds)[kCtrK] += K;
+    wg_ctr(lds)[kCtrMN] += m + n;
   }
   // LDS: [G_U | G_V | B | Z | T_U | T_V] (K*K each), vectors at the end, the
   // Gram staging buffer over B..T_V and beyond
@@ -891,7 +959,7 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   gram_stream(a, su, K, m, GU, buf, cap_rows);
   gram_stream(a, sv, K, n, GV, buf, cap_rows);
   __syncthreads();
-  phase_tick(a, kCtrPhase + 0, &tph);
+  phase_tick(a, lds, kCtrPhase + 0, &tph);
   // 2. R factors: wavefront 0 factors G_U, wavefront 1 factors G_V
   if (wave == 0) {
     int r = pivoted_cholesky_wave(GU, K, pU, dU);
@@ -902,7 +970,7 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   }
   __syncthreads();
   const int rU = s_int[0], rV = s_int[1];
-  phase_tick(a, kCtrPhase + 1, &tph);
+  phase_tick(a, lds, kCtrPhase + 1, &tph);
   if (rU == 0 || rV == 0) {
     if (tid == 0) a.ranks[lr_index] = 0;
     __syncthreads();
@@ -928,14 +996,14 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
     B[j * rU + i] = s;
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 2, &tph);
+  phase_tick(a, lds, kCtrPhase + 2, &tph);
   // 4. SVD of the core by wavefront 0
   if (wave == 0) {
     const int sw = jacobi_svd_wave(B, Z, rU, rV, eps);
     trunc_note(lds, 1, rU, rV, sw, 0);
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 3, &tph);
+  phase_tick(a, lds, kCtrPhase + 3, &tph);
   // 5. order, truncation rank
   for (int j = tid; j < rV; j += blockDim.x) {
     double s = 0.0;
@@ -991,7 +1059,7 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
     T_V[c * K + l] = qv < rV ? dV[l] * yv[c * rV + qv] : 0.0;
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 4, &tph);
+  phase_tick(a, lds, kCtrPhase + 4, &tph);
   // 7. rebuild in place (staging buffer after T_U / T_V in the B / Z region)
   {
     double* rbuf = Z + K * K;
@@ -1000,7 +1068,7 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
     rebuild_stream(a, sv, K, n, T_V, kk, RV{d.v_off, n, kk, 1, n, d.type}, rbuf, rcap);
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 5, &tph);
+  phase_tick(a, lds, kCtrPhase + 5, &tph);
   if (tid == 0) a.ranks[lr_index] = kk;
   __syncthreads();
   return kk;
@@ -1011,13 +1079,13 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
 // (GEMM tiles, Gram matrices, the SVD operand and its rotations, a triangle),
 // then the per-column vectors, then 64 bytes of flags.
 // ---------------------------------------------------------------------------
-constexpr int kLargeVecBytes = 5 * kMaxK * 8 + 5 * kMaxK * 4;
+constexpr int kLargeVecBytes = 7 * kMaxK * 8 + 7 * kMaxK * 4;
 constexpr int kLargeWork = (kLdsBytes - 64 - kLargeVecBytes) / 8;  // doubles
 constexpr int kTileDoubles = kTileBytes / 8;
 
 struct LargeVecs {
-  double *dU, *dV, *eU, *eV, *sig;
-  int *pU, *pV, *sel, *posU, *posV;
+  double *dU, *dV, *eU, *eV, *sig, *qa, *qb;
+  int *pU, *pV, *sel, *posU, *posV, *qpos, *qpiv;
 };
 
 __device__ LargeVecs large_vecs(char* lds) {
@@ -1028,12 +1096,16 @@ __device__ LargeVecs large_vecs(char* lds) {
   v.eU = p + 2 * kMaxK;
   v.eV = p + 3 * kMaxK;
   v.sig = p + 4 * kMaxK;
-  int* ip = (int*)(p + 5 * kMaxK);
+  v.qa = p + 5 * kMaxK;
+  v.qb = p + 6 * kMaxK;
+  int* ip = (int*)(p + 7 * kMaxK);
   v.pU = ip;
   v.pV = ip + kMaxK;
   v.sel = ip + 2 * kMaxK;
   v.posU = ip + 3 * kMaxK;
   v.posV = ip + 4 * kMaxK;
+  v.qpos = ip + 5 * kMaxK;
+  v.qpiv = ip + 6 * kMaxK;
   return v;
 }
 
@@ -1233,11 +1305,167 @@ __device__ int set_rank(const ExecArgs& a, int lr_index, int kk) {
   return kk;
 }
 
-// Dense route for a small leaf (p q + q^2 <= kLargeWork with p = max(m, n),
-// q = min(m, n)): M = U_s V_s^T is formed explicitly and its columns (or those
-// of M^T when n > m) are orthogonalised by one-sided Jacobi in LDS.  With
-// M' Z = W Sigma the kept triplets are written back directly: for M' = M,
-// U <- (M Z)_sel and V <- Z_sel; for M' = M^T, U <- Z_sel and V <- (M^T Z)_sel.
+// Truncated SVD of an operand B' (p x q, column-major, read-only in global
+// memory, q <= kMaxK) through Householder QR with column pivoting stopped
+// early: after r steps the trailing columns have Frobenius norm at most
+// 0.1 eps times the largest column norm (<= 0.1 eps sigma_1), so B' = Q R + E
+// with R r x q (upper triangular up to the column order).  One-sided Jacobi on
+// R^T (q x r) then gives R^T Z = W Sigma: the right singular vectors of B' are
+// the columns of W, the left ones times Sigma are B' W.  On return Vc (q x kk,
+// column-major, global) holds the kept columns of W by decreasing singular
+// value; the caller forms B' Vc.  Returns kk, or -1 when r would exceed the
+// room left in LDS (the caller then diagonalises B' in full).  gwork (p * q
+// doubles of global scratch) holds the work copy when it does not fit in LDS.
+__device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int p, int q, double* Vc, char* lds,
+                      double* gwork, const LargeVecs& v, double eps, int* sweeps) {
+  const int tid = threadIdx.x;
+  int* s_int = (int*)(lds + kLdsBytes - 64);
+  double* W = (double*)lds;
+  const int rmax = min(p, q);
+  constexpr int kReserve = 40;
+  const int rres = min(rmax, kReserve);
+  const bool x_lds = (int64_t)p * q + (int64_t)q * rres + rres * rres <= kLargeWork;
+  double* X = x_lds ? W : gwork;
+  double* rest = x_lds ? W + p * q : W;
+  const int room = kLargeWork - (x_lds ? p * q : 0);
+  int rl = 0;
+  while (rl < rmax && q * (rl + 1) + (rl + 1) * (rl + 1) <= room) ++rl;
+  for (int e = tid; e < p * q; e += blockDim.x) X[e] = Bg[e];
+  __syncthreads();
+  // lanes per column: the largest power of two with tpc * q <= 256 (<= 64)
+  int tpc = 1;
+  while (tpc < 64 && tpc * 2 * q <= (int)blockDim.x) tpc *= 2;
+  const int g = tid / tpc, lt = tid % tpc;
+  double* cn = v.eU;  // squared norms of the trailing columns
+  if (g < q) {
+    double acc = 0.0;
+    for (int i = lt; i < p; i += tpc) acc += X[g * p + i] * X[g * p + i];
+    for (int off = tpc / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, tpc);
+    if (lt == 0) {
+      cn[g] = acc;
+      v.qpos[g] = kMaxK;
+    }
+  }
+  __syncthreads();
+  // tolerance from the largest column norm
+  if (tid < 64) {
+    double mx = 0.0;
+    for (int j = tid; j < q; j += 64) mx = fmax(mx, cn[j]);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (tid == 0) *(double*)(s_int + 4) = 0.01 * eps * eps * mx;
+  }
+  __syncthreads();
+  const double tol2 = *(const double*)(s_int + 4);
+  int r = 0;
+  for (int st = 0;; ++st) {
+    // (a) pivot: the largest trailing column; stop once the trailing block is small
+    if (tid < 64) {
+      double best = -1.0, sum = 0.0;
+      int bi = q;
+      for (int j = tid; j < q; j += 64)
+        if (v.qpos[j] == kMaxK) {
+          const double x = cn[j];
+          sum += x;
+          if (x > best) {
+            best = x;
+            bi = j;
+          }
+        }
+      for (int off = 32; off >= 1; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        int code = 1;                                   // go on
+        if (st == rmax || bi >= q || sum <= tol2 || !(best > 0.0)) code = 0;  // done
+        else if (st == rl) code = 2;                    // no room for another step
+        s_int[8] = code;
+        s_int[9] = bi;
+        if (code == 1) {
+          v.qpos[bi] = st;
+          v.qpiv[st] = bi;
+        }
+      }
+    }
+    __syncthreads();
+    const int code = s_int[8];
+    if (code == 2) return -1;
+    if (code == 0) {
+      r = st;
+      break;
+    }
+    const int jp = s_int[9];
+    double* xp = X + jp * p;
+    // (b) Householder vector of the pivot column (rows st..p-1), in place
+    if (tid < 64) {
+      double nrm2 = 0.0;
+      for (int i = st + tid; i < p; i += 64) nrm2 += xp[i] * xp[i];
+      for (int off = 32; off >= 1; off >>= 1) nrm2 += __shfl_xor(nrm2, off);
+      if (tid == 0) {
+        const double x0 = xp[st];
+        const double nr = sqrt(nrm2);
+        const double al = x0 >= 0.0 ? -nr : nr;
+        const double v0 = x0 - al;
+        const double vtv = nrm2 - x0 * x0 + v0 * v0;
+        xp[st] = v0;
+        v.qa[st] = al;
+        v.qb[st] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      }
+    }
+    __syncthreads();
+    // (c) apply to every trailing column and refresh its norm below row st
+    const double be = v.qb[st];
+    if (g < q && v.qpos[g] == kMaxK) {
+      double* xj = X + g * p;
+      double w = 0.0;
+      for (int i = st + lt; i < p; i += tpc) w += xp[i] * xj[i];
+      for (int off = tpc / 2; off >= 1; off >>= 1) w += __shfl_xor(w, off, tpc);
+      const double f = be * w;
+      double nn = 0.0;
+      for (int i = st + lt; i < p; i += tpc) {
+        const double y = xj[i] - f * xp[i];
+        xj[i] = y;
+        if (i > st) nn += y * y;
+      }
+      for (int off = tpc / 2; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, tpc);
+      if (lt == 0) cn[g] = nn;
+    }
+    __syncthreads();
+  }
+  if (r == 0) {
+    *sweeps = 0;
+    return 0;
+  }
+  // R^T (q x r, column-major: column s is row s of R) and its rotations
+  double* Rt = rest;
+  double* Zb = Rt + q * r;
+  for (int e = tid; e < q * r; e += blockDim.x) {
+    const int j = e % q, s2 = e / q;
+    const int pj = v.qpos[j];
+    Rt[e] = pj == s2 ? v.qa[s2] : (pj > s2 ? X[j * p + s2] : 0.0);
+  }
+  __syncthreads();
+  *sweeps = jacobi_svd(Rt, Zb, q, r, s_int, eps);
+  const int kk = select_kept(a, d, Rt, q, r, v.sig, v.sel, s_int, eps);
+  for (int e = tid; e < q * kk; e += blockDim.x) {
+    const int j = e % q, c = e / q, sc = v.sel[c];
+    Vc[e] = Rt[sc * q + j] / v.sig[sc];
+  }
+  __syncthreads();
+  return kk;
+}
+
+// Dense route for a small leaf (p q <= kMaxK^2 with p = max(m, n), q =
+// min(m, n)): M = U_s V_s^T is formed explicitly (as M' = M, or M^T when
+// n > m, so that M' has q columns) and truncated by qr_svd: the q-side factor
+// is V_c, the p-side factor M' V_c carries the singular values.  When the
+// QR route lacks room, M' is diagonalised by one-sided Jacobi in full
+// (M' Z = W Sigma; p side (M' Z)_sel, q side Z_sel).
 __device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
                            char* lds, double* scratch, double eps, uint64_t* tph) {
   const int tid = threadIdx.x;
@@ -1247,9 +1475,10 @@ __device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, con
   const int p = tr ? n : m, q = tr ? m : n;
   int* s_int = (int*)(lds + kLdsBytes - 64);
   const LargeVecs v = large_vecs(lds);
+  TruncScratch S = trunc_scratch(scratch);
   double* sA = (double*)lds;
   double* sB = sA + TK * (TM + TP);
-  double* Mg = scratch;  // p x q staging in global scratch
+  double* Mg = S.GU;  // p x q <= kMaxK^2
   // 1. M' (p x q, column-major) = X Y^T with (X, Y) = (U_s, V_s) or (V_s, U_s)
   if (!tr)
     gemm_tiles<double>(
@@ -1260,20 +1489,42 @@ __device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, con
         n, m, K, [&](int i, int l) { return sv(a, i, l); }, [&](int l, int j) { return su(a, j, l); },
         [&](int i, int j, double x) { Mg[j * p + i] = x; }, false, false, sA, sB);
   __syncthreads();
-  double* Mp = (double*)lds;
-  double* Z = Mp + p * q;
-  for (int e = tid; e < p * q; e += blockDim.x) Mp[e] = Mg[e];
-  __syncthreads();
-  phase_tick(a, kCtrPhase + 6, tph);
-  // 2. one-sided Jacobi on M'
-  const int sw = jacobi_svd(Mp, Z, p, q, s_int, eps);
-  phase_tick(a, kCtrPhase + 9, tph);
-  // 3. kept triplets
+  phase_tick(a, lds, kCtrPhase + 6, tph);
+  RV uc{d.u_off, m, 0, 1, m, d.type};
+  RV vc{d.v_off, n, 0, 1, n, d.type};
+  // 2. QR-preconditioned SVD
+  int sw = 0;
+  double* Vq = S.YV;  // q x kk
+  const int kq = qr_svd(a, d, Mg, p, q, Vq, lds, S.B, v, eps, &sw);
+  phase_tick(a, lds, kCtrPhase + 9, tph);
+  if (kq >= 0) {
+    trunc_note(lds, 2, p, q, sw, kq);
+    if (kq == 0) return set_rank(a, lr_index, 0);
+    uc.cols = vc.cols = kq;
+    const RV qv = tr ? uc : vc, pv = tr ? vc : uc;
+    for (int e = tid; e < q * kq; e += blockDim.x) vst(a, qv, e % q, e / q, Vq[e]);
+    gemm_tiles<double>(
+        p, kq, q, [&](int i, int j) { return Mg[j * p + i]; }, [&](int j, int c) { return Vq[c * q + j]; },
+        [&](int i, int c, double x) { vst(a, pv, i, c, x); }, false, true, sA, sB);
+    __syncthreads();
+    phase_tick(a, lds, kCtrPhase + 11, tph);
+    return set_rank(a, lr_index, kq);
+  }
+  // 3. fallback: one-sided Jacobi on all of M'
+  double* Mp = Mg;
+  double* Z = S.Z;
+  if ((int64_t)p * q + (int64_t)q * q <= kLargeWork) {
+    Mp = (double*)lds;
+    Z = Mp + p * q;
+    for (int e = tid; e < p * q; e += blockDim.x) Mp[e] = Mg[e];
+    __syncthreads();
+  }
+  sw = jacobi_svd(Mp, Z, p, q, s_int, eps);
+  phase_tick(a, lds, kCtrPhase + 9, tph);
   const int kk = select_kept(a, d, Mp, p, q, v.sig, v.sel, s_int, eps);
-  trunc_note(lds, 2, p, q, sw, kk);
+  trunc_note(lds, 4, p, q, sw, kk);
   if (kk == 0) return set_rank(a, lr_index, 0);
-  RV uc{d.u_off, m, kk, 1, m, d.type};
-  RV vc{d.v_off, n, kk, 1, n, d.type};
+  uc.cols = vc.cols = kk;
   for (int e = tid; e < m * kk; e += blockDim.x) {
     const int i = e % m, c = e / m;
     const int j = v.sel[c];
@@ -1285,15 +1536,17 @@ __device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, con
     vst(a, vc, i, c, tr ? Mp[j * p + i] : Z[j * q + i]);
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 11, tph);
+  phase_tick(a, lds, kCtrPhase + 11, tph);
   return set_rank(a, lr_index, kk);
 }
 
 // Gram route: R factors of U_s and V_s from their Gram matrices (pivoted
 // Cholesky), the core B = Rt_U W Rt_V^T (rU x rV, W = diag(||u_l|| ||v_l||)),
-// one-sided Jacobi on B or B^T (whichever has fewer columns), then
-//   U <- U_s D_U P_U R_U11^{-1} Y_U,  V <- V_s D_V P_V R_V11^{-1} Y_V
-// with (Y_U, Y_V) = ((B Z)_sel, Z_sel) or (Z_sel, (B^T Z)_sel).
+// oriented as B' = B or B^T so that B' has q = min(rU, rV) columns and
+// truncated by qr_svd (or, without room, by one-sided Jacobi on all of B'),
+// then U <- U_s D_U P_U R_U11^{-1} Y_U,  V <- V_s D_V P_V R_V11^{-1} Y_V
+// with Y the core's kept singular vectors (the side that carries Sigma is
+// the p side of B').
 __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
                           char* lds, double* scratch, double eps, uint64_t* tph) {
   const int tid = threadIdx.x;
@@ -1316,7 +1569,7 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
       [&](int i, int j, double x) { GV[i * K + j] = x; }, true, true, sA, sB);
   __syncthreads();
-  phase_tick(a, kCtrPhase + 6, tph);
+  phase_tick(a, lds, kCtrPhase + 6, tph);
   // 2. R factors
   pivoted_cholesky_pair(GU, GV, K, v, s_int);
   const int rU = s_int[0], rV = s_int[1];
@@ -1333,17 +1586,16 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     v.posV[l] = K;
   }
   __syncthreads();
-  phase_tick(a, kCtrPhase + 7, tph);
+  phase_tick(a, lds, kCtrPhase + 7, tph);
   if (rU == 0 || rV == 0) return set_rank(a, lr_index, 0);
   for (int j = tid; j < rU; j += blockDim.x) v.posU[v.pU[j]] = j;
   for (int j = tid; j < rV; j += blockDim.x) v.posV[v.pV[j]] = j;
   for (int l = tid; l < K; l += blockDim.x)
     v.sig[l] = (v.dU[l] == 0.0 || v.dV[l] == 0.0) ? 0.0 : 1.0 / (v.dU[l] * v.dV[l]);
   __syncthreads();
-  // 3. core, oriented so that the SVD operand B' (p x q) has q = min(rU, rV)
+  // 3. core B' (p x q, column-major, global)
   const bool tr = rV > rU;
   const int p = tr ? rV : rU, q = tr ? rU : rV;
-  const bool b_lds = p * q + q * q <= kLargeWork;
   double* Bg = S.B;
   gemm_tiles<double>(
       rU, rV, K, [&](int i, int l) { return GU[(int64_t)v.pU[i] * K + l] * v.sig[l]; },
@@ -1356,36 +1608,43 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       },
       true, true, sA, sB);
   __syncthreads();
-  double* Bp = Bg;
-  double* Z = S.Z;
-  if (b_lds) {
-    Bp = W;
-    Z = W + p * q;
-    for (int e = tid; e < p * q; e += blockDim.x) Bp[e] = Bg[e];
+  phase_tick(a, lds, kCtrPhase + 8, tph);
+  // 4. SVD of the core; Y_q (q side) and Y_p (p side, with Sigma)
+  double* Yq = tr ? S.YU : S.YV;
+  double* Yp = tr ? S.YV : S.YU;
+  int sw = 0;
+  int kk = qr_svd(a, d, Bg, p, q, Yq, lds, S.Z, v, eps, &sw);
+  if (kk >= 0) {
+    trunc_note(lds, 3, p, q, sw, kk);
+    phase_tick(a, lds, kCtrPhase + 9, tph);
+    if (kk == 0) return set_rank(a, lr_index, 0);
+    gemm_tiles<double>(
+        p, kk, q, [&](int i, int j) { return Bg[j * p + i]; }, [&](int j, int c) { return Yq[c * q + j]; },
+        [&](int i, int c, double x) { Yp[c * p + i] = x; }, false, true, sA, sB);
+    __syncthreads();
+  } else {
+    double* Bp = Bg;
+    double* Z = S.Z;
+    if ((int64_t)p * q + (int64_t)q * q <= kLargeWork) {
+      Bp = W;
+      Z = W + p * q;
+      for (int e = tid; e < p * q; e += blockDim.x) Bp[e] = Bg[e];
+      __syncthreads();
+    }
+    sw = jacobi_svd(Bp, Z, p, q, s_int, eps);
+    phase_tick(a, lds, kCtrPhase + 9, tph);
+    kk = select_kept(a, d, Bp, p, q, v.sig, v.sel, s_int, eps);
+    trunc_note(lds, 5, p, q, sw, kk);
+    if (kk == 0) return set_rank(a, lr_index, 0);
+    for (int e = tid; e < p * kk; e += blockDim.x) Yp[e] = Bp[v.sel[e / p] * p + e % p];
+    for (int e = tid; e < q * kk; e += blockDim.x) Yq[e] = Z[v.sel[e / q] * q + e % q];
     __syncthreads();
   }
-  phase_tick(a, kCtrPhase + 8, tph);
-  // 4. SVD of the core
-  const int sw = jacobi_svd(Bp, Z, p, q, s_int, eps);
-  phase_tick(a, kCtrPhase + 9, tph);
-  const int kk = select_kept(a, d, Bp, p, q, v.sig, v.sel, s_int, eps);
-  trunc_note(lds, b_lds ? 3 : 4, p, q, sw, kk);
-  if (kk == 0) return set_rank(a, lr_index, 0);
-  // 5. Y_U (rU x kk), Y_V (rV x kk)
-  for (int e = tid; e < rU * kk; e += blockDim.x) {
-    const int i = e % rU, c = e / rU, j = v.sel[c];
-    S.YU[e] = tr ? Z[j * q + i] : Bp[j * p + i];
-  }
-  for (int e = tid; e < rV * kk; e += blockDim.x) {
-    const int i = e % rV, c = e / rV, j = v.sel[c];
-    S.YV[e] = tr ? Bp[j * p + i] : Z[j * q + i];
-  }
-  __syncthreads();
-  // 6. T_U, T_V (K x kk) by back substitution with the pivoted triangles
+  // 5. T_U, T_V (K x kk) by back substitution with the pivoted triangles
   tri_solve_scatter(GU, K, rU, v.pU, v.posU, S.YU, kk, S.TU, v.dU, W, kLargeWork);
   tri_solve_scatter(GV, K, rV, v.pV, v.posV, S.YV, kk, S.TV, v.dV, W, kLargeWork);
-  phase_tick(a, kCtrPhase + 10, tph);
-  // 7. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile
+  phase_tick(a, lds, kCtrPhase + 10, tph);
+  // 6. rebuild in place: U <- U_s T_U, V <- V_s T_V (a single 64-column tile
   //    since kk <= 64, so every row tile is read completely before it is
   //    overwritten)
   RV uc{d.u_off, m, kk, 1, m, d.type};
@@ -1397,7 +1656,7 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       n, kk, K, [&](int r, int l) { return sv(a, r, l); }, [&](int l, int c) { return S.TV[c * K + l]; },
       [&](int r, int c, double x) { vst(a, vc, r, c, x); }, false, true, sA, sB);
   __syncthreads();
-  phase_tick(a, kCtrPhase + 11, tph);
+  phase_tick(a, lds, kCtrPhase + 11, tph);
   return set_rank(a, lr_index, kk);
 }
 
@@ -1412,11 +1671,11 @@ __device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, cons
   if (K <= kSmallK) return trunc_core_small(a, d, lr_index, su, sv, lds, eps);
   uint64_t tph = tid == 0 ? wall_clock64() : 0;
   if (a.counters && tid == 0) {
-    atomicAdd(&a.counters[kCtrK], (unsigned long long)K);
-    atomicAdd(&a.counters[kCtrMN], (unsigned long long)(m + n));
+    wg_ctr(lds)[kCtrK] += K;
+    wg_ctr(lds)[kCtrMN] += m + n;
   }
   const int p = max(m, n), q = min(m, n);
-  if ((int64_t)p * q + (int64_t)q * q <= kLargeWork && 4 * K >= 3 * q)
+  if ((int64_t)p * q <= (int64_t)kMaxK * kMaxK && 4 * K >= 3 * q)
     return trunc_dense(a, d, lr_index, su, sv, lds, scratch, eps, &tph);
   return trunc_gram(a, d, lr_index, su, sv, lds, scratch, eps, &tph);
 }
@@ -1460,8 +1719,8 @@ __device__ void op_trunc(const ExecArgs& a, const Task& t, char* lds, double* sc
     int64_t K = kc + A.cols + su.kp2;
     int64_t bytes = (int64_t)(d.m + d.n) * (kc + kn) * s + vbytes(A) + vbytes(B) + vbytes(X) + vbytes(Y);
     int64_t flops = 4 * (int64_t)(d.m + d.n) * K * K + 2 * (int64_t)(d.m + d.n) * K * kn + 20 * K * K * K;
-    atomicAdd(&a.counters[0], (unsigned long long)bytes);
-    atomicAdd(&a.counters[1], (unsigned long long)flops);
+    wg_ctr(lds)[0] += bytes;
+    wg_ctr(lds)[1] += flops;
   }
 }
 
@@ -1470,7 +1729,7 @@ __device__ void op_trunc(const ExecArgs& a, const Task& t, char* lds, double* sc
 // ---------------------------------------------------------------------------
 // Algorithmic bytes (every operand read once, every output written once, at
 // run-time extents) and flops of one task; the truncation counts itself.
-__device__ void count_task(const ExecArgs& a, const Task& t) {
+__device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
   if (!a.counters || t.op == OP_TRUNC || t.op == OP_TRUNC2 || t.op == OP_NOP) return;
   int64_t bytes = 0, flops = 0;
   if (t.op == OP_GETRF) {
@@ -1496,8 +1755,8 @@ __device__ void count_task(const ExecArgs& a, const Task& t) {
     RV y = resolve(a, t.y);
     bytes = 2 * vbytes(y);
   }
-  atomicAdd(&a.counters[0], (unsigned long long)bytes);
-  atomicAdd(&a.counters[1], (unsigned long long)flops);
+  wg_ctr(lds)[0] += bytes;
+  wg_ctr(lds)[1] += flops;
 }
 
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch);
@@ -1506,7 +1765,9 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
   const Task& t = a.tasks[id];
   uint64_t t0 = 0;
   if (threadIdx.x == 0) {
-    count_task(a, t);
+    count_task(a, t, lds);
+    if (a.counters && a.trace)
+      for (int k = 0; k < 6; ++k) wg_ctr(lds)[kCtrSize + k] = 0;
     t0 = wall_clock64();
   }
   run_task_body(a, t, lds, scratch);
@@ -1514,11 +1775,12 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
     __syncthreads();
     if (threadIdx.x == 0 && t.op >= 0 && t.op < OP_COUNT) {
       const uint64_t t1 = wall_clock64();
-      atomicAdd(&a.counters[kCtrBusy + t.op], (unsigned long long)(t1 - t0));
-      atomicAdd(&a.counters[kCtrCount + t.op], 1ull);
+      wg_ctr(lds)[kCtrBusy + t.op] += t1 - t0;
+      wg_ctr(lds)[kCtrCount + t.op] += 1;
       if (a.trace) {
-        a.trace[4 * (int64_t)id] = t0;
-        a.trace[4 * (int64_t)id + 1] = t1;
+        uint64_t* tr = a.trace + (int64_t)kTraceWords * id;
+        tr[0] = t0;
+        tr[1] = t1;
         uint64_t info = blockIdx.x & 0xffff;
         if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
           const LrDesc d = a.lr[t.lr];
@@ -1526,7 +1788,7 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
           if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
           info |= (K & 0xffff) << 16 | (uint64_t)(d.m & 0xffff) << 32 | (uint64_t)(d.n & 0xffff) << 48;
         }
-        a.trace[4 * (int64_t)id + 2] = info;
+        tr[2] = info;
         uint64_t info2 = 0;
         if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
           const int* s_int = (const int*)(lds + kLdsBytes - 64);
@@ -1534,7 +1796,12 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
                   (uint64_t)((s_int[13] >> 16) & 0xfff) << 20 | (uint64_t)(s_int[14] & 0xff) << 32 |
                   (uint64_t)((s_int[14] >> 16) & 0xff) << 40;
         }
-        a.trace[4 * (int64_t)id + 3] = info2;
+        tr[3] = info2;
+        for (int k = 0; k < 3; ++k) {
+          const uint64_t lo = wg_ctr(lds)[kCtrSize + 2 * k], hi = wg_ctr(lds)[kCtrSize + 2 * k + 1];
+          tr[4 + k] = (lo > 0xffffffffull ? 0xffffffffull : lo) | (hi > 0xffffffffull ? 0xffffffffull : hi) << 32;
+        }
+        tr[7] = 0;
       }
     }
   }
@@ -1581,14 +1848,31 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
   }
 }
 
+__device__ void wg_ctr_init(const ExecArgs& a, char* lds) {
+  if (a.counters)
+    for (int i = threadIdx.x; i < kCtrSize; i += blockDim.x) wg_ctr(lds)[i] = 0;
+  __syncthreads();
+}
+
+__device__ void wg_ctr_flush(const ExecArgs& a, char* lds) {
+  __syncthreads();
+  if (a.counters)
+    for (int i = threadIdx.x; i < kCtrSize; i += blockDim.x) {
+      const unsigned long long v = wg_ctr(lds)[i];
+      if (v) atomicAdd(&a.counters[i], v);
+    }
+}
+
 // One launch per DAG level: workgroup w runs tasks order[begin + w], order[begin + w + grid], ...
 __global__ void __launch_bounds__(kThreads, 2) exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end) {
   extern __shared__ __align__(16) char lds[];
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
+  wg_ctr_init(a, lds);
   for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
     run_task(a, order[i], lds, scratch);
     __syncthreads();
   }
+  wg_ctr_flush(a, lds);
 }
 
 __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots) {
@@ -1616,6 +1900,7 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
   __shared__ int s_task;
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int tid = threadIdx.x;
+  wg_ctr_init(a, lds);
   for (;;) {
     if (tid == 0) {
       int t = -1;
@@ -1639,7 +1924,10 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
     }
     __syncthreads();
     const int t = s_task;
-    if (t < 0) break;
+    if (t < 0) {
+      wg_ctr_flush(a, lds);
+      return;
+    }
     run_task(a, t, lds, scratch);
     // Publication: every thread's stores precede the workgroup barrier; one
     // agent-scope release fence then makes them visible across XCDs before

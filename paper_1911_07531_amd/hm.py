@@ -298,13 +298,14 @@ class LU:
         return export_leaf(self.h, 1, block, self.tree)
 
     def timeline(self):
-        """(ntasks, 4) uint64 (start, end, info, info2) and the tick rate in kHz (needs HM_DEBUG_TRACE=1);
+        """(ntasks, 8) uint64 (start, end, info, info2, phases x3, spare) and the tick rate in kHz
+        (needs HM_DEBUG_TRACE=1);
         info: workgroup in bits 0-15, for truncations term width / m / n in bits 16-31 / 32-47 / 48-63;
         info2 (truncations): route / SVD rows / SVD columns / sweeps / rank in bits 0-7 / 8-19 / 20-31 /
-        32-39 / 40-47."""
+        32-39 / 40-47; words 4-6: ticks of the six truncation phases, two 32-bit counts per word."""
         n, khz = C.c_int64(), C.c_int64()
         _check(lib().hm_lu_trace(self.h, None, C.byref(n), C.byref(khz)))
-        out = np.zeros((n.value, 4), np.uint64)
+        out = np.zeros((n.value, 8), np.uint64)
         _check(lib().hm_lu_trace(self.h, out.ctypes.data, C.byref(n), C.byref(khz)))
         return out, khz.value
 

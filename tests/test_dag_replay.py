@@ -118,3 +118,30 @@ def test_replay_lazy_updates_within_bounds(n, leaf, eps, max_rank):
     rr, rg = H.rank_table(ref), H.rank_table(f)
     assert max(abs(rg[i] - rr[i]) for i in rr) <= 2
     assert H.lu_error_2norm(dense, ref, exact=True) <= 10 * eps
+
+
+def test_replay_with_reused_temporaries(monkeypatch):
+    """A ring of temporaries far smaller than the DAG needs: slots are reused by
+    temporaries of other shapes, and every reuse must still be ordered after
+    the slot's earlier accesses (random topological orders reproduce the
+    collected-update H-LU within its bounds)."""
+    n, leaf, eps, max_rank = 2048, 32, 1e-4, 16
+    t_big, opts, a = _setup(n, leaf, 2.0, eps, max_rank, lazy=1)
+    big = t_big.dag(opts, 0)
+    monkeypatch.setenv("HM_TEMP_BUDGET_GB", "0.0005")
+    t, _, _ = _setup(n, leaf, 2.0, eps, max_rank, lazy=1)
+    dag = t.dag(opts, 0)
+    assert dag["n_f32"] + dag["n_f64"] < big["n_f32"] + big["n_f64"]  # the small ring is reused
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    pts, diag = inputs.sphere_problem(n, 0)
+    dense = H.kernel_block(pts, a.perm, a.clusters[0], a.clusters[0], diag)
+    ref = H.hlu(a, lazy=True)
+    rr = H.rank_table(ref)
+    for seed in (11, 12):
+        rp = Replay(dag, eps, max_rank)
+        rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+        rp.run(np.random.default_rng(seed))
+        f = _factors_from_replay(rp, t, a, dag)
+        assert H.lu_error_2norm(dense, f, exact=True) <= 10 * eps
+        rg = H.rank_table(f)
+        assert max(abs(rg[i] - rr[i]) for i in rr) <= 2
