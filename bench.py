@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--workload", default="sphere_n131072_eps1e-4_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--exec", dest="exec_mode", default="dataflow", choices=["dataflow", "level"])
     ap.add_argument("--nrhs", type=int, default=32)
-    ap.add_argument("--solves", type=int, default=20, help="solve requests timed for p50/p99")
+    ap.add_argument("--solves", type=int, default=10, help="solve requests timed for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -167,13 +167,14 @@ def main():
     f, st, iters, rel = last
     # solve latency: repeated 32-RHS requests on the resident factors
     lat = []
-    for _ in range(args.solves):
+    for k in range(args.solves):
         x = b_dev.clone().t().contiguous().t()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         f.solve(x, refine_with=A if prec == hm.MIXED else None, rtol=1e-10, max_iter=50)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
+        print(f"# solve request {k}: {lat[-1]:.1f} ms", file=sys.stderr, flush=True)
     med_exec = float(np.median(exec_ms))
     ach = st["bytes_alg"] / (med_exec * 1e-3) / 1e9
     cpu = None
