@@ -24,6 +24,7 @@ namespace hm {
 __global__ void exec_level_kernel(ExecArgs a, const int32_t* order, int begin, int end);
 __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots);
 __global__ void exec_dataflow_kernel(ExecArgs a);
+__global__ void solve_dataflow_kernel(ExecArgs a);
 __global__ void assemble_dense_kernel(ExecArgs a, AsmArgs s, const DenseAsm* blocks);
 __global__ void assemble_aca_kernel(ExecArgs a, AsmArgs s, const LrAsm* blocks, double* fac, int64_t fac_stride,
                                     double aca_eps);
@@ -200,6 +201,8 @@ static hm_status device_setup() {
   (void)hipFuncSetAttribute((const void*)exec_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)exec_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
+  (void)hipFuncSetAttribute((const void*)solve_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)exec_dataflow_kernel, kThreads, kLdsExecBytes) !=
@@ -296,7 +299,8 @@ static void exec_state_free(ExecState& es) {
 }
 
 // Run a DAG on `s`.  Returns the executor's device time in *ms.
-static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, hipStream_t s, float* ms) {
+static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, hipStream_t s, float* ms,
+                         bool solve = false) {
   if (dd.ntasks == 0) {
     if (ms) *ms = 0.f;
     return HM_OK;
@@ -334,7 +338,10 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
                        (const int32_t*)dd.roots.p, dd.nroots);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
+    if (solve)
+      hipLaunchKernelGGL(solve_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
+    else
+      hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, s));
   }
@@ -801,6 +808,7 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   F->stats.rank_overflows = stv[2];
   if (info) *info = 0;
   if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: a task the executor does not run");
   if (stv[0] & ST_SINGULAR) {
     if (info) *info = stv[1];
     hm_lu_s* f = F.release();
@@ -844,7 +852,7 @@ static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
                      0, 1);
   ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
                          (const LrDesc*)pe->lr.p, F->eps, F->max_rank);
-  return run_dag(pe->solve, a, F->solve_st, F->exec, s, nullptr);
+  return run_dag(pe->solve, a, F->solve_st, F->exec, s, nullptr, true);
 }
 
 hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
@@ -928,6 +936,7 @@ hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, do
     int32_t stv[4];
     HIPCHK(hipMemcpy(stv, F->solve_st.status.p, 16, hipMemcpyDeviceToHost));
     if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: a task the executor does not run");
   }
   if (!all_conv) return fail(HM_ENOCONV, "refinement did not reach rtol");
   return HM_OK;

@@ -146,6 +146,6 @@ constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8;
 // phase ticks (two 32-bit counts each), spare
 constexpr int kTraceWords = 8;
 
-enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4 };
+enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4, ST_BADOP = 8 };
 
 }  // namespace hm

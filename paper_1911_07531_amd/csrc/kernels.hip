@@ -300,63 +300,88 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
 // kind 1: x <- U^{-T} x
 // kind 2: x <- U^{-1} x
 // ---------------------------------------------------------------------------
+// A double from one (uniform) lane of the wavefront.
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// One wavefront per group of CW right-hand sides: lane i keeps rows i (and
+// i + 64 when R = 2) of the group in registers; step k broadcasts the finished row k
+// (scaled by 1/U_kk for the U solves) and updates the rows it feeds, so the
+// steps need no workgroup barrier.  T: the packed LU, column-major.
+template <int R, int CW>
+__device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m, int kind, const int32_t* perm,
+                          int c) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j0 = wave * CW; j0 < c; j0 += nw * CW) {
+    const int cw = min(CW, c - j0);
+    double x[R][CW];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + 64 * r;
+      const int src = i < m ? (kind == 0 ? perm[i] : i) : 0;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) x[r][q] = (i < m && q < cw) ? vld(a, X, src, j0 + q) : 0.0;
+    }
+    const bool fwd = kind != 2;
+    for (int s = 0; s < m; ++s) {
+      const int k = fwd ? s : m - 1 - s;
+      const int kl = k & 63, kr = k >> 6;
+      const double sc = kind == 0 ? 1.0 : 1.0 / T[k * m + k];
+      double xk[CW];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        double v = x[0][q];
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+          if (r == kr) v = x[r][q];
+        xk[q] = read_lane(v, kl) * sc;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        if (i == k) {
+#pragma unroll
+          for (int q = 0; q < CW; ++q) x[r][q] = xk[q];
+        } else if (i < m && (fwd ? i > k : i < k)) {
+          // L(i, k) for kind 0, U(k, i) for kind 1, U(i, k) for kind 2
+          const double l = kind == 1 ? T[i * m + k] : T[k * m + i];
+#pragma unroll
+          for (int q = 0; q < CW; ++q) x[r][q] -= l * xk[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + 64 * r;
+#pragma unroll
+      for (int q = 0; q < CW; ++q)
+        if (i < m && q < cw) vst(a, X, i, j0 + q, x[r][q]);
+    }
+  }
+}
+
 __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
   const int m = t.a.rows;
   RV X = resolve(a, t.x);
   const int c = X.cols;
   if (m == 0 || c == 0) return;
   const double* g = a.f64 + t.a.off;
-  const int CC = 64;
-  const bool tri_lds = (int64_t)m * m * 8 + (int64_t)m * CC * 8 <= kLdsBytes;
-  double* sX = (double*)lds;
-  double* sL = sX + m * CC;
-  const double* T = tri_lds ? sL : g;
-  const int tid = threadIdx.x;
-  if (tri_lds)
-    for (int e = tid; e < m * m; e += blockDim.x) sL[e] = g[e];
-  const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
-  for (int j0 = 0; j0 < c; j0 += CC) {
-    const int cc = min(CC, c - j0);
-    // load (rows gathered through the leaf's permutation for L^{-1} P)
-    for (int e = tid; e < m * cc; e += blockDim.x) {
-      int i = X.rs == 1 ? e % m : e / cc;
-      int j = X.rs == 1 ? e / m : e % cc;
-      int src = kind == 0 ? perm[i] : i;
-      sX[i * CC + j] = vld(a, X, src, j0 + j);
-    }
-    __syncthreads();
-    // right-looking substitution: step k finalises row k (up to the diagonal
-    // scale for U) and updates the rows after it; the scale is applied at the end
-    if (kind == 0 || kind == 1) {
-      for (int k = 0; k < m - 1; ++k) {
-        const double sc = kind == 0 ? 1.0 : 1.0 / T[k * m + k];
-        const int rows = m - 1 - k;
-        for (int e = tid; e < rows * cc; e += blockDim.x) {
-          const int i = k + 1 + e / cc, j = e % cc;
-          const double lik = kind == 0 ? T[k * m + i] : T[i * m + k];
-          sX[i * CC + j] -= lik * (sX[k * CC + j] * sc);
-        }
-        __syncthreads();
-      }
-    } else {
-      for (int k = m - 1; k > 0; --k) {
-        const double sc = 1.0 / T[k * m + k];
-        for (int e = tid; e < k * cc; e += blockDim.x) {
-          const int i = e / cc, j = e % cc;
-          sX[i * CC + j] -= T[k * m + i] * (sX[k * CC + j] * sc);
-        }
-        __syncthreads();
-      }
-    }
-    for (int e = tid; e < m * cc; e += blockDim.x) {
-      int i = X.rs == 1 ? e % m : e / cc;
-      int j = X.rs == 1 ? e / m : e % cc;
-      double v = sX[i * CC + j];
-      if (kind != 0) v *= 1.0 / T[i * m + i];
-      vst(a, X, i, j0 + j, v);
-    }
+  const bool tri_lds = (int64_t)m * m * 8 <= kLdsBytes;
+  double* sL = (double*)lds;
+  if (tri_lds) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) sL[e] = g[e];
     __syncthreads();
   }
+  const double* T = tri_lds ? sL : g;
+  const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
+  if (m <= 64)
+    trsm_wave<1, 16>(a, X, T, m, kind, perm, c);
+  else
+    trsm_wave<2, 8>(a, X, T, m, kind, perm, c);
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -1759,8 +1784,11 @@ __device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
   wg_ctr(lds)[1] += flops;
 }
 
+template <bool kSolve>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch);
 
+// kSolve: the task set of a triangular solve (TRSM, GEMM, LRGEMM, ZERO, COPY).
+template <bool kSolve = false>
 __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
   const Task& t = a.tasks[id];
   uint64_t t0 = 0;
@@ -1770,7 +1798,7 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
       for (int k = 0; k < 6; ++k) wg_ctr(lds)[kCtrSize + k] = 0;
     t0 = wall_clock64();
   }
-  run_task_body(a, t, lds, scratch);
+  run_task_body<kSolve>(a, t, lds, scratch);
   if (a.counters) {
     __syncthreads();
     if (threadIdx.x == 0 && t.op >= 0 && t.op < OP_COUNT) {
@@ -1807,16 +1835,21 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
   }
 }
 
+template <bool kSolve>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
+  if (kSolve && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) {
+    if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
+    return;
+  }
   switch (t.op) {
     case OP_GETRF:
-      op_getrf(a, t, lds);
+      if (!kSolve) op_getrf(a, t, lds);
       break;
     case OP_TRSM_L:
       op_trsm(a, t, lds, 0);
       break;
     case OP_TRSM_UT:
-      op_trsm(a, t, lds, 1);
+      if (!kSolve) op_trsm(a, t, lds, 1);
       break;
     case OP_TRSM_U:
       op_trsm(a, t, lds, 2);
@@ -1835,7 +1868,7 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
       break;
     case OP_TRUNC:
     case OP_TRUNC2:
-      op_trunc(a, t, lds, scratch);
+      if (!kSolve) op_trunc(a, t, lds, scratch);
       break;
     case OP_ZERO:
       op_zero(a, t);
@@ -1895,9 +1928,8 @@ __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_
 // to zero.  Every slot below ntasks is filled exactly once for an acyclic DAG;
 // a workgroup that waits longer than spin_limit wall-clock ticks raises ST_TIMEOUT and
 // every workgroup then leaves.
-__global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) {
-  extern __shared__ __align__(16) char lds[];
-  __shared__ int s_task;
+template <bool kSolve>
+__device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int& s_task) {
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int tid = threadIdx.x;
   wg_ctr_init(a, lds);
@@ -1928,7 +1960,7 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
       wg_ctr_flush(a, lds);
       return;
     }
-    run_task(a, t, lds, scratch);
+    run_task<kSolve>(a, t, lds, scratch);
     // Publication: every thread's stores precede the workgroup barrier; one
     // agent-scope release fence then makes them visible across XCDs before
     // any successor count drops.  The workgroup that releases a successor
@@ -1951,6 +1983,20 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_task;
+  dataflow_body<false>(a, lds, s_task);
+}
+
+// The same executor for the forward / backward substitution DAGs, built
+// with the solve's task set only.
+__global__ void __launch_bounds__(kThreads, 2) solve_dataflow_kernel(ExecArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_task;
+  dataflow_body<true>(a, lds, s_task);
 }
 
 // ---------------------------------------------------------------------------
