@@ -76,7 +76,9 @@ typedef struct {
   double eps;       /* relative truncation accuracy (keep sigma_i > eps sigma_1) */
   int max_rank;     /* rank cap, 0 = none (then the capacity 64 bounds it) */
   int prec;         /* hm_precision */
-  int exec;         /* hm_exec */
+  int exec;         /* hm_exec of the factorization; the substitution DAGs of
+                       h_solve, a few tasks per level, always run one launch
+                       per level */
   int lazy;         /* 0: truncate every update of a low-rank leaf when it is
                        produced, in the sequential order of Algorithm 1;
                        1: collect the updates of a low-rank leaf and add them
@@ -160,7 +162,8 @@ hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* da
 /* Per-task timeline of the last h_lu on F, recorded only when the
  * environment variable HM_DEBUG_TRACE=1 was set before h_lu: out (may be
  * NULL to query sizes) receives ntasks x 8 uint64 (start tick, end tick,
- * info, info2, three words of truncation-phase ticks, spare) in trace order;
+ * info, info2, three words of truncation-phase ticks, the tick at which the
+ * dataflow executor queued the task (0 for the first tasks)) in trace order;
  * ticks count at clock_khz kHz.  info bits 0-15
  * hold the workgroup; for truncations bits 16-31 the width of the added
  * terms and bits 32-47 / 48-63 the rows m / columns n of the low-rank leaf,

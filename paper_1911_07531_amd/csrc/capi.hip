@@ -25,6 +25,7 @@ __global__ void exec_level_kernel(ExecArgs a, const int32_t* order, int begin, i
 __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots);
 __global__ void exec_dataflow_kernel(ExecArgs a);
 __global__ void solve_dataflow_kernel(ExecArgs a);
+__global__ void solve_level_kernel(ExecArgs a, const int32_t* order, int begin, int end);
 __global__ void assemble_dense_kernel(ExecArgs a, AsmArgs s, const DenseAsm* blocks);
 __global__ void assemble_aca_kernel(ExecArgs a, AsmArgs s, const LrAsm* blocks, double* fac, int64_t fac_stride,
                                     double aca_eps);
@@ -203,6 +204,8 @@ static hm_status device_setup() {
                             kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)solve_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
+  (void)hipFuncSetAttribute((const void*)solve_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)exec_dataflow_kernel, kThreads, kLdsExecBytes) !=
@@ -327,8 +330,12 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     for (int64_t l = 0; l < dd.nlevels; ++l) {
       int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
       int grid = std::min(e - b, g_nwg);
-      hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
-                         (const int32_t*)dd.order.p, b, e);
+      if (solve)
+        hipLaunchKernelGGL(solve_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
+                           (const int32_t*)dd.order.p, b, e);
+      else
+        hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
+                           (const int32_t*)dd.order.p, b, e);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, s));
@@ -742,10 +749,13 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
     return fail(HM_ENOMEM, "device allocation failed (factors)");
   if ((st = upload(F->perm, t->t.perm, s))) return st;
   if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
-  // HM_DEBUG_TRACE=1 records (start, end, workgroup) of every H-LU task
+  // HM_DEBUG_TRACE=1 records timing and shape information of every H-LU task
   if (const char* e = getenv("HM_DEBUG_TRACE"))
-    if (e[0] == '1' && !dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * kTraceWords * 8, s))
-      return fail(HM_ENOMEM, "device allocation failed (trace)");
+    if (e[0] == '1') {
+      if (!dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * kTraceWords * 8, s))
+        return fail(HM_ENOMEM, "device allocation failed (trace)");
+      HIPCHK(hipMemsetAsync(F->lu_st.trace.p, 0, (size_t)pe->lu.ntasks * kTraceWords * 8, s));
+    }
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
   // copy A into the factor layout
   HIPCHK(hipMemsetAsync(F->ranks.p, 0, p.nranks * 4, s));
@@ -852,7 +862,12 @@ static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
                      0, 1);
   ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
                          (const LrDesc*)pe->lr.p, F->eps, F->max_rank);
-  return run_dag(pe->solve, a, F->solve_st, F->exec, s, nullptr, true);
+  // The substitution DAG is narrow (a few tasks per level): one launch per
+  // level beats the persistent executor's hand-offs there.
+  // HM_SOLVE_EXEC=dataflow selects the persistent executor instead.
+  int mode = HM_EXEC_LEVEL;
+  if (const char* e = getenv("HM_SOLVE_EXEC")) mode = e[0] == 'd' ? HM_EXEC_DATAFLOW : HM_EXEC_LEVEL;
+  return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, true);
 }
 
 hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,

@@ -143,7 +143,7 @@ constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COU
 // then the current task's six truncation-phase tick counts (trace only)
 constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8;
 // words per task of the debug trace: start, end, info, info2, three words of
-// phase ticks (two 32-bit counts each), spare
+// phase ticks (two 32-bit counts each), the tick the task was queued
 constexpr int kTraceWords = 8;
 
 enum StatusCode : int32_t { ST_OK = 0, ST_SINGULAR = 1, ST_RANK = 2, ST_TIMEOUT = 4, ST_BADOP = 8 };

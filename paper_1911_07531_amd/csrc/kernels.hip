@@ -132,6 +132,82 @@ __device__ void gemm_tiles(int m, int n, int k, LA la, LB lb, ST st, bool a_kcon
 constexpr int kTileBytes = 2 * TK * (TM + TP) * 8;  // both tiles in double
 
 // ---------------------------------------------------------------------------
+// block copies with several loads in flight per thread (a plain strided loop
+// waits for every load before its store)
+// ---------------------------------------------------------------------------
+template <class Dst>
+__device__ __forceinline__ void copy_batched(Dst dst, const double* src, int n) {
+  for (int base = 0; base < n; base += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      v[u] = e < n ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < n) dst(e, v[u]);
+    }
+  }
+}
+__device__ __forceinline__ void copy_batched(double* dst, const double* src, int n) {
+  copy_batched([&](int e, double x) { dst[e] = x; }, src, n);
+}
+
+// ---------------------------------------------------------------------------
+// cross-lane reductions
+// ---------------------------------------------------------------------------
+// A double moved between lanes by a DPP pattern (both 32-bit halves).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of g lanes (g a power of two <= 64); every lane of
+// a group gets the group's total.  Within a row of 16 lanes the partners come
+// from DPP mirror and quad patterns (each step joins two disjoint lane sets),
+// across rows from a shuffle.
+__device__ __forceinline__ double group_sum(double x, int g) {
+  if (g >= 64) x += __shfl_xor(x, 32);
+  if (g >= 32) x += __shfl_xor(x, 16);
+  if (g >= 16) x += dpp_f64<0x140>(x);  // row_mirror: i <-> 15 - i
+  if (g >= 8) x += dpp_f64<0x141>(x);   // row_half_mirror: i <-> 7 - i
+  if (g >= 4) x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  if (g >= 2) x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  return x;
+}
+
+// Largest value (smallest index among ties) over the whole wavefront; every
+// lane gets the winner.
+template <int kCtrl>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+  const double ov = dpp_f64<kCtrl>(v);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, kCtrl, 0xF, 0xF, false);
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off >= 16; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(i, off);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  argmax_step<0x140>(v, i);
+  argmax_step<0x141>(v, i);
+  argmax_step<0x4E>(v, i);
+  argmax_step<0xB1>(v, i);
+}
+
+// ---------------------------------------------------------------------------
 // simple element-wise ops
 // ---------------------------------------------------------------------------
 __device__ void op_zero(const ExecArgs& a, const Task& t) {
@@ -227,7 +303,7 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
   int* s_perm = (int*)(lds + kLdsBytes - 16 - 4 * kMaxLeaf);
   const int tid = threadIdx.x;
   if (in_lds)
-    for (int e = tid; e < m * m; e += blockDim.x) A[(e / m) * ld + (e % m)] = g[e];
+    copy_batched([&](int e, double x) { A[(e / m) * ld + (e % m)] = x; }, g, m * m);
   for (int i = tid; i < m; i += blockDim.x) s_perm[i] = i;
   __syncthreads();
   for (int j = 0; j < m; ++j) {
@@ -241,14 +317,7 @@ __device__ void op_getrf(const ExecArgs& a, const Task& t, char* lds) {
           bi = i;
         }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      wave_argmax(best, bi);
       if (bi >= m) bi = j;  // no comparable entry (NaN column): keep the row
       if (tid == 0) {
         s_piv[0] = bi;
@@ -372,7 +441,7 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
   const bool tri_lds = (int64_t)m * m * 8 <= kLdsBytes;
   double* sL = (double*)lds;
   if (tri_lds) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) sL[e] = g[e];
+    copy_batched(sL, g, m * m);
     __syncthreads();
   }
   const double* T = tri_lds ? sL : g;
@@ -443,14 +512,7 @@ __device__ int pivoted_cholesky(double* G, int K, int* perm, double* dsc, int* s
           bi = i;
         }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      wave_argmax(best, bi);
       if (tid == 0) {
         s_int[0] = bi < K ? bi : s;
         s_int[1] = (bi < K && best > tol) ? 1 : 0;
@@ -566,7 +628,7 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
   {
     double f = 0.0;
     for (int e = tid; e < p * q; e += blockDim.x) f += B[e] * B[e];
-    for (int off = 32; off >= 1; off >>= 1) f += __shfl_xor(f, off);
+    f = group_sum(f, 64);
     if ((tid & 63) == 0) atomicAdd(fro_s, f);
   }
   __syncthreads();
@@ -596,11 +658,9 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
           be += y * y;
           ga += x * y;
         }
-      for (int off = tpp / 2; off >= 1; off >>= 1) {
-        al += __shfl_xor(al, off);
-        be += __shfl_xor(be, off);
-        ga += __shfl_xor(ga, off);
-      }
+      al = group_sum(al, tpp);
+      be = group_sum(be, tpp);
+      ga = group_sum(ga, tpp);
       if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
         if (lane == 0) s_flag[0] = 1;
         double zeta = (be - al) / (2.0 * ga);
@@ -796,14 +856,7 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
         bi = l;
       }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      double ob = __shfl_xor(best, off);
-      int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
+    wave_argmax(best, bi);
     if (bi >= K || !(best > tol)) return s;
     const int p = bi;
     if (p != s) {
@@ -884,11 +937,9 @@ __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
           be += y * y;
           ga += x * y;
         }
-      for (int off = tpp / 2; off >= 1; off >>= 1) {
-        al += __shfl_xor(al, off);
-        be += __shfl_xor(be, off);
-        ga += __shfl_xor(ga, off);
-      }
+      al = group_sum(al, tpp);
+      be = group_sum(be, tpp);
+      ga = group_sum(ga, tpp);
       if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
         rotated = 1;
         double zeta = (be - al) / (2.0 * ga);
@@ -1169,14 +1220,7 @@ __device__ void pivoted_cholesky_pair(double* GU, double* GV, int K, const Large
           bi = l;
         }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      wave_argmax(best, bi);
       if (t == 0) {
         const bool go = bi < K && best > tol;
         slot[0] = bi;
@@ -1355,7 +1399,7 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
   const int room = kLargeWork - (x_lds ? p * q : 0);
   int rl = 0;
   while (rl < rmax && q * (rl + 1) + (rl + 1) * (rl + 1) <= room) ++rl;
-  for (int e = tid; e < p * q; e += blockDim.x) X[e] = Bg[e];
+  copy_batched(X, Bg, p * q);
   __syncthreads();
   // lanes per column: the largest power of two with tpc * q <= 256 (<= 64)
   int tpc = 1;
@@ -1365,7 +1409,7 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
   if (g < q) {
     double acc = 0.0;
     for (int i = lt; i < p; i += tpc) acc += X[g * p + i] * X[g * p + i];
-    for (int off = tpc / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, tpc);
+    acc = group_sum(acc, tpc);
     if (lt == 0) {
       cn[g] = acc;
       v.qpos[g] = kMaxK;
@@ -1396,15 +1440,8 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
             bi = j;
           }
         }
-      for (int off = 32; off >= 1; off >>= 1) {
-        sum += __shfl_xor(sum, off);
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      sum = group_sum(sum, 64);
+      wave_argmax(best, bi);
       if (tid == 0) {
         int code = 1;                                   // go on
         if (st == rmax || bi >= q || sum <= tol2 || !(best > 0.0)) code = 0;  // done
@@ -1430,7 +1467,7 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
     if (tid < 64) {
       double nrm2 = 0.0;
       for (int i = st + tid; i < p; i += 64) nrm2 += xp[i] * xp[i];
-      for (int off = 32; off >= 1; off >>= 1) nrm2 += __shfl_xor(nrm2, off);
+      nrm2 = group_sum(nrm2, 64);
       if (tid == 0) {
         const double x0 = xp[st];
         const double nr = sqrt(nrm2);
@@ -1449,7 +1486,7 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
       double* xj = X + g * p;
       double w = 0.0;
       for (int i = st + lt; i < p; i += tpc) w += xp[i] * xj[i];
-      for (int off = tpc / 2; off >= 1; off >>= 1) w += __shfl_xor(w, off, tpc);
+      w = group_sum(w, tpc);
       const double f = be * w;
       double nn = 0.0;
       for (int i = st + lt; i < p; i += tpc) {
@@ -1457,7 +1494,7 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
         xj[i] = y;
         if (i > st) nn += y * y;
       }
-      for (int off = tpc / 2; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, tpc);
+      nn = group_sum(nn, tpc);
       if (lt == 0) cn[g] = nn;
     }
     __syncthreads();
@@ -1541,7 +1578,7 @@ __device__ int trunc_dense(const ExecArgs& a, const LrDesc& d, int lr_index, con
   if ((int64_t)p * q + (int64_t)q * q <= kLargeWork) {
     Mp = (double*)lds;
     Z = Mp + p * q;
-    for (int e = tid; e < p * q; e += blockDim.x) Mp[e] = Mg[e];
+    copy_batched(Mp, Mg, p * q);
     __syncthreads();
   }
   sw = jacobi_svd(Mp, Z, p, q, s_int, eps);
@@ -1653,7 +1690,7 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
     if ((int64_t)p * q + (int64_t)q * q <= kLargeWork) {
       Bp = W;
       Z = W + p * q;
-      for (int e = tid; e < p * q; e += blockDim.x) Bp[e] = Bg[e];
+      copy_batched(Bp, Bg, p * q);
       __syncthreads();
     }
     sw = jacobi_svd(Bp, Z, p, q, s_int, eps);
@@ -1815,6 +1852,12 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
           uint64_t K = (uint64_t)resolve(a, t.a).cols;
           if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
           info |= (K & 0xffff) << 16 | (uint64_t)(d.m & 0xffff) << 32 | (uint64_t)(d.n & 0xffff) << 48;
+        } else {
+          // output rows / columns and the inner dimension
+          const View& o = (t.op == OP_GETRF) ? t.a : (t.op >= OP_TRSM_L && t.op <= OP_TRSM_U) ? t.x : t.y;
+          const RV r = resolve(a, o);
+          const int kd = (t.op == OP_GEMM || t.op == OP_LRGEMM) ? resolve(a, t.a).cols : t.a.rows;
+          info |= (uint64_t)(r.rows & 0xffff) << 16 | (uint64_t)(r.cols & 0xffff) << 32 | (uint64_t)(kd & 0xffff) << 48;
         }
         tr[2] = info;
         uint64_t info2 = 0;
@@ -1829,7 +1872,7 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
           const uint64_t lo = wg_ctr(lds)[kCtrSize + 2 * k], hi = wg_ctr(lds)[kCtrSize + 2 * k + 1];
           tr[4 + k] = (lo > 0xffffffffull ? 0xffffffffull : lo) | (hi > 0xffffffffull ? 0xffffffffull : hi) << 32;
         }
-        tr[7] = 0;
+        // tr[7]: the tick at which the task was pushed to the ready queue
       }
     }
   }
@@ -1908,6 +1951,19 @@ __global__ void __launch_bounds__(kThreads, 2) exec_level_kernel(ExecArgs a, con
   wg_ctr_flush(a, lds);
 }
 
+// The level executor for the forward / backward substitution DAGs.
+__global__ void __launch_bounds__(kThreads, 2) solve_level_kernel(ExecArgs a, const int32_t* order, int begin,
+                                                                  int end) {
+  extern __shared__ __align__(16) char lds[];
+  double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
+  wg_ctr_init(a, lds);
+  for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
+    run_task<true>(a, order[i], lds, scratch);
+    __syncthreads();
+  }
+  wg_ctr_flush(a, lds);
+}
+
 __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_t* roots, int nroots) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int stride = gridDim.x * blockDim.x;
@@ -1977,6 +2033,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
         if (prev == 1) {
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
           int pos = atomicAdd(&a.qctl[1], 1);
+          if (a.trace) a.trace[(int64_t)kTraceWords * s + 7] = wall_clock64();
           if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
       }

@@ -298,7 +298,7 @@ class LU:
         return export_leaf(self.h, 1, block, self.tree)
 
     def timeline(self):
-        """(ntasks, 8) uint64 (start, end, info, info2, phases x3, spare) and the tick rate in kHz
+        """(ntasks, 8) uint64 (start, end, info, info2, phases x3, queued) and the tick rate in kHz
         (needs HM_DEBUG_TRACE=1);
         info: workgroup in bits 0-15, for truncations term width / m / n in bits 16-31 / 32-47 / 48-63;
         info2 (truncations): route / SVD rows / SVD columns / sweeps / rank in bits 0-7 / 8-19 / 20-31 /
