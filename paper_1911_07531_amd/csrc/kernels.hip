@@ -225,6 +225,60 @@ __device__ void op_copy(const ExecArgs& a, const Task& t) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// small operands: every operand of a task staged into LDS in one batched
+// load phase (up to 16 loads per thread in flight), so that the task pays one
+// global round trip before its arithmetic instead of one per k slice
+// ---------------------------------------------------------------------------
+struct StageSrc {
+  RV v;
+  double* dst;           // column-major, leading dimension = v.rows
+  const int32_t* rows;   // optional row gather: element (i, j) <- v(rows[i], j)
+};
+
+__device__ __forceinline__ double stage_ld(const ExecArgs& a, const StageSrc& s, int e) {
+  const int r = s.v.rows, i = e % r, j = e / r;
+  return vld(a, s.v, s.rows ? s.rows[i] : i, j);
+}
+
+// Up to four sources (unused ones with zero rows); element e of the joint
+// index space belongs to the first source whose prefix holds it.
+__device__ __forceinline__ void stage_views(const ExecArgs& a, const StageSrc& s0, const StageSrc& s1,
+                                            const StageSrc& s2, const StageSrc& s3) {
+  const int c0 = s0.v.rows * s0.v.cols, c1 = c0 + s1.v.rows * s1.v.cols, c2 = c1 + s2.v.rows * s2.v.cols,
+            total = c2 + s3.v.rows * s3.v.cols;
+  for (int base = 0; base < total; base += 16 * kThreads) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      v[u] = 0.0;
+      if (e < c0)
+        v[u] = stage_ld(a, s0, e);
+      else if (e < c1)
+        v[u] = stage_ld(a, s1, e - c0);
+      else if (e < c2)
+        v[u] = stage_ld(a, s2, e - c1);
+      else if (e < total)
+        v[u] = stage_ld(a, s3, e - c2);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < c0)
+        s0.dst[e] = v[u];
+      else if (e < c1)
+        s1.dst[e - c0] = v[u];
+      else if (e < c2)
+        s2.dst[e - c1] = v[u];
+      else if (e < total)
+        s3.dst[e - c2] = v[u];
+    }
+  }
+}
+
+constexpr int kLdsDoubles = kLdsBytes / 8;
+
 // y <- beta y + alpha a b
 template <typename CT>
 __device__ void op_gemm_ct(const ExecArgs& a, const Task& t, char* lds) {
@@ -237,6 +291,22 @@ __device__ void op_gemm_ct(const ExecArgs& a, const Task& t, char* lds) {
       int i = e % m, j = e / m;
       vst(a, y, i, j, beta == 0.0 ? 0.0 : beta * vld(a, y, i, j));
     }
+    return;
+  }
+  if ((int64_t)m * k + (int64_t)k * n + (int64_t)m * n <= kLdsDoubles) {
+    double* lA = (double*)lds;
+    double* lB = lA + m * k;
+    double* lY = lB + k * n;
+    const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+    stage_views(a, {A, lA, nullptr}, {B, lB, nullptr}, beta != 0.0 ? StageSrc{y, lY, nullptr} : none, none);
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+      const int i = e % m, j = e / m;
+      double acc = 0.0;
+      for (int l = 0; l < k; ++l) acc += lA[l * m + i] * lB[j * k + l];
+      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[e]) + alpha * acc);
+    }
+    __syncthreads();
     return;
   }
   CT* sA = (CT*)lds;
@@ -262,6 +332,32 @@ __device__ void op_lrgemm_ct(const ExecArgs& a, const Task& t, char* lds) {
       int i = e % m, j = e / m;
       vst(a, y, i, j, beta == 0.0 ? 0.0 : beta * vld(a, y, i, j));
     }
+    return;
+  }
+  if ((int64_t)m * k + (int64_t)k * n2 + (int64_t)n2 * c + (int64_t)m * c + (int64_t)k * c <= kLdsDoubles) {
+    double* lA = (double*)lds;
+    double* lB = lA + m * k;
+    double* lX = lB + k * n2;
+    double* lY = lX + n2 * c;
+    double* lT = lY + m * c;
+    const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+    stage_views(a, {A, lA, nullptr}, {B, lB, nullptr}, {X, lX, nullptr},
+                beta != 0.0 ? StageSrc{y, lY, nullptr} : none);
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * c; e += blockDim.x) {  // T = b x (k x c)
+      const int i = e % k, j = e / k;
+      double acc = 0.0;
+      for (int l = 0; l < n2; ++l) acc += lB[l * k + i] * lX[j * n2 + l];
+      lT[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * c; e += blockDim.x) {
+      const int i = e % m, j = e / m;
+      double acc = 0.0;
+      for (int l = 0; l < k; ++l) acc += lA[l * m + i] * lT[j * k + l];
+      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[e]) + alpha * acc);
+    }
+    __syncthreads();
     return;
   }
   CT* sA = (CT*)lds;
@@ -382,7 +478,7 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
 // steps need no workgroup barrier.  T: the packed LU, column-major.
 template <int R, int CW>
 __device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m, int kind, const int32_t* perm,
-                          int c) {
+                          int c, const double* sx, const double* rdiag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j0 = wave * CW; j0 < c; j0 += nw * CW) {
     const int cw = min(CW, c - j0);
@@ -392,13 +488,14 @@ __device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m
       const int i = lane + 64 * r;
       const int src = i < m ? (kind == 0 ? perm[i] : i) : 0;
 #pragma unroll
-      for (int q = 0; q < CW; ++q) x[r][q] = (i < m && q < cw) ? vld(a, X, src, j0 + q) : 0.0;
+      for (int q = 0; q < CW; ++q)
+        x[r][q] = (i < m && q < cw) ? (sx ? sx[(j0 + q) * m + i] : vld(a, X, src, j0 + q)) : 0.0;
     }
     const bool fwd = kind != 2;
     for (int s = 0; s < m; ++s) {
       const int k = fwd ? s : m - 1 - s;
       const int kl = k & 63, kr = k >> 6;
-      const double sc = kind == 0 ? 1.0 : 1.0 / T[k * m + k];
+      const double sc = kind == 0 ? 1.0 : (rdiag ? rdiag[k] : 1.0 / T[k * m + k]);
       double xk[CW];
 #pragma unroll
       for (int q = 0; q < CW; ++q) {
@@ -438,18 +535,47 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
   const int c = X.cols;
   if (m == 0 || c == 0) return;
   const double* g = a.f64 + t.a.off;
-  const bool tri_lds = (int64_t)m * m * 8 <= kLdsBytes;
+  const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
   double* sL = (double*)lds;
-  if (tri_lds) {
+  const double* sx = nullptr;
+  bool tri_lds = false;
+  if ((int64_t)m * m + (int64_t)m * c <= kLdsDoubles) {
+    // the triangle and the panel (rows gathered for L^{-1} P) in one phase
+    double* sX = sL + m * m;
+    RV tri{t.a.off, m, m, 1, m, VT_F64};
+    const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+    stage_views(a, {tri, sL, nullptr}, {X, sX, kind == 0 ? perm : nullptr}, none, none);
+    __syncthreads();
+    sx = sX;
+    tri_lds = true;
+  } else if ((int64_t)m * m * 8 <= kLdsBytes) {
     copy_batched(sL, g, m * m);
     __syncthreads();
+    tri_lds = true;
   }
   const double* T = tri_lds ? sL : g;
-  const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
-  if (m <= 64)
-    trsm_wave<1, 16>(a, X, T, m, kind, perm, c);
-  else
-    trsm_wave<2, 8>(a, X, T, m, kind, perm, c);
+  // reciprocal diagonal for the U solves, after the staged data when room is left
+  double* rdiag = nullptr;
+  if (kind != 0 && tri_lds && (int64_t)m * m + (int64_t)(sx ? m * c : 0) + m <= kLdsDoubles) {
+    rdiag = sL + m * m + (sx ? m * c : 0);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) rdiag[i] = 1.0 / T[i * m + i];
+    __syncthreads();
+  }
+  // columns per wavefront: spread the panel over all four
+  const int per = (c + 3) / 4;
+  if (m <= 64) {
+    if (per <= 2)
+      trsm_wave<1, 2>(a, X, T, m, kind, perm, c, sx, rdiag);
+    else if (per <= 4)
+      trsm_wave<1, 4>(a, X, T, m, kind, perm, c, sx, rdiag);
+    else
+      trsm_wave<1, 16>(a, X, T, m, kind, perm, c, sx, rdiag);
+  } else {
+    if (per <= 2)
+      trsm_wave<2, 2>(a, X, T, m, kind, perm, c, sx, rdiag);
+    else
+      trsm_wave<2, 8>(a, X, T, m, kind, perm, c, sx, rdiag);
+  }
   __syncthreads();
 }
 
