@@ -156,6 +156,28 @@ __device__ __forceinline__ void copy_batched(double* dst, const double* src, int
 }
 
 // ---------------------------------------------------------------------------
+// Jacobi rotation: for the column pair with squared norms al, be and inner
+// product ga (ga != 0), cs and sn of the rotation that makes the pair
+// orthogonal (Hestenes; t the smaller root of t^2 + 2 zeta t - 1 = 0).  The
+// square roots come from the hardware reciprocal square root with two Newton
+// steps (relative error near the rounding level).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& cs, double& sn) {
+  const double zeta = (be - al) / (2.0 * ga);
+  const double h = 1.0 + zeta * zeta;
+  const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + h * rsqrt_nr(h));
+  cs = rsqrt_nr(1.0 + tt * tt);
+  sn = cs * tt;
+}
+
+// ---------------------------------------------------------------------------
 // cross-lane reductions
 // ---------------------------------------------------------------------------
 // A double moved between lanes by a DPP pattern (both 32-bit halves).
@@ -568,6 +590,8 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
       trsm_wave<1, 2>(a, X, T, m, kind, perm, c, sx, rdiag);
     else if (per <= 4)
       trsm_wave<1, 4>(a, X, T, m, kind, perm, c, sx, rdiag);
+    else if (per <= 8)
+      trsm_wave<1, 8>(a, X, T, m, kind, perm, c, sx, rdiag);
     else
       trsm_wave<1, 16>(a, X, T, m, kind, perm, c, sx, rdiag);
   } else {
@@ -787,11 +811,10 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
       al = group_sum(al, tpp);
       be = group_sum(be, tpp);
       ga = group_sum(ga, tpp);
-      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && ga * ga > tol * tol * (al * be)) {
         if (lane == 0) s_flag[0] = 1;
-        double zeta = (be - al) / (2.0 * ga);
-        double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        double cs, sn;
+        jacobi_rotation(al, be, ga, cs, sn);
         for (int r = lane; r < p; r += tpp) {
           double x = B[ci * p + r], y = B[cj * p + r];
           B[ci * p + r] = cs * x - sn * y;
@@ -1066,11 +1089,10 @@ __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
       al = group_sum(al, tpp);
       be = group_sum(be, tpp);
       ga = group_sum(ga, tpp);
-      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+      if (ci >= 0 && ga != 0.0 && al > tiny && be > tiny && ga * ga > tol * tol * (al * be)) {
         rotated = 1;
-        double zeta = (be - al) / (2.0 * ga);
-        double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        double cs, sn;
+        jacobi_rotation(al, be, ga, cs, sn);
         for (int r = sub; r < p; r += tpp) {
           double x = B[ci * p + r], y = B[cj * p + r];
           B[ci * p + r] = cs * x - sn * y;
