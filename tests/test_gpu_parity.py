@@ -159,3 +159,64 @@ def test_edge_sizes():
         a_user[np.ix_(perm, perm)] = dense
         res = np.linalg.norm(b - a_user @ x, axis=0) / np.linalg.norm(b, axis=0)
         assert np.all(res <= 1e-6), (n, res)
+
+
+def test_mixed_precision_c1():
+    """FP32 off-diagonal storage (FP64 diagonal leaves, pivots, Gram/core SVD):
+    the same error bound against the exact matrix, ranks within +-2 of the
+    FP64 oracle's, and iterative refinement against the FP64 H-matvec reaching
+    1e-10 relative residual."""
+    p = Problem(2048, 32, 1e-6, prec=hm.MIXED)
+    f = hm.LU(p.A, p.opts)
+    of = H.hlu(p.oa, lazy=True)
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    err = H.lu_error_2norm(dense, gf, exact=True)
+    print(f"mixed ||PA-LU||/||A|| = {err:.3e}")
+    assert err <= 10 * p.eps
+    orank, grank = H.rank_table(of), H.rank_table(gf)
+    assert max(abs(grank[k] - orank[k]) for k in orank) <= 2
+    b = inputs.rhs(p.n, 8, seed=1)
+    xd = device_rhs(b)
+    _, iters, rel = f.solve(xd, refine_with=p.A, rtol=1e-10, max_iter=50)
+    assert np.all(rel <= 1e-10), rel
+    ga = p.gpu_as_oracle(0, p.A.h)
+    ah = np.empty((p.n, p.n))
+    ah[np.ix_(ga.perm, ga.perm)] = H.densify(ga.root)
+    x = to_host(xd)
+    res = np.linalg.norm(b - ah @ x, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(res <= 1e-9), res
+
+
+def test_solve_executors_identical(monkeypatch):
+    """The substitution DAG gives bit-identical solutions level by level and
+    with the persistent executor."""
+    p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False)
+    f = hm.LU(p.A, p.opts)
+    b = inputs.rhs(p.n, 5, seed=3)
+    out = []
+    for mode in ("level", "dataflow"):
+        monkeypatch.setenv("HM_SOLVE_EXEC", mode)
+        x = device_rhs(b)
+        f.solve(x)
+        out.append(to_host(x))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_reused_temporaries_on_device(monkeypatch):
+    """A ring of temporaries much smaller than the DAG needs (every slot reused
+    by temporaries of other shapes): repeated factorizations and both
+    executors give bit-identical factors, within the error bound."""
+    monkeypatch.setenv("HM_TEMP_BUDGET_GB", "0.0005")
+    p = Problem(2048, 32, 1e-4, max_rank=16)
+    b = inputs.rhs(p.n, 3, seed=4)
+    sols = []
+    for mode in (hm.DATAFLOW, hm.DATAFLOW, hm.LEVEL):
+        opts = hm.make_opts(leaf=32, eta=2.0, eps=1e-4, max_rank=16, exec_mode=mode)
+        f = hm.LU(p.A, opts)
+        x = device_rhs(b)
+        f.solve(x)
+        sols.append(to_host(x))
+    assert np.array_equal(sols[0], sols[1]) and np.array_equal(sols[0], sols[2])
+    gf = p.gpu_as_oracle(1, f.h)
+    assert H.lu_error_2norm(p.dense_exact(), gf, exact=True) <= 10 * p.eps
