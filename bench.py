@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--solves", type=int, default=10, help="solve requests timed for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip the plain FP64 H-LU of the same workload (reported beside the mixed one)")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")
@@ -175,6 +177,29 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
         print(f"# solve request {k}: {lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+    fp64 = None
+    if prec == hm.MIXED and not args.no_fp64_compare:
+        # the same factorization with every block in FP64 (plain form), timed the same way
+        o64 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=hm.FP64, exec_mode=exec_mode)
+        A64 = hm.Matrix(tree, hm.LAPLACE3D, diag, o64)
+        f64 = hm.LU(A64, o64)  # warm-up (traces the FP64 plan)
+        del f64
+        t64 = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            f64 = hm.LU(A64, o64)
+            torch.cuda.synchronize()
+            t64.append(((time.perf_counter() - t1) * 1e3, f64.stats()))
+            del f64
+        ms64 = float(np.median([x[0] for x in t64]))
+        st64 = t64[-1][1]
+        ach64 = st64["bytes_alg"] / (st64["exec_ms"] * 1e-3) / 1e9
+        fp64 = {"hlu_ms": ms64, "executor_ms": st64["exec_ms"], "achieved_hbm_gbs": ach64,
+                "roofline_frac": ach64 / HBM_PEAK_GBS, "bytes_alg": st64["bytes_alg"],
+                "mixed_speedup": ms64 / float(np.median(lu_ms))}
+        print(f"# plain FP64 H-LU: {ms64:.1f} ms (executor {st64['exec_ms']:.1f} ms)", file=sys.stderr, flush=True)
+        del A64
     med_exec = float(np.median(exec_ms))
     ach = st["bytes_alg"] / (med_exec * 1e-3) / 1e9
     cpu = None
@@ -227,6 +252,7 @@ def main():
                      "flops_alg_per_launch": st["flops_alg"],
                      "fp64_flop_frac": st["flops_alg"] / (med_exec * 1e-3) / (FP64_PEAK_TFS * 1e12)},
         "cpu_baseline": cpu,
+        "plain_fp64": fp64,
     }
     print(json.dumps(out), flush=True)
 

@@ -2144,7 +2144,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
       if (slot < a.ntasks) {
         const uint64_t t0 = wall_clock64();
         for (;;) {
-          t = __hip_atomic_load(&a.queue[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          t = __hip_atomic_load(&a.queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (t >= 0) break;
           if (__hip_atomic_load(&a.qctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
           if ((int64_t)(wall_clock64() - t0) > a.spin_limit) {
@@ -2168,8 +2168,12 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
     // Publication: every thread's stores precede the workgroup barrier; one
     // agent-scope release fence then makes them visible across XCDs before
     // any successor count drops.  The workgroup that releases a successor
-    // (its count reaches zero) orders the push after an acq_rel fence, so the
-    // consumer's acquire covers every predecessor's data.
+    // (its count reaches zero) puts an acq_rel fence between that decrement
+    // and the push: it acquires every other predecessor's release (their
+    // fences precede their decrements, which its decrement reads) and
+    // releases them with its own data, so the relaxed queue store needs no
+    // fence of its own.  The consumer reads the slot relaxed and then takes
+    // one agent-scope acquire fence.
     __syncthreads();
     if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -2182,7 +2186,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
           int pos = atomicAdd(&a.qctl[1], 1);
           if (a.trace) a.trace[(int64_t)kTraceWords * s + 7] = wall_clock64();
-          if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
