@@ -1169,14 +1169,16 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   double* TU = Z + K * K;
   double* TV = TU + K * K;
   char* vend = lds + kLdsBytes - 64;
-  double* dU = (double*)(vend - 3 * kSmallK * 8 - 5 * kSmallK * 4);
+  double* dU = (double*)(vend - 4 * kSmallK * 8 - 6 * kSmallK * 4);
   double* dV = dU + kSmallK;
   double* sig = dV + kSmallK;
-  int* pU = (int*)(sig + kSmallK);
+  double* qa = sig + kSmallK;
+  int* pU = (int*)(qa + kSmallK);
   int* pV = pU + kSmallK;
   int* sel = pV + kSmallK;
   int* posU = sel + kSmallK;
   int* posV = posU + kSmallK;
+  int* qpos = posV + kSmallK;
   double* buf = B;
   const int cap_rows = (int)(((char*)dU - (char*)buf) / 8 / K) - 1;
   // 1. Gram matrices
@@ -1221,26 +1223,96 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   }
   __syncthreads();
   phase_tick(a, lds, kCtrPhase + 2, &tph);
-  // 4. SVD of the core by wavefront 0
+  // 4. SVD of the core B (p = rU rows, q = rV columns) by wavefront 0:
+  //    Householder QR with column pivoting, stopped once the trailing columns
+  //    fall below 0.1 eps of the largest column (so B = Q R + E with
+  //    ||E||_F <= 0.1 eps sigma_1), then one-sided Jacobi on R^T (q x r):
+  //    R^T Z = W Sigma gives the right singular vectors W of B, and B W the
+  //    left ones times Sigma.  B itself is kept in Z's place for that product.
+  const int qq = rV;
   if (wave == 0) {
-    const int sw = jacobi_svd_wave(B, Z, rU, rV, eps);
-    trunc_note(lds, 1, rU, rV, sw, 0);
+    const int lane = tid & 63;
+    const int pp = rU, rmax = min(pp, qq);
+    double* cn = sig;  // squared norms of the trailing columns
+    for (int e = lane; e < pp * qq; e += 64) Z[e] = B[e];
+    if (lane < qq) {
+      double acc = 0.0;
+      for (int i = 0; i < pp; ++i) acc += B[lane * pp + i] * B[lane * pp + i];
+      cn[lane] = acc;
+      qpos[lane] = kSmallK;
+    }
+    wave_sync();
+    double mx = lane < qq ? cn[lane] : 0.0;
+    int mi = lane;
+    wave_argmax(mx, mi);
+    const double tol2 = 0.01 * eps * eps * mx;
+    int r = 0;
+    for (int st = 0;; ++st) {
+      double best = (lane < qq && qpos[lane] == kSmallK) ? cn[lane] : -1.0;
+      double sum = group_sum(best > 0.0 ? best : 0.0, 64);
+      int bi = lane < qq ? lane : qq;
+      wave_argmax(best, bi);
+      if (st == rmax || bi >= qq || sum <= tol2 || !(best > 0.0)) {
+        r = st;
+        break;
+      }
+      double* xp = B + bi * pp;
+      const double xi = (lane >= st && lane < pp) ? xp[lane] : 0.0;
+      const double nrm2 = group_sum(xi * xi, 64);
+      const double x0 = xp[st];
+      const double nr = sqrt(nrm2);
+      const double al = x0 >= 0.0 ? -nr : nr;
+      const double v0 = x0 - al;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+      const double be = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      wave_sync();
+      if (lane == 0) {
+        xp[st] = v0;
+        qa[st] = al;
+        qpos[bi] = st;
+      }
+      wave_sync();
+      if (lane < qq && qpos[lane] == kSmallK) {
+        double* xj = B + lane * pp;
+        double w = 0.0;
+        for (int i = st; i < pp; ++i) w += xp[i] * xj[i];
+        const double f = be * w;
+        double nn = 0.0;
+        for (int i = st; i < pp; ++i) {
+          const double y = xj[i] - f * xp[i];
+          xj[i] = y;
+          if (i > st) nn += y * y;
+        }
+        cn[lane] = nn;
+      }
+      wave_sync();
+    }
+    // R^T (q x r; column s is row s of R) in TU, its rotations in TV
+    for (int e = lane; e < qq * r; e += 64) {
+      const int j = e % qq, s2 = e / qq, pj = qpos[j];
+      TU[e] = pj == s2 ? qa[s2] : (pj > s2 ? B[j * pp + s2] : 0.0);
+    }
+    wave_sync();
+    const int sw = r > 0 ? jacobi_svd_wave(TU, TV, qq, r, eps) : 0;
+    if (lane == 0) s_int[3] = r;
+    trunc_note(lds, 1, qq, r, sw, 0);
   }
   __syncthreads();
+  const int rr = s_int[3];
   phase_tick(a, lds, kCtrPhase + 3, &tph);
-  // 5. order, truncation rank
-  for (int j = tid; j < rV; j += blockDim.x) {
+  // 5. order, truncation rank (singular values: column norms of R^T Z)
+  for (int j = tid; j < rr; j += blockDim.x) {
     double s = 0.0;
-    for (int r = 0; r < rU; ++r) s += B[j * rU + r] * B[j * rU + r];
+    for (int r = 0; r < qq; ++r) s += TU[j * qq + r] * TU[j * qq + r];
     sig[j] = sqrt(s);
   }
   if (tid == 0) s_int[2] = 0;
   __syncthreads();
   double smax = 0.0;
-  for (int j = 0; j < rV; ++j) smax = fmax(smax, sig[j]);
-  for (int j = tid; j < rV; j += blockDim.x) {
+  for (int j = 0; j < rr; ++j) smax = fmax(smax, sig[j]);
+  for (int j = tid; j < rr; j += blockDim.x) {
     int rk = 0;
-    for (int l = 0; l < rV; ++l)
+    for (int l = 0; l < rr; ++l)
       if (sig[l] > sig[j] || (sig[l] == sig[j] && l < j)) ++rk;
     sel[rk] = j;
     if (smax > 0.0 && sig[j] > eps * smax) atomicAdd(&s_int[2], 1);
@@ -1262,13 +1334,20 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   //    into rows by permutation and scale in place of B / Z
   double* yu = TU;
   double* yv = TV;
-  for (int e = tid; e < rU * kk; e += blockDim.x) {
-    int i = e % rU, c = e / rU;
-    yu[c * rU + i] = B[sel[c] * rU + i];
-  }
-  for (int e = tid; e < rV * kk; e += blockDim.x) {
-    int i = e % rV, c = e / rV;
-    yv[c * rV + i] = Z[sel[c] * rV + i];
+  {
+    double* vc = B;  // right singular vectors (rV x kk), unit columns
+    for (int e = tid; e < rV * kk; e += blockDim.x) {
+      const int i = e % rV, c = e / rV, j = sel[c];
+      vc[e] = TU[j * qq + i] / sig[j];
+    }
+    __syncthreads();
+    for (int e = tid; e < rU * kk; e += blockDim.x) {  // B V (rU x kk), B kept in Z
+      const int i = e % rU, c = e / rU;
+      double acc = 0.0;
+      for (int j = 0; j < rV; ++j) acc += Z[j * rU + i] * vc[c * rV + j];
+      yu[e] = acc;
+    }
+    for (int e = tid; e < rV * kk; e += blockDim.x) yv[e] = vc[e];
   }
   __syncthreads();
   upper_solve(GU, K, rU, yu, kk);
