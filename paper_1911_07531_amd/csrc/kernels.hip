@@ -926,6 +926,61 @@ __device__ __forceinline__ ColRef stack_col(const ExecArgs& a, const Stack& st, 
   return col_of(st.t2, a, i, st.r2, min(st.m, st.r2 + st.t2.rows), st.alpha2);
 }
 
+
+// A stack column resolved once into LDS for streaming: stack row r reads
+// element (r - lo) * rs of `base` (FP32 when is32) times scale inside
+// [lo, hi); an identity column holds scale at row `one`.
+struct ColDesc {
+  const void* base;
+  int lo, hi, one, rs, is32, pad_;
+  double scale;
+};
+
+__device__ __forceinline__ double desc_ld(const ColDesc& d, int r) {
+  if (r < d.lo || r >= d.hi) return 0.0;
+  if (d.one >= 0) return r == d.one ? d.scale : 0.0;
+  const int64_t k = (int64_t)(r - d.lo) * d.rs;
+  return d.scale * (d.is32 ? (double)((const float*)d.base)[k] : ((const double*)d.base)[k]);
+}
+
+// Descriptors of the K columns of a stack (threads t0 .. t0 + K - 1).
+__device__ __forceinline__ void stack_descs(const ExecArgs& a, const Stack& st, int K, ColDesc* out, int t0) {
+  const int c = (int)threadIdx.x - t0;
+  if (c >= 0 && c < K) {
+    const ColRef r = stack_col(a, st, c);
+    ColDesc d;
+    d.base = r.p64 ? (const void*)(r.p64 + r.base) : r.p32 ? (const void*)(r.p32 + r.base) : nullptr;
+    d.lo = r.lo;
+    d.hi = (d.base || r.one >= 0) ? r.hi : r.lo;
+    d.one = r.one;
+    d.rs = r.rs;
+    d.is32 = r.p32 != nullptr && r.p64 == nullptr;
+    d.pad_ = 0;
+    d.scale = r.scale;
+    out[c] = d;
+  }
+}
+
+// Copies rows [r0, r0 + rows) of a stack of K described columns into buf
+// (column c at buf + c * ld): element e = c * rows + i, sixteen per thread in
+// flight, consecutive threads on consecutive rows.
+__device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, int rows, double* buf, int ld) {
+  const int total = rows * K;
+  for (int base = 0; base < total; base += 16 * kThreads) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      v[u] = e < total ? desc_ld(desc[e / rows], r0 + e % rows) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < total) buf[(e / rows) * ld + e % rows] = v[u];
+    }
+  }
+}
+
 // Copies rows [r0, r0 + rows) of the stacked panel st (K columns) into buf
 // (column c at buf + c * ld), four columns at a time so that several loads
 // per thread are in flight.
@@ -948,13 +1003,18 @@ __device__ __forceinline__ void stage_rows(const ExecArgs& a, const Stack& st, i
 
 // G = X^T X (K x K, row-major) for X = the stacked panel st (m x K), staged
 // through LDS in chunks of up to `cap_rows` rows.
-__device__ void gram_stream(const ExecArgs& a, const Stack& st, int K, int m, double* G, double* buf, int cap_rows) {
+__device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, double* G,
+                            double* buf, int cap_rows) {
   const int tid = threadIdx.x;
   const int ld = cap_rows | 1;  // odd stride: conflict-free column reads
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // K*K <= 1024 entries: at most 4 per thread
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    stage_rows(a, st, K, r0, rows, buf, ld);
+    // short chunks: one batch over all columns; tall ones: column groups
+    if (rows <= kThreads)
+      stage_desc(desc, K, r0, rows, buf, ld);
+    else
+      stage_rows(a, st, K, r0, rows, buf, ld);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1117,13 +1177,18 @@ __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
 // (K x kk, column-major, LDS).  Rows are staged through LDS in chunks; a
 // chunk is read completely before any of its rows is written, so out may
 // alias the panel's C columns.
-__device__ void rebuild_stream(const ExecArgs& a, const Stack& st, int K, int m, const double* T, int kk, RV out,
+__device__ void rebuild_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, const double* T,
+                               int kk, RV out,
                                double* buf, int cap_rows) {
   const int tid = threadIdx.x;
   const int ld = cap_rows | 1;
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    stage_rows(a, st, K, r0, rows, buf, ld);
+    // short chunks: one batch over all columns; tall ones: column groups
+    if (rows <= kThreads)
+      stage_desc(desc, K, r0, rows, buf, ld);
+    else
+      stage_rows(a, st, K, r0, rows, buf, ld);
     __syncthreads();
     for (int e = tid; e < rows * kk; e += blockDim.x) {
       int i = e % rows, c = e / rows;
@@ -1179,11 +1244,17 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   int* posU = sel + kSmallK;
   int* posV = posU + kSmallK;
   int* qpos = posV + kSmallK;
+  // column descriptors of the two stacks, below the vectors
+  ColDesc* descU = (ColDesc*)dU - 2 * kSmallK;
+  ColDesc* descV = descU + kSmallK;
+  stack_descs(a, su, K, descU, 0);
+  stack_descs(a, sv, K, descV, 64);
+  __syncthreads();
   double* buf = B;
-  const int cap_rows = (int)(((char*)dU - (char*)buf) / 8 / K) - 1;
+  const int cap_rows = (int)(((char*)descU - (char*)buf) / 8 / K) - 1;
   // 1. Gram matrices
-  gram_stream(a, su, K, m, GU, buf, cap_rows);
-  gram_stream(a, sv, K, n, GV, buf, cap_rows);
+  gram_stream(a, su, descU, K, m, GU, buf, cap_rows);
+  gram_stream(a, sv, descV, K, n, GV, buf, cap_rows);
   __syncthreads();
   phase_tick(a, lds, kCtrPhase + 0, &tph);
   // 2. R factors: wavefront 0 factors G_U, wavefront 1 factors G_V
@@ -1366,9 +1437,9 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   // 7. rebuild in place (staging buffer after T_U / T_V in the B / Z region)
   {
     double* rbuf = Z + K * K;
-    const int rcap = (int)(((char*)dU - (char*)rbuf) / 8 / K) - 1;
-    rebuild_stream(a, su, K, m, T_U, kk, RV{d.u_off, m, kk, 1, m, d.type}, rbuf, rcap);
-    rebuild_stream(a, sv, K, n, T_V, kk, RV{d.v_off, n, kk, 1, n, d.type}, rbuf, rcap);
+    const int rcap = (int)(((char*)descU - (char*)rbuf) / 8 / K) - 1;
+    rebuild_stream(a, su, descU, K, m, T_U, kk, RV{d.u_off, m, kk, 1, m, d.type}, rbuf, rcap);
+    rebuild_stream(a, sv, descV, K, n, T_V, kk, RV{d.v_off, n, kk, 1, n, d.type}, rbuf, rcap);
   }
   __syncthreads();
   phase_tick(a, lds, kCtrPhase + 5, &tph);
