@@ -1,7 +1,8 @@
 """Benchmark: H-LU time and achieved HBM GB/s at n=131072, eps=1e-4 (sphere
 single-layer workload, leaf 64, eta 2, rank cap 64, mixed precision), plus
 solve latency (32 N(0,1) right-hand sides refined to 1e-10 against the FP64
-H-matvec).
+H-matvec).  --workload line_* runs the one-dimensional log-kernel model
+problem (Sec. 5.1) instead: a coarse block structure with a deep hierarchy.
 
 One step = h_lu of the resident H-matrix + h_solve of 32 RHS with
 refinement.  Inputs (tree, traced DAG, assembled matrix) are resident before
@@ -30,7 +31,19 @@ WORKLOADS = {
     "sphere_n131072_eps1e-4_fp64": (131072, 64, 1e-4, 64, 0),
     "sphere_n32768_eps1e-6_fp64": (32768, 64, 1e-6, 64, 0),
     "sphere_n2048_eps1e-6_fp64": (2048, 32, 1e-6, 0, 0),
+    "line_n131072_eps1e-4_mixed": (131072, 64, 1e-4, 64, 1),
+    "line_n1048576_eps1e-4_mixed": (1048576, 64, 1e-4, 64, 1),
 }
+
+
+def problem(workload, n):
+    """(points, diag, device kernel id, oracle kernel name) of a workload's geometry at size n."""
+    from paper_1911_07531_amd import hm, inputs
+    if workload.startswith("line"):
+        pts, diag = inputs.line_problem(n)
+        return pts, diag, hm.LOG2D, "log2d"
+    pts, diag = inputs.sphere_problem(n, 0)
+    return pts, diag, hm.LAPLACE3D, "laplace3d"
 
 
 def parse():
@@ -69,14 +82,13 @@ def measured_traffic(workload, executor):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n_sample, leaf, eps, max_rank, lazy):
+def cpu_baseline(workload, n_sample, leaf, eps, max_rank, lazy):
     """Time the FP64 oracle's H-LU on a bounded sample of the same workload."""
     from oracle import hmatrix as H
-    from paper_1911_07531_amd import inputs
-    pts, diag = inputs.sphere_problem(n_sample, 0)
+    pts, diag, _, kname = problem(workload, n_sample)
     perm, cl = H.build_cluster_tree(pts, leaf)
     root = H.build_block_tree(cl[0], 2.0)
-    a = H.assemble(pts, perm, cl, root, diag, eps, max_rank)
+    a = H.assemble(pts, perm, cl, root, diag, eps, max_rank, kernel=kname)
     t0 = time.perf_counter()
     H.hlu(a, lazy=bool(lazy))
     dt = time.perf_counter() - t0
@@ -106,17 +118,16 @@ def main():
     n, leaf, eps, max_rank, prec = WORKLOADS[args.workload]
     exec_mode = hm.DATAFLOW if args.exec_mode == "dataflow" else hm.LEVEL
     torch.cuda.set_device(0)
-    pts, diag = inputs.sphere_problem(n, 0)
+    pts, diag, kern, _ = problem(args.workload, n)
     opts = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode)
     t0 = time.perf_counter()
     tree = hm.Tree(pts, opts)
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
-    A = hm.Matrix(tree, hm.LAPLACE3D, diag, opts)
+    A = hm.Matrix(tree, kern, diag, opts)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     t0 = time.perf_counter()
-    tree.dag(opts, 0) if False else None
     sz = np.zeros(9, np.int64)
     hm._check(hm.lib().hm_dag_sizes(tree.h, hm.C.byref(opts), 0, sz.ctypes.data))
     t_trace = time.perf_counter() - t0
@@ -181,7 +192,7 @@ def main():
     if prec == hm.MIXED and not args.no_fp64_compare:
         # the same factorization with every block in FP64 (plain form), timed the same way
         o64 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=hm.FP64, exec_mode=exec_mode)
-        A64 = hm.Matrix(tree, hm.LAPLACE3D, diag, o64)
+        A64 = hm.Matrix(tree, kern, diag, o64)
         f64 = hm.LU(A64, o64)  # warm-up (traces the FP64 plan)
         del f64
         t64 = []
@@ -205,14 +216,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline: oracle H-LU on the sample ...", file=sys.stderr, flush=True)
-        t_cpu = cpu_baseline(args.cpu_sample_n, leaf, eps, max_rank, opts.lazy)
+        t_cpu = cpu_baseline(args.workload, args.cpu_sample_n, leaf, eps, max_rank, opts.lazy)
         # scale the sample by the ratio of algorithmic flops (n log^2 n growth measured on the GPU side)
         f_s = None
         try:
-            p2 = inputs.sphere_points(args.cpu_sample_n, 0)
+            p2, d2, k2, _ = problem(args.workload, args.cpu_sample_n)
             o2 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode)
             t2 = hm.Tree(p2, o2)
-            A2 = hm.Matrix(t2, hm.LAPLACE3D, inputs.sphere_self_term(args.cpu_sample_n), o2)
+            A2 = hm.Matrix(t2, k2, d2, o2)
             f2 = hm.LU(A2, o2)
             f_s = f2.stats()["flops_alg"]
         except Exception:

@@ -62,7 +62,9 @@ typedef enum {
 
 typedef enum {
   HM_LAPLACE3D = 0, /* a_ij = 1 / (4 pi |x_i - x_j|) */
-  HM_LOG2D = 1      /* a_ij = -log |x_i - x_j| / (2 pi) */
+  HM_LOG2D = 1      /* a_ij = -log |x_i - x_j| / (2 pi); with points on a line the
+                       kernel of the one-dimensional model problem (Sec. 5.1)
+                       up to the factor -1/(2 pi) */
 } hm_kernel;
 
 typedef enum {
@@ -77,8 +79,8 @@ typedef struct {
   int max_rank;     /* rank cap, 0 = none (then the capacity 64 bounds it) */
   int prec;         /* hm_precision */
   int exec;         /* hm_exec of the factorization; the substitution DAGs of
-                       h_solve, a few tasks per level, always run one launch
-                       per level */
+                       h_solve, a few tasks per level, always run on the
+                       persistent executor with 128 workgroups */
   int lazy;         /* 0: truncate every update of a low-rank leaf when it is
                        produced, in the sequential order of Algorithm 1;
                        1: collect the updates of a low-rank leaf and add them
@@ -111,8 +113,9 @@ hm_status hm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx)
                            void (*dealloc)(void* ptr, size_t bytes, void* stream, void* ctx), void* ctx);
 
 /* Cluster tree + block tree (host only, no device needed).
- * pts_host: n x dim, row-major, FP64, caller-owned (copied).  dim in {2, 3}.
- * Uses opts->leaf and opts->eta. */
+ * pts_host: n x dim, row-major, FP64, caller-owned (copied).  dim in {1, 2, 3};
+ * points are embedded in R^3 with zero trailing coordinates (the kernels of
+ * h_assemble see the 3D distance).  Uses opts->leaf and opts->eta. */
 hm_status build_htree(const double* pts_host, int64_t n, int dim, const hm_opts* opts, hm_tree* out);
 
 /* Tree tables (host): sizes, then copies.  Any output pointer may be NULL.

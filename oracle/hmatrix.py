@@ -39,6 +39,11 @@ Readings where the paper is silent (each one is listed in the design notes):
       top-level hmul call collects the exact low-rank terms it produces for
       every low-rank leaf and applies them in one truncation,
       C <- T_eps(C + sum of terms), when it returns.
+  R7  the one-dimensional model problem of Sec. 5.1 uses the kernel
+      -log|x - y| / (2 pi), a negative multiple of the printed log|x - y|
+      (same block ranks, same pivot order in exact arithmetic, a positive
+      definite operator on [0, 1]); the diagonal holds the kernel's mean over
+      the collocation cell.
 
 Parity is pinned in tests/test_oracle_*.py against: scipy's getrf on the same
 leaf block, Eckart-Young for compression, brute-force tiling of the block
@@ -226,16 +231,31 @@ class HMatrix:
 # ---------------------------------------------------------------------------
 # Entries and compression (Sec. 2.1: admissible blocks approximable to eps)
 # ---------------------------------------------------------------------------
-def kernel_block(points, perm, rows: Cluster, cols: Cluster, diag: float, r=None, c=None) -> np.ndarray:
-    """Entries a_ij = 1/(4 pi |x_i - x_j|), a_ii = diag, for permuted index ranges."""
+KERNELS = ("laplace3d", "log2d")
+
+
+def kernel_block(points, perm, rows: Cluster, cols: Cluster, diag: float, r=None, c=None,
+                 kernel: str = "laplace3d") -> np.ndarray:
+    """Entries a_ij = k(|x_i - x_j|), a_ii = diag, for permuted index ranges.
+
+    kernel "laplace3d": k(d) = 1/(4 pi d), the single layer potential of the
+    sphere problem (Sec. 5.1); "log2d": k(d) = -log(d)/(2 pi), the kernel of
+    the one-dimensional model problem (Sec. 5.1) with the sign and scale of
+    the 2D Laplace fundamental solution (Reading R7).
+    """
+    if kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}")
     ri = perm[rows.begin:rows.end] if r is None else perm[r[0]:r[1]]
     ci = perm[cols.begin:cols.end] if c is None else perm[c[0]:c[1]]
     x = points[ri]
     y = points[ci]
     d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2))
     same = ri[:, None] == ci[None, :]
-    with np.errstate(divide="ignore"):
-        a = 1.0 / (FOUR_PI * d)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        if kernel == "laplace3d":
+            a = 1.0 / (FOUR_PI * d)
+        else:
+            a = -np.log(d) / (2.0 * math.pi)
     a[same] = diag
     return a
 
@@ -285,7 +305,7 @@ RANDOMIZED_MIN_SIDE = 2048
 
 
 def assemble(points, perm, clusters, root: Block, diag: float, eps: float, max_rank: int = 0,
-             seed: int = 0) -> HMatrix:
+             seed: int = 0, kernel: str = "laplace3d") -> HMatrix:
     """Fill the leaves of the block tree (Def. 2.3).
 
     Dense leaves hold the entries; admissible leaves hold the truncated SVD of
@@ -295,11 +315,12 @@ def assemble(points, perm, clusters, root: Block, diag: float, eps: float, max_r
     points = np.asarray(points, dtype=np.float64)
     for b in leaf_blocks(root):
         if b.kind == "D":
-            b.D = kernel_block(points, perm, b.tau, b.sigma, diag)
+            b.D = kernel_block(points, perm, b.tau, b.sigma, diag, kernel=kernel)
         else:
             m, n = b.rows, b.cols
             if min(m, n) <= RANDOMIZED_MIN_SIDE:
-                b.U, b.V = _compress_dense(kernel_block(points, perm, b.tau, b.sigma, diag), eps, max_rank)
+                b.U, b.V = _compress_dense(kernel_block(points, perm, b.tau, b.sigma, diag, kernel=kernel), eps,
+                                           max_rank)
             else:
                 chunk = 4096
 
@@ -308,7 +329,7 @@ def assemble(points, perm, clusters, root: Block, diag: float, eps: float, max_r
                     for c0 in range(0, b.cols, chunk):
                         c1 = min(b.cols, c0 + chunk)
                         blk = kernel_block(points, perm, b.tau, b.sigma, diag,
-                                           c=(b.sigma.begin + c0, b.sigma.begin + c1))
+                                           c=(b.sigma.begin + c0, b.sigma.begin + c1), kernel=kernel)
                         out += blk @ x[c0:c1]
                     return out
 
@@ -317,7 +338,7 @@ def assemble(points, perm, clusters, root: Block, diag: float, eps: float, max_r
                     for c0 in range(0, b.cols, chunk):
                         c1 = min(b.cols, c0 + chunk)
                         blk = kernel_block(points, perm, b.tau, b.sigma, diag,
-                                           c=(b.sigma.begin + c0, b.sigma.begin + c1))
+                                           c=(b.sigma.begin + c0, b.sigma.begin + c1), kernel=kernel)
                         out[c0:c1] = blk.T @ y
                     return out
 

@@ -235,6 +235,15 @@ static int64_t temp_budget() {
   return (int64_t)(gb * (double)(1ll << 30));
 }
 
+// Row chunk of the low-rank products that the substitution DAG splits over
+// several workgroups (those with a side of at least twice this); 0 = none.
+// HM_SOLVE_SPLIT overrides it.
+static int32_t solve_split_rows() {
+  int v = 1024;
+  if (const char* e = getenv("HM_SOLVE_SPLIT")) v = std::max(0, atoi(e));
+  return v;
+}
+
 static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out) {
   std::lock_guard<std::mutex> lk(t->mu);
   auto key = std::make_tuple(prec, max_rank, lazy);
@@ -250,7 +259,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
   }
   if (need_trace && !pe->traced) {
     if (!trace_lu(pe->plan, temp_budget(), lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
-    if (!trace_solve(pe->plan)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_solve(pe->plan, solve_split_rows())) return fail(HM_EINVAL, pe->plan.err);
     pe->traced = true;
   }
   *out = pe;
@@ -318,7 +327,15 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.status = (int32_t*)es.status.p;
   a.counters = (unsigned long long*)es.counters.p;
   a.trace = (uint64_t*)es.trace.p;
-  a.nwg = g_nwg;
+  int nwg = g_nwg;
+  // The substitution DAG has a few tasks per level: 128 persistent
+  // workgroups hold every ready task (HM_SOLVE_NWG overrides the count).
+  if (solve && mode != HM_EXEC_LEVEL) {
+    int v = 128;
+    if (const char* e = getenv("HM_SOLVE_NWG")) v = atoi(e);
+    if (v >= 1 && v < nwg) nwg = v;
+  }
+  a.nwg = nwg;
   a.spin_limit = g_clock_khz * 1000 * 30;  // 30 s of wall clock
   hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
   HIPCHK(hipMemsetAsync(es.counters.p, 0, kCtrSize * 8, s));
@@ -346,7 +363,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e0, s));
     if (solve)
-      hipLaunchKernelGGL(solve_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
+      hipLaunchKernelGGL(solve_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     else
       hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
@@ -399,8 +416,8 @@ hm_status hm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*dealloc)
 
 hm_status build_htree(const double* pts, int64_t n, int dim, const hm_opts* opts, hm_tree* out) {
   if (!pts || !out || !opts) return fail(HM_EINVAL, "null pointer");
-  if (n < 1 || opts->leaf < 1 || !(opts->eta > 0) || (dim != 2 && dim != 3))
-    return fail(HM_EINVAL, "need n >= 1, leaf >= 1, eta > 0, dim in {2,3}");
+  if (n < 1 || opts->leaf < 1 || !(opts->eta > 0) || dim < 1 || dim > 3)
+    return fail(HM_EINVAL, "need n >= 1, leaf >= 1, eta > 0, dim in {1,2,3}");
   if (n > (int64_t)1 << 30) return fail(HM_EINVAL, "n too large");
   auto t = new (std::nothrow) hm_tree_s();
   if (!t) return fail(HM_ENOMEM, "host allocation failed");
@@ -862,11 +879,11 @@ static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
                      0, 1);
   ExecArgs a = base_args((double*)F->f64.p, (float*)F->f32.p, (int32_t*)F->piv.p, (int32_t*)F->ranks.p,
                          (const LrDesc*)pe->lr.p, F->eps, F->max_rank);
-  // The substitution DAG is narrow (a few tasks per level): one launch per
-  // level beats the persistent executor's hand-offs there.
-  // HM_SOLVE_EXEC=dataflow selects the persistent executor instead.
-  int mode = HM_EXEC_LEVEL;
-  if (const char* e = getenv("HM_SOLVE_EXEC")) mode = e[0] == 'd' ? HM_EXEC_DATAFLOW : HM_EXEC_LEVEL;
+  // The substitution DAG runs on the persistent executor (a hand-off costs
+  // less than a launch per level); HM_SOLVE_EXEC=level selects one launch
+  // per level instead.
+  int mode = HM_EXEC_DATAFLOW;
+  if (const char* e = getenv("HM_SOLVE_EXEC")) mode = e[0] == 'l' ? HM_EXEC_LEVEL : HM_EXEC_DATAFLOW;
   return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, true);
 }
 

@@ -23,11 +23,13 @@ constexpr int kLdsBytes = 76 * 1024;  // dynamic LDS per workgroup (two workgrou
 constexpr double kInnerEps = 0.1;
 
 enum ViewType : int32_t { VT_F64 = 0, VT_F32 = 1, VT_IDENT = 2, VT_NONE = 3 };
-enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2 };
+enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2, DYN_COLS2 = 4 };
 
 // Strided matrix view: element (i, j) lives at arena[off + i*rs + j*cs].
 // With DYN_ROWS / DYN_COLS the extent is ranks[rank_id] (a low-rank leaf's
-// current rank, or the nrhs of a solve), bounded by rows / cols.
+// current rank, or the nrhs of a solve), bounded by rows / cols; with
+// DYN_COLS2 the column count is ranks[rank_id2] instead (a view whose rows
+// follow a rank and whose columns follow the nrhs).
 struct View {
   int64_t off;
   int32_t rows, cols;
@@ -35,7 +37,7 @@ struct View {
   int32_t type;
   int32_t dyn;
   int32_t rank_id;
-  int32_t pad_;
+  int32_t rank_id2;
 };
 
 enum Op : int32_t {
@@ -50,7 +52,8 @@ enum Op : int32_t {
   OP_ZERO = 8,     // y <- 0
   OP_COPY = 9,     // y <- a (element type conversion allowed)
   OP_TRUNC2 = 10,  // accumulator lr <- T_eps(alpha pad(a) pad(b)^T + beta pad(x) pad(y)^T)
-  OP_COUNT = 11,
+  OP_GEMMP = 11,   // y <- y + alpha a (b_0 + ... + b_{r0-1}), b_p = b shifted by p * piv elements
+  OP_COUNT = 12,
 };
 
 struct Task {

@@ -288,6 +288,15 @@ class Tracer {
     temp_base_ = p.prec == 1 ? p.blocks_f32 : p.n_f64;
     temp_top_ = temp_base_;
   }
+  // Substitution DAGs: temporaries in FP64 after the factor's FP64 arena, and
+  // low-rank products with a side of at least 2 * rows rows split into
+  // partial products of about `rows` rows (0 = never split).
+  void set_solve(int32_t split_rows) {
+    tsize_ = 8;
+    temp_type_ = VT_F64;
+    temp_base_ = temp_top_ = p_.n_f64;
+    split_ = split_rows;
+  }
 
   bool ok() const { return err_.empty(); }
   const std::string& err() const { return err_; }
@@ -568,7 +577,7 @@ class Tracer {
     if (bn.kind == BK_DENSE) {
       gemm(y, alpha, dense(b), x, 1.0);
     } else if (bn.kind == BK_LOWRANK) {
-      lrgemm(y, alpha, lr_u(b), transpose(lr_v(b)), x, 1.0);
+      lr_mul_into(y, alpha, lr_u(b), lr_v(b), x);
     } else {
       int64_t rb = t_.cl[bn.tau].begin, cb = t_.cl[bn.sigma].begin;
       for (int i = 0; i < 2; ++i)
@@ -581,13 +590,58 @@ class Tracer {
         }
     }
   }
+  // y += alpha U (V^T x) for the factors U (m x k), V (n2 x k) of a low-rank
+  // leaf.  Large ones become P partial products W_p = V_p^T x_p over row
+  // chunks of x (one FP64 temporary, k x c each at a fixed stride) and Q
+  // tasks y_q += alpha U_q (W_0 + ... + W_{P-1}) over row chunks of y, so
+  // that one product runs on P + Q workgroups instead of one.
+  void lr_mul_into(const HView& y, double alpha, const HView& U, const HView& V, const HView& x) {
+    const int32_t m = y.v.rows, n2 = V.v.rows;
+    if (split_ <= 0 || std::max(m, n2) < 2 * split_) {
+      lrgemm(y, alpha, U, transpose(V), x, 1.0);
+      return;
+    }
+    const int32_t cap = U.v.cols, cw = x.v.cols;
+    const int P = (n2 + split_ - 1) / split_, Q = (m + split_ - 1) / split_;
+    HView W = temp(cap, cw * P, -1);
+    const int64_t stride = (int64_t)cap * cw;
+    auto part = [&](int p) {
+      HView w = W;
+      w.v.off = W.v.off + p * stride;
+      w.v.cols = cw;
+      w.v.dyn = DYN_ROWS | DYN_COLS2;
+      w.v.rank_id = U.v.rank_id;
+      w.v.rank_id2 = x.v.rank_id;
+      w.rect = Rect{0, cap, p * cw, (p + 1) * cw};
+      return w;
+    };
+    for (int p = 0; p < P; ++p) {
+      const int32_t r0 = (int32_t)((int64_t)n2 * p / P), r1 = (int32_t)((int64_t)n2 * (p + 1) / P);
+      gemm(part(p), 1.0, transpose(rows(V, r0, r1)), rows(x, r0, r1), 0.0);
+    }
+    HView w0 = part(0);
+    w0.rect = W.rect;
+    for (int q = 0; q < Q; ++q) {
+      const int32_t r0 = (int32_t)((int64_t)m * q / Q), r1 = (int32_t)((int64_t)m * (q + 1) / Q);
+      HView yq = rows(y, r0, r1), uq = rows(U, r0, r1);
+      Task t = blank(OP_GEMMP);
+      t.alpha = alpha;
+      t.beta = 1.0;
+      t.y = yq.v;
+      t.a = uq.v;
+      t.b = w0.v;
+      t.r0 = P;
+      t.piv = stride;
+      emit(t, {{&uq, ACC_R}, {&w0, ACC_R}, {&yq, ACC_RW}});
+    }
+  }
   // y += alpha B^T x
   void hmat_tmul_into(const HView& y, double alpha, int b, const HView& x) {
     const BlockNode& bn = t_.bl[b];
     if (bn.kind == BK_DENSE) {
       gemm(y, alpha, transpose(dense(b)), x, 1.0);
     } else if (bn.kind == BK_LOWRANK) {
-      lrgemm(y, alpha, lr_v(b), transpose(lr_u(b)), x, 1.0);
+      lr_mul_into(y, alpha, lr_v(b), lr_u(b), x);
     } else {
       int64_t rb = t_.cl[bn.tau].begin, cb = t_.cl[bn.sigma].begin;
       for (int i = 0; i < 2; ++i)
@@ -1014,6 +1068,7 @@ class Tracer {
   std::vector<int> touched_;                   // leaves with collected updates in this call
   int scope_ = 0;                              // depth of nested hmul calls
   bool lazy_ = false;
+  int32_t split_ = 0;                          // row chunk of split low-rank products (solve DAGs)
   std::vector<Pool> pools_;
   std::vector<int> preds_;
   std::vector<std::pair<int, int>> edges_;
@@ -1048,9 +1103,10 @@ bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
   return true;
 }
 
-bool trace_solve(Plan& p) {
+bool trace_solve(Plan& p, int32_t split_rows) {
   p.solve = Dag();
   Tracer tr(p, p.solve, 0);
+  tr.set_solve(split_rows);
   HView x = tr.panel();
   tr.solve_lower(0, x);
   tr.solve_upper(0, x);
@@ -1059,6 +1115,7 @@ bool trace_solve(Plan& p) {
     return false;
   }
   tr.finish();
+  p.n_f64 = std::max(p.n_f64, tr.temp_end());
   return true;
 }
 

@@ -83,6 +83,6 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
 // lazy: collect the updates of each low-rank leaf and add them with a balanced
 // tree of truncations when the leaf is next read (accumulator arithmetic).
 bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy);
-bool trace_solve(Plan& p);
+bool trace_solve(Plan& p, int32_t split_rows);
 
 }  // namespace hm

@@ -30,7 +30,7 @@ __device__ __forceinline__ RV resolve(const ExecArgs& a, const View& v) {
   RV r;
   r.off = v.off;
   r.rows = (v.dyn & DYN_ROWS) ? a.ranks[v.rank_id] : v.rows;
-  r.cols = (v.dyn & DYN_COLS) ? a.ranks[v.rank_id] : v.cols;
+  r.cols = (v.dyn & DYN_COLS2) ? a.ranks[v.rank_id2] : (v.dyn & DYN_COLS) ? a.ranks[v.rank_id] : v.cols;
   r.rs = v.rs;
   r.cs = v.cs;
   r.type = v.type;
@@ -404,7 +404,289 @@ __device__ void op_lrgemm_ct(const ExecArgs& a, const Task& t, char* lds) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Products of the forward / backward substitution (solve executors only).
+// A solve applies each low-rank block as y += alpha U (V^T x) with c <= 64
+// panel columns: a tall-skinny reduction over the block's columns followed by
+// a row-wise update.  Both stream their operands through LDS in chunks, 32
+// loads per thread in flight, and compute with 4 x 4 register tiles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stage_pair(const ExecArgs& a, const RV& v0, double* d0, const RV& v1, double* d1) {
+  const int c0 = v0.rows * v0.cols, total = c0 + v1.rows * v1.cols;
+  for (int base = 0; base < total; base += 32 * kThreads) {
+    double v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      v[u] = 0.0;
+      if (e < c0)
+        v[u] = vld(a, v0, e % v0.rows, e / v0.rows);
+      else if (e < total)
+        v[u] = vld(a, v1, (e - c0) % v1.rows, (e - c0) / v1.rows);
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = base + u * kThreads + (int)threadIdx.x;
+      if (e < c0)
+        d0[e] = v[u];
+      else if (e < total)
+        d1[e - c0] = v[u];
+    }
+  }
+}
+
+// Result tiles of an m x n (<= 64 x 64) product: thread t owns rows
+// 4*tx .. 4*tx+3 and columns 4*ty .. 4*ty+3 of tile t mod NT, and works on
+// every G-th row of each staged chunk (G groups split the reduction).
+struct SkinnyMap {
+  int mt, nt, g, tx, ty, grp;
+  __device__ SkinnyMap(int m, int n) {
+    mt = (m + 3) >> 2;
+    nt = mt * ((n + 3) >> 2);
+    g = max(1, kThreads / nt);
+    const int t = (int)threadIdx.x;
+    grp = t / nt;
+    tx = (t % nt) % mt;
+    ty = (t % nt) / mt;
+  }
+  __device__ bool active() const { return grp < g; }
+};
+
+// acc = A B for A m x K, B K x n (m, n <= 64), K streamed through `work`
+// (nwork doubles).  A chunk is staged transposed (rows of B's reduction
+// index contiguous), so that A = V^T and B = x read columns of V and x.
+// Threads of group grp > 0 leave partial sums; reduce_groups adds them.
+__device__ void skinny_ab(const ExecArgs& a, const RV& A, const RV& B, double* work, int nwork, const SkinnyMap& mp,
+                          double (&acc)[4][4]) {
+  const int m = A.rows, n = B.cols, K = A.cols;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  int kc = min(K, nwork / (m + n));
+  if (kc > 1 && !(kc & 1)) --kc;  // odd: the staged columns start in different LDS banks
+  double* lA = work;
+  const int i0 = min(4 * mp.tx, m - 1), j0 = min(4 * mp.ty, n - 1);
+  for (int k0 = 0; k0 < K; k0 += kc) {
+    const int kk = min(kc, K - k0);
+    double* lB = lA + kk * m;
+    const RV At{A.off + (int64_t)k0 * A.cs, kk, m, A.cs, A.rs, A.type};
+    const RV Bc{B.off + (int64_t)k0 * B.rs, kk, n, B.rs, B.cs, B.type};
+    __syncthreads();
+    stage_pair(a, At, lA, Bc, lB);
+    __syncthreads();
+    if (mp.active()) {
+      const double* pa[4];
+      const double* pb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pa[r] = lA + min(i0 + r, m - 1) * kk;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pb[c] = lB + min(j0 + c, n - 1) * kk;
+      for (int l = mp.grp; l < kk; l += mp.g) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = pa[r][l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = pb[c][l];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[r][c] += av[r] * bv[c];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Adds the groups' partial sums into group 0's registers (through `work`,
+// which must hold g * 16 * nt doubles).
+__device__ void reduce_groups(double* work, const SkinnyMap& mp, double (&acc)[4][4]) {
+  if (mp.g == 1) return;
+  const int slot = (int)threadIdx.x % mp.nt;
+  if (mp.active() && mp.grp > 0)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) work[((mp.grp - 1) * mp.nt + slot) * 16 + e] = acc[e >> 2][e & 3];
+  __syncthreads();
+  if (mp.grp == 0)
+    for (int q = 1; q < mp.g; ++q)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e >> 2][e & 3] += work[((q - 1) * mp.nt + slot) * 16 + e];
+  __syncthreads();
+}
+
+// y (m x c) <- beta y + alpha U T: U m x k from the arenas, T k x c in LDS
+// (column-major, leading dimension k); rows streamed through `work`.
+// Thread t owns rows rg, rg + RG, rg + 2 RG, rg + 3 RG of a chunk of 4 RG rows
+// (consecutive threads on consecutive rows) and columns 4 cg .. 4 cg + 3.
+__device__ void rows_update(const ExecArgs& a, const RV& y, const RV& U, const double* lT, double alpha, double beta,
+                            double* work, int nwork) {
+  const int m = y.rows, c = y.cols, k = U.cols;
+  const int cg_n = (c + 3) >> 2;
+  int rg_n = kThreads / cg_n;
+  rg_n = min(rg_n, max(1, (nwork / (k + c)) >> 2));
+  const int R = 4 * rg_n;
+  const int t = (int)threadIdx.x, rg = t % rg_n, cg = t / rg_n;
+  const bool act = cg < cg_n;
+  const int j0 = 4 * cg;
+  const RV none{0, 0, 0, 1, 1, VT_NONE};
+  for (int r0 = 0; r0 < m; r0 += R) {
+    const int rr = min(R, m - r0);
+    double* lU = work;
+    double* lY = work + rr * k;
+    const RV Ur{U.off + (int64_t)r0 * U.rs, rr, k, U.rs, U.cs, U.type};
+    const RV Yr{y.off + (int64_t)r0 * y.rs, rr, c, y.rs, y.cs, y.type};
+    __syncthreads();
+    stage_pair(a, Ur, lU, beta != 0.0 ? Yr : none, lY);
+    __syncthreads();
+    if (act) {
+      double acc[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) acc[q][cc] = 0.0;
+      int ri[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ri[q] = min(rg + q * rg_n, rr - 1);
+      const double* pt[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) pt[cc] = lT + min(j0 + cc, c - 1) * k;
+      for (int l = 0; l < k; ++l) {
+        double uv[4], tv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) uv[q] = lU[ri[q] + l * rr];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) tv[cc] = pt[cc][l];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[q][cc] += uv[q] * tv[cc];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = rg + q * rg_n;
+        if (i >= rr) continue;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int j = j0 + cc;
+          if (j < c) vst(a, Yr, i, j, (beta == 0.0 ? 0.0 : beta * lY[i + j * rr]) + alpha * acc[q][cc]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// OP_GEMM in a solve when the result is at most 64 x 64 and the reduction is
+// long (the partial products V_p^T x_p of a split low-rank block).
+__device__ void op_gemm_skinny(const ExecArgs& a, const Task& t, char* lds) {
+  const RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+  const int m = y.rows, n = y.cols;
+  if (m == 0 || n == 0) return;
+  double* work = (double*)lds;
+  const SkinnyMap mp(m, n);
+  double acc[4][4];
+  skinny_ab(a, A, B, work, kLdsDoubles, mp, acc);
+  reduce_groups(work, mp, acc);
+  if (mp.grp == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = 4 * mp.tx + r, j = 4 * mp.ty + c;
+        if (i < m && j < n) vst(a, y, i, j, (t.beta == 0.0 ? 0.0 : t.beta * vld(a, y, i, j)) + t.alpha * acc[r][c]);
+      }
+  __syncthreads();
+}
+
+// T (k x c, LDS) from registers of group 0
+__device__ __forceinline__ void acc_to_lds(double* lT, int m, int n, const SkinnyMap& mp, const double (&acc)[4][4]) {
+  if (mp.grp == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = 4 * mp.tx + r, j = 4 * mp.ty + c;
+        if (i < m && j < n) lT[i + j * m] = acc[r][c];
+      }
+  __syncthreads();
+}
+
+// OP_LRGEMM in a solve, when its operands do not fit LDS at once:
+// T = b x by the streamed reduction, then y <- beta y + alpha a T by rows.
+__device__ void op_lrgemm_solve(const ExecArgs& a, const Task& t, char* lds) {
+  const RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b), X = resolve(a, t.x);
+  const int m = y.rows, c = y.cols, k = A.cols;
+  if (m == 0 || c == 0) return;
+  double* lT = (double*)lds + (kLdsDoubles - 64 * 64);
+  double* work = (double*)lds;
+  const int nwork = kLdsDoubles - 64 * 64;
+  if (k == 0 || B.cols == 0) {
+    for (int e = threadIdx.x; e < k * c; e += blockDim.x) lT[e] = 0.0;
+  } else {
+    const SkinnyMap mp(k, c);
+    double acc[4][4];
+    skinny_ab(a, B, X, work, nwork, mp, acc);
+    reduce_groups(work, mp, acc);
+    acc_to_lds(lT, k, c, mp, acc);
+  }
+  __syncthreads();
+  rows_update(a, y, A, lT, t.alpha, t.beta, work, nwork);
+}
+
+// OP_GEMMP: y <- y + alpha a (b_0 + ... + b_{P-1}); b_p (k x c) at offset
+// b.off + p * piv, summed in LDS in one batched pass, p in increasing order.
+__device__ void op_gemmp(const ExecArgs& a, const Task& t, char* lds) {
+  const RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+  const int m = y.rows, c = y.cols, k = A.cols, P = t.r0;
+  if (k > 64 || c > 64) {
+    if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
+    return;
+  }
+  if (m == 0 || c == 0) return;
+  double* lT = (double*)lds + (kLdsDoubles - 64 * 64);
+  double* work = (double*)lds;
+  const int nwork = kLdsDoubles - 64 * 64;
+  const int kc = k * c;
+  // each thread sums its elements over p with up to 32 loads in flight
+  for (int e0 = 0; e0 < kc; e0 += kThreads) {
+    const int e = e0 + (int)threadIdx.x;
+    const int i = e < kc ? e % max(k, 1) : 0, j = e < kc ? e / max(k, 1) : 0;
+    double s = 0.0;
+    for (int p0 = 0; p0 < P; p0 += 32) {
+      double v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        v[u] = 0.0;
+        if (e < kc && p0 + u < P) {
+          RV bp = B;
+          bp.off += (int64_t)(p0 + u) * t.piv;
+          v[u] = vld(a, bp, i, j);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 32; ++u) s += v[u];
+    }
+    if (e < kc) lT[e] = s;
+  }
+  __syncthreads();
+  rows_update(a, y, A, lT, t.alpha, t.beta, work, nwork);
+}
+
 __device__ __forceinline__ bool all_f32(const View& v) { return v.type != VT_F64; }
+
+// a solve GEMM with a result of at most 64 x 64 and a long reduction
+__device__ __forceinline__ bool solve_skinny_gemm(const ExecArgs& a, const Task& t) {
+  const RV y = resolve(a, t.y), A = resolve(a, t.a);
+  return y.rows <= 64 && y.cols <= 64 && A.cols > 64;
+}
+
+// op_lrgemm_ct serves the product: its small-operand path applies (every
+// operand in LDS), or the rank or panel width exceeds 64
+__device__ __forceinline__ bool lrgemm_fits_lds(const ExecArgs& a, const Task& t) {
+  const RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+  const int64_t m = y.rows, c = y.cols, k = A.cols, n2 = B.cols;
+  return m * k + k * n2 + n2 * c + m * c + k * c <= kLdsDoubles || k > 64 || c > 64;
+}
 
 // ---------------------------------------------------------------------------
 // GETRF: dense LU with partial pivoting (LAPACK getrf convention: first
@@ -2109,6 +2391,10 @@ __device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
     RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b), X = resolve(a, t.x);
     bytes = vbytes(A) + vbytes(B) + vbytes(X) + (t.beta != 0.0 ? 2 : 1) * vbytes(y);
     flops = 2 * (int64_t)A.cols * B.cols * X.cols + 2 * (int64_t)y.rows * A.cols * y.cols;
+  } else if (t.op == OP_GEMMP) {
+    RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
+    bytes = vbytes(A) + (int64_t)t.r0 * vbytes(B) + 2 * vbytes(y);
+    flops = 2 * (int64_t)y.rows * y.cols * A.cols + (int64_t)t.r0 * B.rows * B.cols;
   } else if (t.op == OP_ZERO) {
     bytes = vbytes(resolve(a, t.y));
   } else if (t.op == OP_COPY) {
@@ -2178,7 +2464,8 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
 
 template <bool kSolve>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
-  if (kSolve && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) {
+  if ((kSolve && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) ||
+      (!kSolve && t.op == OP_GEMMP)) {
     if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
     return;
   }
@@ -2196,16 +2483,23 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
       op_trsm(a, t, lds, 2);
       break;
     case OP_GEMM:
-      if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b))
+      if (kSolve && solve_skinny_gemm(a, t))
+        op_gemm_skinny(a, t, lds);
+      else if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b))
         op_gemm_ct<float>(a, t, lds);
       else
         op_gemm_ct<double>(a, t, lds);
       break;
     case OP_LRGEMM:
-      if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b) && all_f32(t.x))
+      if (kSolve && !lrgemm_fits_lds(a, t))
+        op_lrgemm_solve(a, t, lds);
+      else if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b) && all_f32(t.x))
         op_lrgemm_ct<float>(a, t, lds);
       else
         op_lrgemm_ct<double>(a, t, lds);
+      break;
+    case OP_GEMMP:
+      if (kSolve) op_gemmp(a, t, lds);
       break;
     case OP_TRUNC:
     case OP_TRUNC2:

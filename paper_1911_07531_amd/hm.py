@@ -20,7 +20,8 @@ FP64, MIXED = 0, 1
 LAPLACE3D, LOG2D = 0, 1
 DATAFLOW, LEVEL = 0, 1
 
-OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy", "trunc2"]
+OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy", "trunc2",
+            "gemmp"]
 
 
 class HmError(RuntimeError):
@@ -45,7 +46,7 @@ class LuStats(C.Structure):
 
 # numpy view of one traced task record (struct Task in csrc/hm_internal.h)
 VIEW_DTYPE = np.dtype([("off", "<i8"), ("rows", "<i4"), ("cols", "<i4"), ("rs", "<i4"), ("cs", "<i4"),
-                       ("type", "<i4"), ("dyn", "<i4"), ("rank_id", "<i4"), ("pad", "<i4")])
+                       ("type", "<i4"), ("dyn", "<i4"), ("rank_id", "<i4"), ("rank_id2", "<i4")])
 TASK_DTYPE = np.dtype([("op", "<i4"), ("lr", "<i4"), ("r0", "<i4"), ("c0", "<i4"), ("row0", "<i4"),
                        ("c1", "<i4"), ("piv", "<i8"), ("alpha", "<f8"), ("beta", "<f8"),
                        ("y", VIEW_DTYPE), ("a", VIEW_DTYPE), ("b", VIEW_DTYPE), ("x", VIEW_DTYPE)])

@@ -10,6 +10,10 @@ The geometry stands in for the paper's model problem, the Laplace single layer
 potential on the unit sphere (Sec. 5.1, "Model Problems"): a quasi-uniform
 point set on the sphere replaces the piecewise-constant Galerkin mesh; the
 paper notes that the entries do not matter for the block structure.
+
+The second workload is the paper's one-dimensional model problem (Sec. 5.1,
+the log-kernel integral equation on [0, 1]): n collocation points at the
+midpoints of a uniform mesh of the unit interval.
 """
 from __future__ import annotations
 
@@ -70,3 +74,24 @@ def rhs(n: int, nrhs: int, seed: int = 1) -> np.ndarray:
 def sphere_problem(n: int, seed: int = 0):
     """(points, diag) for the sphere single-layer workload of size n."""
     return sphere_points(n, seed), sphere_self_term(n)
+
+
+def line_points(n: int) -> np.ndarray:
+    """Midpoints x_i = (i + 1/2) / n of the n cells of a uniform mesh of [0, 1], as an (n, 1) array."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    return ((np.arange(n, dtype=np.float64) + 0.5) / n).reshape(n, 1)
+
+
+def line_self_term(n: int) -> float:
+    """Diagonal value for the kernel -log|x - y| / (2 pi) on the line: its mean over
+    the cell [x_i - h/2, x_i + h/2] around the collocation point, h = 1/n,
+    which is (1 - log(h/2)) / (2 pi)."""
+    h = 1.0 / n
+    return (1.0 - math.log(0.5 * h)) / (2.0 * math.pi)
+
+
+def line_problem(n: int, seed: int = 0):
+    """(points, diag) for the one-dimensional log-kernel workload of size n (no
+    random draw: the mesh is uniform; ``seed`` is accepted for a common signature)."""
+    return line_points(n), line_self_term(n)

@@ -12,7 +12,7 @@ import numpy as np
 import scipy.linalg as sla
 
 VT_F64, VT_F32, VT_IDENT, VT_NONE = 0, 1, 2, 3
-DYN_ROWS, DYN_COLS = 1, 2
+DYN_ROWS, DYN_COLS, DYN_COLS2 = 1, 2, 4
 
 
 class Replay:
@@ -32,6 +32,8 @@ class Replay:
     def dims(self, v):
         rows = self.ranks[v["rank_id"]] if v["dyn"] & DYN_ROWS else v["rows"]
         cols = self.ranks[v["rank_id"]] if v["dyn"] & DYN_COLS else v["cols"]
+        if v["dyn"] & DYN_COLS2:
+            cols = self.ranks[v["rank_id2"]]
         return int(rows), int(cols)
 
     def view(self, v):
@@ -129,6 +131,14 @@ class Replay:
             self.view(t["y"])[:] = self.view(t["a"])
         elif op == 10:
             self.trunc(t, two=True)
+        elif op == 11:  # y += alpha a (b_0 + ... + b_{P-1}), b_p at offset b.off + p * piv
+            y = self.view(t["y"])
+            bsum = 0.0
+            for p in range(int(t["r0"])):
+                bv = t["b"].copy()
+                bv["off"] = int(t["b"]["off"]) + p * int(t["piv"])
+                bsum = bsum + np.asarray(self.view(bv), np.float64)
+            y[:] = np.asarray(y, np.float64) + t["alpha"] * (np.asarray(self.view(t["a"]), np.float64) @ bsum)
         else:
             raise ValueError(op)
 

@@ -26,19 +26,27 @@ def to_host(t):
 
 
 class Problem:
-    """Sphere workload on both sides: the oracle's tree/assembly and the GPU's."""
+    """A workload on both sides: the oracle's tree/assembly and the GPU's.
+
+    geometry "sphere": the single layer potential on the sphere; "line": the
+    one-dimensional log-kernel model problem on [0, 1]."""
 
     def __init__(self, n, leaf, eps, max_rank=0, eta=2.0, seed=0, prec=hm.FP64, exec_mode=hm.DATAFLOW,
-                 oracle=True):
+                 oracle=True, geometry="sphere"):
         self.n, self.leaf, self.eps, self.max_rank = n, leaf, eps, max_rank
-        self.pts, self.diag = inputs.sphere_problem(n, seed)
+        if geometry == "sphere":
+            self.pts, self.diag = inputs.sphere_problem(n, seed)
+            self.kernel, self.kname = hm.LAPLACE3D, "laplace3d"
+        else:
+            self.pts, self.diag = inputs.line_problem(n)
+            self.kernel, self.kname = hm.LOG2D, "log2d"
         self.opts = hm.make_opts(leaf=leaf, eta=eta, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode)
         self.tree = hm.Tree(self.pts, self.opts)
-        self.A = hm.Matrix(self.tree, hm.LAPLACE3D, self.diag, self.opts)
+        self.A = hm.Matrix(self.tree, self.kernel, self.diag, self.opts)
         if oracle:
             perm, cl = H.build_cluster_tree(self.pts, leaf)
             root = H.build_block_tree(cl[0], eta)
-            self.oa = H.assemble(self.pts, perm, cl, root, self.diag, eps, max_rank)
+            self.oa = H.assemble(self.pts, perm, cl, root, self.diag, eps, max_rank, kernel=self.kname)
         else:
             self.oa = None
 
@@ -59,4 +67,7 @@ class Problem:
     def dense_exact(self):
         """Exact kernel matrix in permuted order (small n only)."""
         perm, cl = H.build_cluster_tree(self.pts, self.leaf)
-        return H.kernel_block(self.pts, perm, cl[0], cl[0], self.diag)
+        return H.kernel_block(self.pts, perm, cl[0], cl[0], self.diag, kernel=self.kname)
+
+    def exact_block(self, perm, tau, sigma):
+        return H.kernel_block(self.pts, perm, tau, sigma, self.diag, kernel=self.kname)

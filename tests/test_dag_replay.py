@@ -65,12 +65,18 @@ def test_replay_matches_oracle_hlu(n, leaf, eps, max_rank, orders):
                 assert np.array_equal(b.piv, ob.piv)
 
 
-def test_replay_solve_matches_oracle():
+@pytest.mark.parametrize("split", [None, "12"])
+def test_replay_solve_matches_oracle(split, monkeypatch):
+    """The substitution DAG, with the large low-rank products split into
+    partial products and their sums (split = 12 rows) or not."""
+    if split is not None:
+        monkeypatch.setenv("HM_SOLVE_SPLIT", split)
     n, leaf, eps = 512, 32, 1e-6
     t, opts, a = _setup(n, leaf, 2.0, eps, 0)
     ref = H.hlu(a)
     dag = t.dag(opts, 0)
     sdag = t.dag(opts, 1)
+    assert (sdag["tasks"]["op"] == 11).any() == (split is not None)
     blocks = {b.index: b for b in H.leaf_blocks(a.root)}
     rp = Replay(dag, eps, 0)
     rp.load_matrix(blocks, dag["block_off"], dag["lr"])

@@ -73,12 +73,12 @@ def test_assembly_ranks_and_error_c1(c1):
     rng = np.random.default_rng(0)
     lr = [b for b in H.leaf_blocks(ga.root) if b.kind == "R"]
     for b in rng.choice(lr, 40, replace=False):
-        exact = H.kernel_block(p.pts, ga.perm, b.tau, b.sigma, p.diag)
+        exact = p.exact_block(ga.perm, b.tau, b.sigma)
         s1 = np.linalg.norm(exact, 2)
         assert np.linalg.norm(exact - b.U @ b.V.T, 2) <= 2 * p.eps * s1
     for b in H.leaf_blocks(ga.root):
         if b.kind == "D":
-            exact = H.kernel_block(p.pts, ga.perm, b.tau, b.sigma, p.diag)
+            exact = p.exact_block(ga.perm, b.tau, b.sigma)
             assert np.array_equal(b.D, exact) or np.max(np.abs(b.D - exact)) <= 1e-15 * np.abs(exact).max()
 
 
@@ -220,3 +220,27 @@ def test_reused_temporaries_on_device(monkeypatch):
     assert np.array_equal(sols[0], sols[1]) and np.array_equal(sols[0], sols[2])
     gf = p.gpu_as_oracle(1, f.h)
     assert H.lu_error_2norm(p.dense_exact(), gf, exact=True) <= 10 * p.eps
+
+
+def test_split_solve_products(monkeypatch):
+    """Low-rank products of the substitution DAG split into partial products
+    over row chunks (128 rows here: every product with a side of 256 rows or
+    more) give the unsplit solution up to rounding, identically on both
+    executors."""
+    b = inputs.rhs(4096, 5, seed=3)
+    out = {}
+    for split in ("0", "128"):
+        monkeypatch.setenv("HM_SOLVE_SPLIT", split)
+        p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False)  # a new tree traces a new plan
+        sdag = p.tree.dag(p.opts, 1)
+        assert (sdag["tasks"]["op"] == 11).any() == (split != "0")
+        f = hm.LU(p.A, p.opts)
+        for mode in ("level", "dataflow"):
+            monkeypatch.setenv("HM_SOLVE_EXEC", mode)
+            x = device_rhs(b)
+            f.solve(x)
+            out[(split, mode)] = to_host(x)
+    assert np.array_equal(out[("128", "level")], out[("128", "dataflow")])
+    assert np.array_equal(out[("0", "level")], out[("0", "dataflow")])
+    ref = out[("0", "level")]
+    assert np.max(np.abs(out[("128", "level")] - ref)) <= 1e-9 * np.abs(ref).max()

@@ -63,6 +63,31 @@ def test_invalid_arguments_rejected(L):
     assert b"n >= 1" in L.hm_last_error() or b"null" in L.hm_last_error()
     with pytest.raises(hm.HmError):
         hm.Tree(pts, hm.make_opts(leaf=-3))
+    for dim in (0, 4):
+        assert L.build_htree(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3, dim,
+                             ctypes.byref(hm.make_opts()), ctypes.byref(h)) == hm.HM_EINVAL
+
+
+@pytest.mark.parametrize("n,leaf", [(4096, 32), (3000, 64), (1, 8)])
+def test_line_tree_parity_with_oracle(n, leaf):
+    """Points on [0, 1] given with dim = 1: the host tree equals the oracle's,
+    boxes padded with zero trailing coordinates."""
+    pts = inputs.line_points(n)
+    t = hm.Tree(pts, hm.make_opts(leaf=leaf, eta=2.0))
+    perm, cl, box, bl = t.tables()
+    operm, ocl = H.build_cluster_tree(pts, leaf)
+    oroot = H.build_block_tree(ocl[0], 2.0)
+    assert np.array_equal(perm, operm)
+    assert len(cl) == len(ocl)
+    for i, c in enumerate(ocl):
+        assert box[i, 0] == c.lo[0] and box[i, 3] == c.hi[0]
+        assert not box[i, [1, 2, 4, 5]].any()
+        assert list(cl[i][:2]) == [c.begin, c.end]
+    kind = {"S": 0, "D": 1, "R": 2}
+    oblocks = H.block_list(oroot)
+    assert len(bl) == len(oblocks)
+    for b in oblocks:
+        assert list(bl[b.index][:3]) == [b.tau.index, b.sigma.index, kind[b.kind]]
 
 
 @pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])

@@ -12,7 +12,11 @@
   and the block-diagonal special case;
 * the 10*eps bound of ||P A - L U||_2 / ||A||_2 at n = 2048 (exact 2-norm) and
   agreement of the power-iteration estimate with it;
-* solve and matvec against dense products; iterative refinement.
+* solve and matvec against dense products; iterative refinement;
+* the log kernel of the one-dimensional model problem (Sec. 5.1): row sums
+  of the matrix times h against the closed-form integral of the kernel over
+  [0, 1] (midpoint rule, O(h) error), and the same eps = 0 and 10*eps pins
+  on the line.
 """
 import numpy as np
 import pytest
@@ -22,12 +26,15 @@ from oracle import hmatrix as H
 from paper_1911_07531_amd import inputs
 
 
-def _problem(n, leaf, eta, eps, max_rank=0, seed=0):
-    pts, diag = inputs.sphere_problem(n, seed)
+def _problem(n, leaf, eta, eps, max_rank=0, seed=0, geometry="sphere"):
+    if geometry == "sphere":
+        (pts, diag), kernel = inputs.sphere_problem(n, seed), "laplace3d"
+    else:
+        (pts, diag), kernel = inputs.line_problem(n), "log2d"
     perm, cl = H.build_cluster_tree(pts, leaf)
     root = H.build_block_tree(cl[0], eta)
-    a = H.assemble(pts, perm, cl, root, diag, eps, max_rank)
-    dense = H.kernel_block(pts, perm, cl[0], cl[0], diag)
+    a = H.assemble(pts, perm, cl, root, diag, eps, max_rank, kernel=kernel)
+    dense = H.kernel_block(pts, perm, cl[0], cl[0], diag, kernel=kernel)
     return a, dense
 
 
@@ -192,9 +199,11 @@ def _dense_block_lu(a, leaf_ranges):
     return a, pivs
 
 
-@pytest.mark.parametrize("n,leaf,eta", [(512, 32, 2.0), (700, 24, 1.0), (256, 32, 0.0)])
-def test_hlu_eps0_equals_dense_block_lu(n, leaf, eta):
-    a, dense = _problem(n, leaf, eta, 0.0)
+@pytest.mark.parametrize("n,leaf,eta,geometry", [(512, 32, 2.0, "sphere"), (700, 24, 1.0, "sphere"),
+                                                  (256, 32, 0.0, "sphere"), (512, 32, 2.0, "line"),
+                                                  (600, 20, 2.0, "line")])
+def test_hlu_eps0_equals_dense_block_lu(n, leaf, eta, geometry):
+    a, dense = _problem(n, leaf, eta, 0.0, geometry=geometry)
     if eta == 0.0:
         assert all(b.kind != "R" for b in H.leaf_blocks(a.root))
     else:
@@ -309,3 +318,32 @@ def test_hlu_lazy_error_bound_c1(c1):
     seq = H.rank_table(H.hlu(a))
     lz = H.rank_table(f)
     assert min(lz[i] - seq[i] for i in seq) >= -2
+
+
+def test_log_kernel_row_sums_are_the_integral():
+    """h * sum_j a_ij approximates the integral of -log|x_i - y| / (2 pi) over
+    [0, 1], which is (1 - x log x - (1 - x) log(1 - x)) / (2 pi): the own cell
+    is exact (the diagonal is the cell mean) and the midpoint rule on the
+    others errs by about h * zeta(2) / (12 * 2 pi) ~ 0.022 h.  A wrong sign,
+    scale, logarithm base or self term misses this by more than 0.1 h."""
+    import math
+    for n in (256, 2048):
+        pts, diag = inputs.line_problem(n)
+        perm, cl = H.build_cluster_tree(pts, 32)
+        a = H.kernel_block(pts, perm, cl[0], cl[0], diag, kernel="log2d")
+        x = pts[perm, 0]
+        exact = (1.0 - x * np.log(x) - (1.0 - x) * np.log1p(-x)) / (2.0 * math.pi)
+        err = np.abs(a.sum(axis=1) / n - exact)
+        assert err.max() <= 0.03 / n, err.max() * n
+        assert err.max() >= 0.01 / n  # the midpoint rule's own error is visible
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_hlu_error_bound_line(lazy):
+    a, dense = _problem(2048, 32, 2.0, 1e-6, geometry="line")
+    f = H.hlu(a, lazy=lazy)
+    err = H.lu_error_2norm(dense, f, exact=True)
+    assert err <= 10 * 1e-6
+    # the coarse 1D structure: ranks stay small (log-kernel blocks one cluster apart)
+    ranks = [b.rank for b in H.leaf_blocks(f.root) if b.kind == "R"]
+    assert 0 < max(ranks) <= 24

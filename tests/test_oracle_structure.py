@@ -115,3 +115,47 @@ def test_admissibility_brute_force_boxes():
         eta = 2.0
         expect = d > 0 and min(np.linalg.norm(hi1 - lo1), np.linalg.norm(hi2 - lo2)) <= eta * d
         assert H.admissible(c1, c2, eta) == expect
+
+
+def test_line_mesh_midpoints():
+    x = inputs.line_points(8)[:, 0]
+    assert x.shape == (8,)
+    assert np.array_equal(x, np.array([1, 3, 5, 7, 9, 11, 13, 15]) / 16.0)
+    # mean of -log|t| / (2 pi) over a cell of width h around its midpoint, by quadrature
+    from scipy.integrate import quad
+    for n in (1, 10, 1000):
+        h = 1.0 / n
+        v = 2 * quad(lambda t: -math.log(t), 0.0, 0.5 * h)[0] / h / (2 * math.pi)
+        assert abs(inputs.line_self_term(n) - v) <= 1e-12 * abs(v)
+
+
+@pytest.mark.parametrize("levels,leaf", [(3, 32), (5, 32), (6, 16), (4, 64)])
+def test_line_block_tree_closed_form(levels, leaf):
+    """Uniform points on [0, 1] with eta = 2 (Sec. 5.1, the 1D model problem):
+    bisection halves every cluster, so level l holds 2^l clusters of equal
+    width w_l.  Neighbours (gap h, diameter w_l - h > 2h once a cluster has
+    more than 3 points) are inadmissible; clusters one cluster apart (gap
+    w_l + h) are admissible.  Hence the inadmissible blocks of each level form
+    the tridiagonal 3 * 2^l - 2, every adjacent pair of parents gives 3
+    admissible son blocks on each side (3 * 2^l - 6 low-rank leaves on level
+    l >= 1), and the leaves of level L = log2(n / leaf) are dense."""
+    n = leaf << levels
+    perm, cl = H.build_cluster_tree(inputs.line_points(n), leaf)
+    assert np.array_equal(perm, np.arange(n))
+    root = H.build_block_tree(cl[0], 2.0)
+    by_level = {}
+    for b in H.block_list(root):
+        lt, ls = b.tau.level, b.sigma.level
+        assert lt == ls
+        w = b.tau.size
+        i, j = b.tau.begin // w, b.sigma.begin // w
+        assert b.sigma.size == w == n >> lt
+        if abs(i - j) <= 1:
+            assert b.kind == ("D" if lt == levels else "S")
+        else:
+            assert b.kind == "R" and abs(i // 2 - j // 2) == 1
+        by_level.setdefault(lt, {"S": 0, "D": 0, "R": 0})[b.kind] += 1
+    for l in range(levels + 1):
+        c = by_level[l]
+        assert c["S" if l < levels else "D"] == 3 * 2 ** l - 2
+        assert c["R"] == max(0, 3 * 2 ** l - 6)
