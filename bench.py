@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the plain FP64 H-LU of the same workload (reported beside the mixed one)")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip timing h_lu_solve (H-LU and substitution as one DAG) against h_lu + h_solve")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")
@@ -188,6 +190,34 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
         print(f"# solve request {k}: {lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+    fused = None
+    if not args.no_fused:
+        # factorize-and-solve of the 32 RHS (no refinement): one fused DAG vs h_lu then h_solve
+        def fresh():
+            return b_dev.clone().t().contiguous().t()
+        g = hm.LU(A, opts, rhs=fresh())  # warm-up (traces the fused DAG)
+        del g
+        tf, ts = [], []
+        for _ in range(2):
+            x = fresh()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = hm.LU(A, opts, rhs=x)
+            torch.cuda.synchronize()
+            tf.append((time.perf_counter() - t1) * 1e3)
+            del g
+            x = fresh()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = hm.LU(A, opts)
+            g.solve(x)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t1) * 1e3)
+            del g
+        fused = {"fused_ms": float(np.median(tf)), "separate_ms": float(np.median(ts)),
+                 "speedup": float(np.median(ts) / np.median(tf)), "nrhs": args.nrhs}
+        print(f"# h_lu_solve (one DAG) {fused['fused_ms']:.1f} ms vs h_lu + h_solve {fused['separate_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     fp64 = None
     if prec == hm.MIXED and not args.no_fp64_compare:
         # the same factorization with every block in FP64 (plain form), timed the same way
@@ -264,6 +294,7 @@ def main():
                      "fp64_flop_frac": st["flops_alg"] / (med_exec * 1e-3) / (FP64_PEAK_TFS * 1e12)},
         "cpu_baseline": cpu,
         "plain_fp64": fp64,
+        "fused_lu_solve": fused,
     }
     print(json.dumps(out), flush=True)
 

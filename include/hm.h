@@ -138,6 +138,19 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
  * Synchronises `stream`. */
 hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info);
 
+/* H-LU and substitution as one task DAG (the fusion of composed operations
+ * that the semi-automatic construction allows, Sec. 6; cf. the merged DAGs of
+ * Sec. 4.3): the H-LU of A (Algorithm 2) and the forward/backward substitution of the first
+ * min(nrhs, 64) columns of B are traced into one DAG and run by one persistent
+ * launch, so that a block row's substitution starts as soon as its factors
+ * are final; further columns are solved after it as by h_solve without
+ * refinement.  B: device, n x nrhs, column-major, ldb >= n, overwritten by
+ * the solution.  The factors equal those of h_lu (task for task the same
+ * H-LU); *out and *info as for h_lu (on failure B is unspecified).  opts->exec
+ * is ignored (always the persistent executor).  Synchronises `stream`. */
+hm_status h_lu_solve(hm_matrix A, const hm_opts* opts, double* B, int64_t ldb, int64_t nrhs, void* stream, hm_lu* out,
+                     int64_t* info);
+
 /* Solve A X = B in place.  B: device, n x nrhs, column-major, leading
  * dimension ldb >= n.  With A_or_null != NULL the solution is refined with
  * r = b - A_H x (FP64 h_matvec) until every column has ||r|| / ||b|| <= rtol
@@ -182,7 +195,7 @@ hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_kh
 hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out);
 
 /* The traced DAG without a device (host only), for inspection and tests.
- * which: 0 = H-LU, 1 = solve.  sizes: ntasks, nedges, nlevels, task_bytes
+ * which: 0 = H-LU, 1 = solve, 2 = H-LU + solve (the DAG of h_lu_solve).  sizes: ntasks, nedges, nlevels, task_bytes
  * (sizeof one task record), n_f64, n_f32, n_piv (arena sizes in elements),
  * nlr (low-rank leaves), nranks.  hm_dag_export copies (any pointer may be
  * NULL): tasks (ntasks records), succ_ptr (ntasks + 1), succ_idx (nedges),

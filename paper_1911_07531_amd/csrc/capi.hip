@@ -26,6 +26,7 @@ __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_
 __global__ void exec_dataflow_kernel(ExecArgs a);
 __global__ void solve_dataflow_kernel(ExecArgs a);
 __global__ void solve_level_kernel(ExecArgs a, const int32_t* order, int begin, int end);
+__global__ void fused_dataflow_kernel(ExecArgs a);
 __global__ void assemble_dense_kernel(ExecArgs a, AsmArgs s, const DenseAsm* blocks);
 __global__ void assemble_aca_kernel(ExecArgs a, AsmArgs s, const LrAsm* blocks, double* fac, int64_t fac_stride,
                                     double aca_eps);
@@ -137,7 +138,8 @@ struct PlanEntry {
   Plan plan;
   bool traced = false;
   bool uploaded = false;
-  DevDag lu, solve;
+  bool fused_traced = false, fused_uploaded = false;
+  DevDag lu, solve, fused;
   DevBuf lr;
   int device = -1;
 };
@@ -178,6 +180,7 @@ struct hm_lu_s {
   int prec, exec;
   double eps;
   int max_rank;
+  int64_t dag_ntasks = 0;  // tasks of the DAG that produced the factors (H-LU, or H-LU + substitution)
   DevBuf f64, f32, piv, ranks, perm;
   ExecState lu_st, solve_st;
   DevBuf work;  // solve/refinement vectors
@@ -205,6 +208,8 @@ static hm_status device_setup() {
   (void)hipFuncSetAttribute((const void*)solve_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)solve_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsExecBytes);
+  (void)hipFuncSetAttribute((const void*)fused_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   int per_cu = 0;
@@ -266,6 +271,16 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
   return HM_OK;
 }
 
+// The fused H-LU + substitution DAG of a plan, traced on first use (host only).
+static hm_status trace_fused(hm_tree t, PlanEntry* pe, int lazy) {
+  std::lock_guard<std::mutex> lk(t->mu);
+  if (!pe->fused_traced) {
+    if (!trace_lu_solve(pe->plan, temp_budget(), lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
+    pe->fused_traced = true;
+  }
+  return HM_OK;
+}
+
 static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
   dd.ntasks = (int64_t)d.tasks.size();
   dd.nedges = d.nedges;
@@ -310,9 +325,14 @@ static void exec_state_free(ExecState& es) {
   dev_free(es.counters);
 }
 
-// Run a DAG on `s`.  Returns the executor's device time in *ms.
+enum DagKind { DAG_LU = 0, DAG_SOLVE = 1, DAG_FUSED = 2 };
+
+// Run a DAG on `s`; *ms receives the executor's device time.  The fused DAG
+// always runs on the persistent executor.
 static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, hipStream_t s, float* ms,
-                         bool solve = false) {
+                         int kind = DAG_LU) {
+  const bool solve = kind == DAG_SOLVE;
+  if (kind == DAG_FUSED) mode = HM_EXEC_DATAFLOW;
   if (dd.ntasks == 0) {
     if (ms) *ms = 0.f;
     return HM_OK;
@@ -364,6 +384,8 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     HIPCHK(hipEventRecord(e0, s));
     if (solve)
       hipLaunchKernelGGL(solve_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
+    else if (kind == DAG_FUSED)
+      hipLaunchKernelGGL(fused_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     else
       hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
@@ -490,12 +512,13 @@ void hm_tree_free(hm_tree t) {
 }
 
 hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes) {
-  if (!t || !opts || !sizes || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
+  if (!t || !opts || !sizes || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
   if (opts->max_rank < 0 || opts->max_rank > kMaxCap) return fail(HM_EINVAL, "max_rank must be in [0, 64]");
   PlanEntry* pe;
   hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
   if (st) return st;
-  const Dag& d = which == 0 ? pe->plan.lu : pe->plan.solve;
+  if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
+  const Dag& d = which == 0 ? pe->plan.lu : which == 1 ? pe->plan.solve : pe->plan.fused;
   sizes[0] = (int64_t)d.tasks.size();
   sizes[1] = d.nedges;
   sizes[2] = (int64_t)d.level_ptr.size() - 1;
@@ -510,12 +533,13 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
 
 hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
                         int32_t* level, int64_t* block_off, int64_t* lr) {
-  if (!t || !opts || (which != 0 && which != 1)) return fail(HM_EINVAL, "bad argument");
+  if (!t || !opts || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
   PlanEntry* pe;
   hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
   if (st) return st;
   const Plan& p = pe->plan;
-  const Dag& d = which == 0 ? p.lu : p.solve;
+  if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
+  const Dag& d = which == 0 ? p.lu : which == 1 ? p.solve : p.fused;
   if (tasks) std::memcpy(tasks, d.tasks.data(), d.tasks.size() * sizeof(Task));
   if (succ_ptr) std::memcpy(succ_ptr, d.succ_ptr.data(), d.succ_ptr.size() * 4);
   if (succ_idx) std::memcpy(succ_idx, d.succ_idx.data(), d.succ_idx.size() * 4);
@@ -607,7 +631,10 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
   size_t fac_bytes = 0;
   while (i0 < lrs.size()) {
     const LrDesc& d0 = p.lr[lrs[i0].lr];
-    int64_t stride = ((int64_t)(d0.m + d0.n) * kMaxK * 8 + d0.m + 255) / 256 * 32;  // doubles
+    // one slot per block: U (m x kMaxK), V (n x kMaxK) and m row flags; the
+    // batch is sorted by m + n, so (m0 + n0) bounds every block's m + n, and
+    // m + n (not m0) bounds its flags
+    int64_t stride = ((int64_t)(d0.m + d0.n) * (kMaxK * 8 + 1) + 255) / 256 * 32;  // doubles
     int64_t cnt = std::min<int64_t>({(int64_t)(lrs.size() - i0), maxb, std::max<int64_t>(1, fac_budget / (stride * 8))});
     size_t need = (size_t)(cnt * stride * 8);
     if (need > fac_bytes) {
@@ -687,6 +714,7 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
       !dev_alloc(A->mv_x, (size_t)tr.n * 16 * 8, s) || !dev_alloc(A->mv_y, (size_t)tr.n * 16 * 8, s))
     return fail(HM_ENOMEM, "device allocation failed (matvec)");
   HIPCHK(hipStreamSynchronize(s));
+  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: an ACA scratch slot is too small");
   *out = A.release();
   if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "compression wanted more than 64 columns");
   return HM_OK;
@@ -740,18 +768,39 @@ hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, doub
 }
 
 // ----------------------------------------------------------------------------
-hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info) {
+// ... and uploaded on first use.
+static hm_status get_fused(hm_tree t, PlanEntry* pe, int lazy, hipStream_t s) {
+  hm_status st0 = trace_fused(t, pe, lazy);
+  if (st0) return st0;
+  if (!pe->fused_uploaded) {
+    hm_status st = upload_dag(pe->plan.fused, pe->fused, s);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    pe->fused_uploaded = true;
+  }
+  return HM_OK;
+}
+
+// h_lu, and with B != NULL h_lu_solve: the first min(nrhs, 64) columns of B
+// are substituted inside the factorization's DAG.
+static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info, double* B,
+                         int64_t ldb, int64_t nrhs) {
   if (!A || !out) return fail(HM_EINVAL, "null pointer");
   if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
   if (opts->max_rank != A->max_rank) return fail(HM_EINVAL, "max_rank differs from the assembled matrix");
+  const bool fused = B != nullptr && nrhs > 0;
+  if (fused && ldb < A->tree->t.n) return fail(HM_EINVAL, "ldb < n");
   hm_status st = device_setup();
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   hm_tree t = A->tree;
   PlanEntry* pe;
   if ((st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe))) return st;
+  if (fused && (st = get_fused(t, pe, opts->lazy, s))) return st;
   if ((st = ensure_uploaded(pe, s))) return st;
   const Plan& p = pe->plan;
+  const DevDag& dag = fused ? pe->fused : pe->lu;
+  const Dag& hdag = fused ? p.fused : p.lu;
   const Plan& pa = A->pe->plan;
   auto F = std::make_unique<hm_lu_s>();
   F->tree = t;
@@ -765,13 +814,14 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
       !dev_alloc(F->piv, std::max<int64_t>(1, p.n_piv) * 4, s) || !dev_alloc(F->ranks, p.nranks * 4, s))
     return fail(HM_ENOMEM, "device allocation failed (factors)");
   if ((st = upload(F->perm, t->t.perm, s))) return st;
-  if ((st = exec_state_alloc(F->lu_st, pe->lu.ntasks, s))) return st;
+  F->dag_ntasks = dag.ntasks;
+  if ((st = exec_state_alloc(F->lu_st, dag.ntasks, s))) return st;
   // HM_DEBUG_TRACE=1 records timing and shape information of every H-LU task
   if (const char* e = getenv("HM_DEBUG_TRACE"))
     if (e[0] == '1') {
-      if (!dev_alloc(F->lu_st.trace, (size_t)pe->lu.ntasks * kTraceWords * 8, s))
+      if (!dev_alloc(F->lu_st.trace, (size_t)dag.ntasks * kTraceWords * 8, s))
         return fail(HM_ENOMEM, "device allocation failed (trace)");
-      HIPCHK(hipMemsetAsync(F->lu_st.trace.p, 0, (size_t)pe->lu.ntasks * kTraceWords * 8, s));
+      HIPCHK(hipMemsetAsync(F->lu_st.trace.p, 0, (size_t)dag.ntasks * kTraceWords * 8, s));
     }
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
   // copy A into the factor layout
@@ -809,9 +859,24 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
                          (const LrDesc*)pe->lr.p, opts->eps, opts->max_rank);
   a.scratch = (double*)scratch.p;
   a.scratch_stride = kScratchPerWg;
+  const int64_t n = t->t.n;
+  const int nc = fused ? (int)std::min<int64_t>(nrhs, p.nrhs_cap) : 0;
+  double* panel = (double*)F->f64.p + p.panel_off;
+  const unsigned gr = (unsigned)((n * nc + 255) / 256);
+  if (fused) {
+    hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)F->ranks.p + p.nrhs_slot, nc, 0, 0, 0, 1);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(gr), dim3(256), 0, s, (const double*)B, ldb,
+                       (const int64_t*)F->perm.p, n, nc, panel, n);
+    HIPCHK(hipGetLastError());
+  }
   float ms = 0.f;
-  st = run_dag(pe->lu, a, F->lu_st, opts->exec, s, &ms);
+  st = run_dag(dag, a, F->lu_st, opts->exec, s, &ms, fused ? DAG_FUSED : DAG_LU);
   if (st) return st;
+  if (fused) {
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3(gr), dim3(256), 0, s, (const double*)panel, n,
+                       (const int64_t*)F->perm.p, n, nc, B, ldb, 1.0, 0.0);
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(hipStreamSynchronize(s));
   dev_free(scratch);
   int32_t stv[4];
@@ -823,10 +888,10 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   double ntr = (double)std::max<unsigned long long>(1, ctr[kCtrCount + OP_TRUNC] + ctr[kCtrCount + OP_TRUNC2]);
   F->stats.trunc_mean_k = ctr[kCtrK] / ntr;
   F->stats.trunc_mean_mn = ctr[kCtrMN] / ntr;
-  F->stats.ntasks = pe->lu.ntasks;
-  F->stats.nedges = pe->lu.nedges;
-  F->stats.nlevels = pe->lu.nlevels;
-  for (const Task& tk : p.lu.tasks)
+  F->stats.ntasks = dag.ntasks;
+  F->stats.nedges = dag.nedges;
+  F->stats.nlevels = dag.nlevels;
+  for (const Task& tk : hdag.tasks)
     if (tk.op >= 0 && tk.op < OP_COUNT) F->stats.tasks_by_op[tk.op]++;
   F->stats.bytes_alg = (int64_t)ctr[0];
   F->stats.flops_alg = (int64_t)ctr[1];
@@ -844,7 +909,20 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
   }
   *out = F.release();
   if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "a truncation wanted more than 64 columns");
+  if (fused && nrhs > nc)
+    return h_solve(*out, nullptr, B + (int64_t)nc * ldb, ldb, nrhs - nc, 0.0, 0, stream, nullptr, nullptr);
   return HM_OK;
+}
+
+hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64_t* info) {
+  return lu_impl(A, opts, stream, out, info, nullptr, 0, 0);
+}
+
+hm_status h_lu_solve(hm_matrix A, const hm_opts* opts, double* B, int64_t ldb, int64_t nrhs, void* stream, hm_lu* out,
+                     int64_t* info) {
+  if (!B && nrhs > 0) return fail(HM_EINVAL, "null pointer");
+  if (nrhs < 0) return fail(HM_EINVAL, "nrhs < 0");
+  return lu_impl(A, opts, stream, out, info, B, ldb, nrhs);
 }
 
 void hm_lu_free(hm_lu F) {
@@ -857,11 +935,11 @@ void hm_lu_free(hm_lu F) {
 
 hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz) {
   if (!F) return fail(HM_EINVAL, "null pointer");
-  if (ntasks) *ntasks = F->pe->lu.ntasks;
+  if (ntasks) *ntasks = F->dag_ntasks;
   if (clock_khz) *clock_khz = g_clock_khz;
   if (!out) return HM_OK;
   if (!F->lu_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
-  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->pe->lu.ntasks * kTraceWords * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->dag_ntasks * kTraceWords * 8, hipMemcpyDeviceToHost));
   return HM_OK;
 }
 
@@ -884,7 +962,7 @@ static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
   // per level instead.
   int mode = HM_EXEC_DATAFLOW;
   if (const char* e = getenv("HM_SOLVE_EXEC")) mode = e[0] == 'l' ? HM_EXEC_LEVEL : HM_EXEC_DATAFLOW;
-  return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, true);
+  return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, DAG_SOLVE);
 }
 
 hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,

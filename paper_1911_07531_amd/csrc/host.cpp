@@ -296,7 +296,11 @@ class Tracer {
     temp_type_ = VT_F64;
     temp_base_ = temp_top_ = p_.n_f64;
     split_ = split_rows;
+    sub_ = true;
   }
+  void set_temp_base(int64_t b) { temp_base_ = temp_top_ = b; }
+  // tasks emitted from now on belong to a substitution (flag c1 = 1)
+  void begin_substitution() { sub_ = true; }
 
   bool ok() const { return err_.empty(); }
   const std::string& err() const { return err_; }
@@ -439,6 +443,7 @@ class Tracer {
 
   // ---- task emission with dependency tracking (Def. 3.2 + WAR/WAW) -----------
   void emit(Task tk, std::initializer_list<std::pair<const HView*, int>> acc) {
+    if (sub_) tk.c1 = 1;
     // a low-rank leaf with collected updates gets them applied before any
     // other task touches it
     for (auto& a : acc)
@@ -1069,6 +1074,7 @@ class Tracer {
   int scope_ = 0;                              // depth of nested hmul calls
   bool lazy_ = false;
   int32_t split_ = 0;                          // row chunk of split low-rank products (solve DAGs)
+  bool sub_ = false;                           // emitting substitution tasks
   std::vector<Pool> pools_;
   std::vector<int> preds_;
   std::vector<std::pair<int, int>> edges_;
@@ -1093,6 +1099,8 @@ bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
   p.nrhs_slot = (int)p.lr.size();
   p.nranks = p.nrhs_slot + 1;
   int64_t end = tr.temp_end();
+  p.lu_temp_base = p.prec == 1 ? p.blocks_f32 : p.n_f64;
+  p.lu_temp_end = end;
   if (p.prec == 1) {
     p.temp_bytes = (end - p.blocks_f32) * 4;
     p.n_f32 = end;
@@ -1100,6 +1108,36 @@ bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
     p.temp_bytes = (end - p.n_f64) * 8;
     p.n_f64 = end;
   }
+  return true;
+}
+
+bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy) {
+  p.fused = Dag();
+  // the H-LU part registers its accumulators again, in the same order
+  const std::vector<LrDesc> lr_saved = p.lr;
+  const std::vector<int32_t> blk_saved = p.lr_block;
+  p.lr.resize(p.nlr_leaf);
+  p.lr_block.resize(p.nlr_leaf);
+  Tracer tr(p, p.fused, temp_budget_bytes);
+  tr.set_temp_base(p.lu_temp_base);
+  tr.set_lazy(lazy);
+  tr.hlu(0);
+  tr.flush_all();
+  tr.begin_substitution();
+  HView x = tr.panel();
+  tr.solve_lower(0, x);
+  tr.solve_upper(0, x);
+  bool same = p.lr.size() == lr_saved.size() && p.lr_block == blk_saved;
+  for (size_t i = 0; same && i < p.lr.size(); ++i)
+    same = p.lr[i].u_off == lr_saved[i].u_off && p.lr[i].v_off == lr_saved[i].v_off && p.lr[i].cap == lr_saved[i].cap;
+  if (!tr.ok() || !same || tr.temp_end() != p.lu_temp_end) {
+    p.lr = lr_saved;
+    p.lr_block = blk_saved;
+    p.fused = Dag();
+    p.err = tr.ok() ? "internal: the fused trace differs from the H-LU trace" : tr.err();
+    return false;
+  }
+  tr.finish();
   return true;
 }
 

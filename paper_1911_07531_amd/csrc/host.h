@@ -72,6 +72,8 @@ struct Plan {
   int nrhs_slot = 0;
   int nlr_leaf = 0;        // low-rank leaves (the first entries of lr); the rest are accumulators
   Dag lu, solve;
+  Dag fused;               // H-LU followed by the substitution, one DAG (traced on demand)
+  int64_t lu_temp_base = 0, lu_temp_end = 0;  // temporaries of the H-LU trace (its element type)
   int64_t temp_bytes = 0;
   std::string err;
 };
@@ -84,5 +86,11 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
 // tree of truncations when the leaf is next read (accumulator arithmetic).
 bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy);
 bool trace_solve(Plan& p, int32_t split_rows);
+// The H-LU and the forward/backward substitution traced as one DAG (the
+// fusion of composed operations): a block row's substitution may start as
+// soon as its factors are final.  The H-LU part is task for task the DAG of
+// trace_lu (same temporaries, same accumulators); the substitution's tasks
+// carry c1 = 1 and its low-rank products are not split.  Requires trace_lu.
+bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy);
 
 }  // namespace hm

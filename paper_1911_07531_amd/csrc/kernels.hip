@@ -1039,6 +1039,7 @@ __device__ TruncScratch trunc_scratch(double* p) {
 // columns; Z (q x q, column-major) accumulates the rotations.  Round-robin
 // pairing, all pairs of a round in parallel.
 __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, double eps) {
+  static_assert(kThreads == 256, "four wavefront partial sums below");
   const int tid = threadIdx.x;
   for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   __syncthreads();
@@ -1055,13 +1056,16 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
   if (tid == 0) s_flag[1] = 0;
   __syncthreads();
   double* fro_s = (double*)(s_flag + 2);
-  if (tid == 0) *fro_s = 0.0;
-  __syncthreads();
   {
+    // per-wavefront partial sums added in a fixed order (the slots after
+    // fro_s are free once the caller's QR and Cholesky are done)
+    double* part = (double*)(s_flag + 4);
     double f = 0.0;
     for (int e = tid; e < p * q; e += blockDim.x) f += B[e] * B[e];
     f = group_sum(f, 64);
-    if ((tid & 63) == 0) atomicAdd(fro_s, f);
+    if ((tid & 63) == 0) part[tid >> 6] = f;
+    __syncthreads();
+    if (tid == 0) *fro_s = part[0] + part[1] + part[2] + part[3];
   }
   __syncthreads();
   const double tiny = *fro_s * fmax(1e-4 * eps * eps, 4.930380657631324e-32 * (p > 16 ? p : 16));
@@ -2405,11 +2409,15 @@ __device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
   wg_ctr(lds)[1] += flops;
 }
 
-template <bool kSolve>
+// Task sets of the executors: the H-LU's, the substitution's (TRSM, GEMM,
+// LRGEMM, GEMMP, ZERO, COPY with the streamed large-product paths), or both
+// (a fused DAG, whose substitution tasks carry c1 = 1).
+enum ExecMode { kModeLU = 0, kModeSolve = 1, kModeFused = 2 };
+
+template <int kMode>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch);
 
-// kSolve: the task set of a triangular solve (TRSM, GEMM, LRGEMM, ZERO, COPY).
-template <bool kSolve = false>
+template <int kMode = kModeLU>
 __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
   const Task& t = a.tasks[id];
   uint64_t t0 = 0;
@@ -2419,7 +2427,7 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
       for (int k = 0; k < 6; ++k) wg_ctr(lds)[kCtrSize + k] = 0;
     t0 = wall_clock64();
   }
-  run_task_body<kSolve>(a, t, lds, scratch);
+  run_task_body<kMode>(a, t, lds, scratch);
   if (a.counters) {
     __syncthreads();
     if (threadIdx.x == 0 && t.op >= 0 && t.op < OP_COUNT) {
@@ -2462,28 +2470,32 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
   }
 }
 
-template <bool kSolve>
+template <int kMode>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch) {
-  if ((kSolve && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) ||
-      (!kSolve && t.op == OP_GEMMP)) {
+  constexpr bool kLU = kMode != kModeSolve, kSub = kMode != kModeLU;
+  // streamed paths for the substitution's products only, so that the H-LU
+  // part of a fused DAG computes exactly as the H-LU's own DAG
+  const bool sub = kSub && (!kLU || t.c1 == 1);
+  if ((!kLU && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) ||
+      (!kSub && t.op == OP_GEMMP)) {
     if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
     return;
   }
   switch (t.op) {
     case OP_GETRF:
-      if (!kSolve) op_getrf(a, t, lds);
+      if (kLU) op_getrf(a, t, lds);
       break;
     case OP_TRSM_L:
       op_trsm(a, t, lds, 0);
       break;
     case OP_TRSM_UT:
-      if (!kSolve) op_trsm(a, t, lds, 1);
+      if (kLU) op_trsm(a, t, lds, 1);
       break;
     case OP_TRSM_U:
       op_trsm(a, t, lds, 2);
       break;
     case OP_GEMM:
-      if (kSolve && solve_skinny_gemm(a, t))
+      if (sub && solve_skinny_gemm(a, t))
         op_gemm_skinny(a, t, lds);
       else if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b))
         op_gemm_ct<float>(a, t, lds);
@@ -2491,7 +2503,7 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
         op_gemm_ct<double>(a, t, lds);
       break;
     case OP_LRGEMM:
-      if (kSolve && !lrgemm_fits_lds(a, t))
+      if (sub && !lrgemm_fits_lds(a, t))
         op_lrgemm_solve(a, t, lds);
       else if (all_f32(t.y) && all_f32(t.a) && all_f32(t.b) && all_f32(t.x))
         op_lrgemm_ct<float>(a, t, lds);
@@ -2499,11 +2511,11 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
         op_lrgemm_ct<double>(a, t, lds);
       break;
     case OP_GEMMP:
-      if (kSolve) op_gemmp(a, t, lds);
+      if (kSub) op_gemmp(a, t, lds);
       break;
     case OP_TRUNC:
     case OP_TRUNC2:
-      if (!kSolve) op_trunc(a, t, lds, scratch);
+      if (kLU) op_trunc(a, t, lds, scratch);
       break;
     case OP_ZERO:
       op_zero(a, t);
@@ -2550,7 +2562,7 @@ __global__ void __launch_bounds__(kThreads, 2) solve_level_kernel(ExecArgs a, co
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   wg_ctr_init(a, lds);
   for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
-    run_task<true>(a, order[i], lds, scratch);
+    run_task<kModeSolve>(a, order[i], lds, scratch);
     __syncthreads();
   }
   wg_ctr_flush(a, lds);
@@ -2576,7 +2588,7 @@ __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_
 // to zero.  Every slot below ntasks is filled exactly once for an acyclic DAG;
 // a workgroup that waits longer than spin_limit wall-clock ticks raises ST_TIMEOUT and
 // every workgroup then leaves.
-template <bool kSolve>
+template <int kMode>
 __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int& s_task) {
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int tid = threadIdx.x;
@@ -2608,7 +2620,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
       wg_ctr_flush(a, lds);
       return;
     }
-    run_task<kSolve>(a, t, lds, scratch);
+    run_task<kMode>(a, t, lds, scratch);
     // Publication: every thread's stores precede the workgroup barrier; one
     // agent-scope release fence then makes them visible across XCDs before
     // any successor count drops.  The workgroup that releases a successor
@@ -2641,7 +2653,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
 __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_task;
-  dataflow_body<false>(a, lds, s_task);
+  dataflow_body<kModeLU>(a, lds, s_task);
 }
 
 // The same executor for the forward / backward substitution DAGs, built
@@ -2649,7 +2661,14 @@ __global__ void __launch_bounds__(kThreads, 2) exec_dataflow_kernel(ExecArgs a) 
 __global__ void __launch_bounds__(kThreads, 2) solve_dataflow_kernel(ExecArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_task;
-  dataflow_body<true>(a, lds, s_task);
+  dataflow_body<kModeSolve>(a, lds, s_task);
+}
+
+// The persistent executor for a fused DAG (H-LU followed by the substitution).
+__global__ void __launch_bounds__(kThreads, 2) fused_dataflow_kernel(ExecArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_task;
+  dataflow_body<kModeFused>(a, lds, s_task);
 }
 
 // ---------------------------------------------------------------------------
@@ -2691,6 +2710,10 @@ __global__ void __launch_bounds__(kThreads) assemble_aca_kernel(ExecArgs a, AsmA
   double* U = fac + (int64_t)blockIdx.x * fac_stride;  // m x kMaxK
   double* V = U + (int64_t)m * kMaxK;                  // n x kMaxK
   char* used = (char*)(V + (int64_t)n * kMaxK);        // m flags
+  if ((int64_t)(m + n) * kMaxK * 8 + m > fac_stride * 8) {  // the slot must hold this block
+    if (tid == 0) atomicOr(&a.status[0], ST_BADOP);
+    return;
+  }
   double* red = (double*)(lds + kLdsBytes - 4096);     // reduction scratch
   int* ired = (int*)(lds + kLdsBytes - 2048);
   for (int i = tid; i < m; i += blockDim.x) used[i] = 0;

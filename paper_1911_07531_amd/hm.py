@@ -56,7 +56,7 @@ _lib = None
 
 def exported_symbols():
     """Names every build of libhm.so must export (the entry points of include/hm.h)."""
-    return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu",
+    return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu", "h_lu_solve",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
             "hm_dag_export", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
 
@@ -83,6 +83,7 @@ def lib():
         "hm_tree_export": [vp, vp, vp, vp, vp],
         "h_assemble": [vp, ip, dbl, C.POINTER(Opts), vp, C.POINTER(vp)],
         "h_lu": [vp, C.POINTER(Opts), vp, C.POINTER(vp), C.POINTER(i64)],
+        "h_lu_solve": [vp, C.POINTER(Opts), vp, i64, i64, vp, C.POINTER(vp), C.POINTER(i64)],
         "h_solve": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
         "hm_footprint": [vp, ip, C.POINTER(C.c_size_t)],
@@ -253,12 +254,18 @@ class Matrix:
 
 
 class LU:
-    """H-LU factors (h_lu)."""
+    """H-LU factors (h_lu).  With rhs (an (n, nrhs) column-major float64 device
+    tensor) the factorization and the substitution of rhs run as one DAG
+    (h_lu_solve) and rhs is overwritten by the solution."""
 
-    def __init__(self, a: Matrix, opts: Opts, stream=None):
+    def __init__(self, a: Matrix, opts: Opts, stream=None, rhs=None):
         h = C.c_void_p()
         info = C.c_int64(0)
-        code = lib().h_lu(a.h, C.byref(opts), _stream_ptr(stream), C.byref(h), C.byref(info))
+        if rhs is None:
+            code = lib().h_lu(a.h, C.byref(opts), _stream_ptr(stream), C.byref(h), C.byref(info))
+        else:
+            bp, ldb, k = _col_major(rhs)
+            code = lib().h_lu_solve(a.h, C.byref(opts), bp, ldb, k, _stream_ptr(stream), C.byref(h), C.byref(info))
         if code != HM_OK and code != HM_ERANK:
             _check(code, info.value)
         self.rank_overflow = code == HM_ERANK

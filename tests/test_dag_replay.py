@@ -151,3 +151,45 @@ def test_replay_with_reused_temporaries(monkeypatch):
         assert H.lu_error_2norm(dense, f, exact=True) <= 10 * eps
         rg = H.rank_table(f)
         assert max(abs(rg[i] - rr[i]) for i in rr) <= 2
+
+
+@pytest.mark.parametrize("lazy", [0, 1])
+def test_fused_lu_solve_dag(lazy):
+    """The H-LU and the substitution traced as one DAG (h_lu_solve): its first
+    tasks are the H-LU DAG's tasks, record for record, with the same edges
+    among them; replayed in random topological orders it gives the oracle's
+    factors and solution."""
+    n, leaf, eps = 512, 32, 1e-6
+    t, opts, a = _setup(n, leaf, 2.0, eps, 0, lazy=lazy)
+    dag = t.dag(opts, 0)
+    fdag = t.dag(opts, 2)
+    nl = len(dag["tasks"])
+    assert len(fdag["tasks"]) > nl
+    assert fdag["tasks"][:nl].tobytes() == dag["tasks"].tobytes()
+    assert np.all(fdag["tasks"]["c1"][nl:] == 1)
+    sp, si, fsp, fsi = dag["succ_ptr"], dag["succ_idx"], fdag["succ_ptr"], fdag["succ_idx"]
+    for i in range(nl):
+        own = fsi[fsp[i]:fsp[i + 1]]
+        assert np.array_equal(np.sort(own[own < nl]), np.sort(si[sp[i]:sp[i + 1]]))
+    assert np.all(fsi[fsp[nl]:] >= nl)  # no substitution task precedes an H-LU task
+    ref = H.hlu(a, lazy=bool(lazy))
+    b = inputs.rhs(n, 4, seed=2)
+    ref_x = H.solve(ref, b)
+    blocks = {bb.index: bb for bb in H.leaf_blocks(a.root)}
+    for k in range(2):
+        rp = Replay(fdag, eps, 0)
+        rp.load_matrix(blocks, fdag["block_off"], fdag["lr"])
+        rs = fdag["nranks"] - 1
+        rp.ranks[rs] = 4
+        po = min(int(tk["x"]["off"]) for tk in fdag["tasks"][nl:] if tk["op"] in (2, 4))
+        rp.f64[po:po + n * 4] = b[a.perm].flatten(order="F")
+        rp.run(np.random.default_rng(10 + k))
+        x = np.empty((n, 4))
+        x[a.perm] = rp.f64[po:po + n * 4].reshape(4, n).T
+        if lazy:
+            # collected updates: the device combines a batch by a tree of
+            # truncations, the oracle in one; compare through the residual
+            f = _factors_from_replay(rp, t, a, fdag)
+            assert np.allclose(x, H.solve(f, b), rtol=0, atol=1e-9 * np.abs(x).max())
+        else:
+            assert np.allclose(x, ref_x, rtol=0, atol=1e-9 * np.abs(ref_x).max())

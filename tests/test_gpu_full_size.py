@@ -62,3 +62,23 @@ def test_level_and_dataflow_identical_full_size(c3):
     f.solve(x1)
     g.solve(x2)
     assert np.array_equal(to_host(x1), to_host(x2))
+
+
+def test_fused_lu_solve_full_size(c3):
+    """h_lu_solve at n = 131072: the same factors as h_lu (sampled leaves bit
+    for bit) and the solution of h_lu + h_solve up to the rounding of the
+    split products of the separate substitution."""
+    pts, diag, tree, A, f = c3
+    opts = hm.make_opts(leaf=LEAF, eta=2.0, eps=EPS, max_rank=CAP, prec=hm.MIXED)
+    b = inputs.rhs(N, 4, seed=3)
+    x1, x2 = device_rhs(b), device_rhs(b)
+    f.solve(x1)
+    g = hm.LU(A, opts, rhs=x2)
+    x1, x2 = to_host(x1), to_host(x2)
+    print("fused vs separate: max relative difference", np.abs(x1 - x2).max() / np.abs(x1).max())
+    assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x1).max()
+    _, _, _, bl = tree.tables()
+    leaves = np.nonzero(bl[:, 2] != 0)[0]
+    for bi in np.random.default_rng(1).choice(leaves, 200, replace=False):
+        r1, r2 = f.leaf(int(bi)), g.leaf(int(bi))
+        assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])

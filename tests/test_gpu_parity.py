@@ -244,3 +244,43 @@ def test_split_solve_products(monkeypatch):
     assert np.array_equal(out[("0", "level")], out[("0", "dataflow")])
     ref = out[("0", "level")]
     assert np.max(np.abs(out[("128", "level")] - ref)) <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])
+def test_fused_lu_solve_equals_separate(prec):
+    """h_lu_solve runs the H-LU and the substitution as one DAG: the factors
+    equal h_lu's leaf for leaf, bit for bit, and the solution equals h_lu
+    followed by h_solve bit for bit (no product is split at this size); with
+    70 right-hand sides the first 64 are fused and the rest solved after."""
+    p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False, prec=prec)
+    f = hm.LU(p.A, p.opts)
+    _, _, _, bl = p.tree.tables()
+    leaves = np.nonzero(bl[:, 2] != 0)[0]
+    for nrhs in (5, 70):
+        b = inputs.rhs(p.n, nrhs, seed=7)
+        x1 = device_rhs(b)
+        f.solve(x1)
+        x2 = device_rhs(b)
+        g = hm.LU(p.A, p.opts, rhs=x2)
+        assert np.array_equal(to_host(x1), to_host(x2))
+        for bi in leaves[::7]:
+            r1, r2 = f.leaf(int(bi)), g.leaf(int(bi))
+            assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
+
+
+def test_assembly_reproducible():
+    """Two assemblies of the same tree are bit-identical (same H-matvec bit
+    for bit, same leaves).  Each ACA workgroup owns a scratch slot sized for
+    its block; an undersized slot made neighbouring blocks overwrite each
+    other's factors now and then."""
+    pts, diag = inputs.sphere_problem(32768, 0)
+    opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=64, prec=hm.MIXED)
+    t = hm.Tree(pts, opts)
+    mats = [hm.Matrix(t, hm.LAPLACE3D, diag, opts) for _ in range(3)]
+    x = device_rhs(inputs.rhs(32768, 4, seed=11))
+    ys = [to_host(m.matvec(x)) for m in mats]
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+    _, _, _, bl = t.tables()
+    for bi in np.nonzero(bl[:, 2] == 2)[0]:
+        r = [m.leaf(int(bi)) for m in mats]
+        assert all(np.array_equal(r[0][1], q[1]) and np.array_equal(r[0][2], q[2]) for q in r[1:]), bi
