@@ -206,6 +206,24 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
 hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
                         int32_t* level, int64_t* block_off, int64_t* lr);
 
+/* The paper-level leaf call of every traced task (host only): ncalls calls of
+ * 4 int32 each (kind 0 hlu, 1 htrsl, 2 htrsu, 3 hmul; then the blocks: hlu
+ * (d, d, d), htrsl (L, M, M), htrsu (U, M, M), hmul (A, B, C), block indices
+ * of hm_tree_export), and task_call (ntasks int32, the call of each task, -1
+ * outside any call).  which as for hm_dag_sizes.  Any output may be NULL. */
+hm_status hm_dag_calls(hm_tree t, const hm_opts* opts, int which, int64_t* ncalls, int32_t* calls, int32_t* task_call);
+
+/* The H-LU task graph by the paper's semi-automatic construction (host only):
+ * task refinement from the single task hlu(A, L, U) with inherited and refined
+ * dependencies of Definition 3.2 (Sec. 3, Algorithms 9-11), and with
+ * sparsify != 0 the removal of redundant edges after every refinement step
+ * (Sec. 4.1, Algorithm 12, paths of at most max_path edges, 0 = unbounded).
+ * tasks: ntasks x 4 int32 as in hm_dag_calls; edges: nedges x 2 int32 (task
+ * indices, predecessor first).  Call with NULL arrays to learn the sizes
+ * (each call recomputes the graph). */
+hm_status hm_semiauto_dag(hm_tree t, int sparsify, int max_path, int64_t* ntasks, int64_t* nedges, int32_t* tasks,
+                          int32_t* edges);
+
 void hm_tree_free(hm_tree t);
 void hm_matrix_free(hm_matrix A);
 void hm_lu_free(hm_lu F);

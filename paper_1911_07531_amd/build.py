@@ -33,10 +33,11 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libhm.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    host_o = os.path.join(BUILD, "host.o")
-    _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", "-c",
-          os.path.join(CSRC, "host.cpp"), "-o", host_o])
-    objs.append(host_o)
+    for src in ("host.cpp", "semiauto.cpp"):
+        o = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", "-c",
+              os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
     for src in ("kernels.hip", "capi.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])

@@ -531,6 +531,36 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
   return HM_OK;
 }
 
+hm_status hm_dag_calls(hm_tree t, const hm_opts* opts, int which, int64_t* ncalls, int32_t* calls, int32_t* task_call) {
+  if (!t || !opts || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
+  PlanEntry* pe;
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
+  if (st) return st;
+  if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
+  const Plan& p = pe->plan;
+  const Dag& d = which == 0 ? p.lu : which == 1 ? p.solve : p.fused;
+  if (ncalls) *ncalls = (int64_t)(d.calls.size() / 4);
+  if (calls && !d.calls.empty()) std::memcpy(calls, d.calls.data(), d.calls.size() * 4);
+  if (task_call && !d.task_call.empty()) std::memcpy(task_call, d.task_call.data(), d.task_call.size() * 4);
+  return HM_OK;
+}
+
+hm_status hm_semiauto_dag(hm_tree t, int sparsify, int max_path, int64_t* ntasks, int64_t* nedges, int32_t* tasks,
+                          int32_t* edges) {
+  if (!t || max_path < 0) return fail(HM_EINVAL, "bad argument");
+  std::vector<int32_t> tv, ev;
+  try {
+    build_semiauto_dag(t->t, sparsify != 0, max_path, tv, ev);
+  } catch (const std::bad_alloc&) {
+    return fail(HM_ENOMEM, "host allocation failed");
+  }
+  if (ntasks) *ntasks = (int64_t)(tv.size() / 4);
+  if (nedges) *nedges = (int64_t)(ev.size() / 2);
+  if (tasks && !tv.empty()) std::memcpy(tasks, tv.data(), tv.size() * 4);
+  if (edges && !ev.empty()) std::memcpy(edges, ev.data(), ev.size() * 4);
+  return HM_OK;
+}
+
 hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
                         int32_t* level, int64_t* block_off, int64_t* lr) {
   if (!t || !opts || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");

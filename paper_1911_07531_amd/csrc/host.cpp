@@ -453,6 +453,7 @@ class Tracer {
       }
     int id = (int)d_.tasks.size();
     d_.tasks.push_back(tk);
+    d_.task_call.push_back(call_);
     preds_.clear();
     // A view whose extent follows a rank must be ordered after the truncation
     // that set it: the task must also access that low-rank leaf's (or
@@ -917,7 +918,9 @@ class Tracer {
         for (int j = 0; j < 2; ++j)
           for (int l = 0; l < 2; ++l) hmul(alpha, A.son[2 * i + l], B.son[2 * l + j], C.son[2 * i + j]);
     } else {
+      const int prev = begin_call(PT_HMUL, a, b, c);
       leaf_update(alpha, a, b, c);
+      call_ = prev;
     }
     --scope_;
     if (top) {
@@ -974,10 +977,10 @@ class Tracer {
       for (int j = 0; j < 2; ++j) htrsl(L.son[0], M.son[j]);
       for (int j = 0; j < 2; ++j) hmul(-1.0, L.son[2], M.son[j], M.son[2 + j]);
       for (int j = 0; j < 2; ++j) htrsl(L.son[3], M.son[2 + j]);
-    } else if (M.kind == BK_DENSE) {
-      solve_lower(ld, dense(m));
     } else {
-      solve_lower(ld, lr_u(m));
+      const int prev = begin_call(PT_HTRSL, ld, m, m);
+      solve_lower(ld, M.kind == BK_DENSE ? dense(m) : lr_u(m));
+      call_ = prev;
     }
   }
   // Mirror of Algorithm 3: X U = M (X overwrites M)
@@ -988,10 +991,10 @@ class Tracer {
       for (int j = 0; j < 2; ++j) htrsu(U.son[0], M.son[2 * j]);
       for (int j = 0; j < 2; ++j) hmul(-1.0, M.son[2 * j], U.son[1], M.son[2 * j + 1]);
       for (int j = 0; j < 2; ++j) htrsu(U.son[3], M.son[2 * j + 1]);
-    } else if (M.kind == BK_DENSE) {
-      solve_upper_t(ud, transpose(dense(m)));
     } else {
-      solve_upper_t(ud, lr_v(m));
+      const int prev = begin_call(PT_HTRSU, ud, m, m);
+      solve_upper_t(ud, M.kind == BK_DENSE ? transpose(dense(m)) : lr_v(m));
+      call_ = prev;
     }
   }
   // Algorithm 2
@@ -1004,12 +1007,22 @@ class Tracer {
       hmul(-1.0, A.son[2], A.son[1], A.son[3]);
       hlu(A.son[3]);
     } else {
+      const int prev = begin_call(PT_HLU, a, a, a);
       getrf(a);
+      call_ = prev;
     }
   }
 
   void fail(const std::string& m) {
     if (err_.empty()) err_ = m;
+  }
+  // tasks emitted from now on belong to this paper-level leaf call; returns
+  // the previous call
+  int begin_call(int fn, int b0, int b1, int b2) {
+    const int prev = call_;
+    call_ = (int)(d_.calls.size() / 4);
+    d_.calls.insert(d_.calls.end(), {fn, b0, b1, b2});
+    return prev;
   }
 
  private:
@@ -1074,6 +1087,7 @@ class Tracer {
   int scope_ = 0;                              // depth of nested hmul calls
   bool lazy_ = false;
   int32_t split_ = 0;                          // row chunk of split low-rank products (solve DAGs)
+  int32_t call_ = -1;                          // current paper-level leaf call (Dag::calls)
   bool sub_ = false;                           // emitting substitution tasks
   std::vector<Pool> pools_;
   std::vector<int> preds_;

@@ -40,8 +40,16 @@ void build_cluster_tree(const double* pts, int64_t n, int dim, int leaf, Tree& t
 void build_block_tree(Tree& t, double eta);
 
 // Storage of every leaf block inside the arenas, and the traced task DAGs.
+// The paper's task kinds (Sec. 3): the leaf-level calls of Algorithms 1-3.
+enum PaperFn { PT_HLU = 0, PT_HTRSL = 1, PT_HTRSU = 2, PT_HMUL = 3 };
+
 struct Dag {
   std::vector<Task> tasks;
+  // the paper-level leaf call (hlu, htrsl, htrsu, hmul on blocks) that each
+  // task belongs to: task_call[i] indexes calls (4 ints: kind, three block
+  // indices as in build_semiauto_dag), -1 outside any call
+  std::vector<int32_t> task_call;
+  std::vector<int32_t> calls;
   std::vector<int32_t> indeg;
   std::vector<int32_t> succ_ptr, succ_idx;
   std::vector<int32_t> level;       // longest-path level of each task
@@ -92,5 +100,12 @@ bool trace_solve(Plan& p, int32_t split_rows);
 // trace_lu (same temporaries, same accumulators); the substitution's tasks
 // carry c1 = 1 and its low-rank products are not split.  Requires trace_lu.
 bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy);
+// The paper's semi-automatic construction of the H-LU task graph (Sec. 3,
+// Algorithms 9-11; with sparsify, Algorithm 12 after every refinement step,
+// paths of at most max_path edges, 0 = unbounded).  tasks: 4 ints per leaf
+// task (kind, blocks: hlu (d, d, d), htrsl (L, M, M), htrsu (U, M, M), hmul
+// (A, B, C)), in creation order; edges: pairs of task indices.
+void build_semiauto_dag(const Tree& t, bool sparsify, int max_path, std::vector<int32_t>& tasks,
+                        std::vector<int32_t>& edges);
 
 }  // namespace hm

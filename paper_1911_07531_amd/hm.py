@@ -58,7 +58,7 @@ def exported_symbols():
     """Names every build of libhm.so must export (the entry points of include/hm.h)."""
     return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu", "h_lu_solve",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
-            "hm_dag_export", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
+            "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
 
 
 def lib():
@@ -92,6 +92,8 @@ def lib():
         "hm_dag_sizes": [vp, C.POINTER(Opts), ip, vp],
         "hm_dag_export": [vp, C.POINTER(Opts), ip, vp, vp, vp, vp, vp, vp],
         "hm_lu_trace": [vp, vp, C.POINTER(i64), C.POINTER(i64)],
+        "hm_dag_calls": [vp, C.POINTER(Opts), ip, C.POINTER(i64), vp, vp],
+        "hm_semiauto_dag": [vp, ip, ip, C.POINTER(i64), C.POINTER(i64), vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -198,6 +200,27 @@ class Tree:
         bl = np.zeros((nbl.value, 7), np.int32)
         _check(lib().hm_tree_export(self.h, perm.ctypes.data, cl.ctypes.data, box.ctypes.data, bl.ctypes.data))
         return perm, cl, box, bl
+
+    def calls(self, opts: Opts, which: int = 0):
+        """(calls (ncalls, 4) int32, task_call (ntasks,) int32) of a traced DAG (hm_dag_calls)."""
+        nc = C.c_int64(0)
+        _check(lib().hm_dag_calls(self.h, C.byref(opts), which, C.byref(nc), None, None))
+        sz = np.zeros(10, np.int64)
+        _check(lib().hm_dag_sizes(self.h, C.byref(opts), which, sz.ctypes.data))
+        calls = np.zeros((max(1, nc.value), 4), np.int32)
+        tc = np.zeros(max(1, int(sz[0])), np.int32)
+        _check(lib().hm_dag_calls(self.h, C.byref(opts), which, C.byref(nc), calls.ctypes.data, tc.ctypes.data))
+        return calls[:nc.value], tc[:int(sz[0])]
+
+    def semiauto_dag(self, sparsify: bool = False, max_path: int = 0):
+        """The paper's semi-automatic H-LU task graph (hm_semiauto_dag): (tasks (n, 4), edges (m, 2))."""
+        nt, ne = C.c_int64(0), C.c_int64(0)
+        _check(lib().hm_semiauto_dag(self.h, int(sparsify), max_path, C.byref(nt), C.byref(ne), None, None))
+        tasks = np.zeros((max(1, nt.value), 4), np.int32)
+        edges = np.zeros((max(1, ne.value), 2), np.int32)
+        _check(lib().hm_semiauto_dag(self.h, int(sparsify), max_path, C.byref(nt), C.byref(ne), tasks.ctypes.data,
+                                     edges.ctypes.data))
+        return tasks[:nt.value], edges[:ne.value]
 
     def dag(self, opts: Opts, which: int = 0):
         """The traced DAG (host only): dict of numpy arrays and sizes."""
