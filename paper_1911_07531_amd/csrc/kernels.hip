@@ -2585,32 +2585,49 @@ __global__ void exec_reset_kernel(ExecArgs a, const int32_t* indeg, const int32_
 
 // Persistent dataflow executor: workgroups claim queue slots in order, run the
 // task that lands there, and release successors whose predecessor count drops
-// to zero.  Every slot below ntasks is filled exactly once for an acyclic DAG;
-// a workgroup that waits longer than spin_limit wall-clock ticks raises ST_TIMEOUT and
-// every workgroup then leaves.
+// to zero.  In the substitution DAGs (narrow chains) a workgroup runs the
+// first substitution task it releases itself, with no queue round trip, and
+// fills that task's queue slot with a skip marker (-2), so that every slot
+// below ntasks is still filled exactly once for an acyclic DAG; a workgroup
+// that draws a marker claims the next slot.  A workgroup that waits longer
+// than spin_limit wall-clock ticks raises ST_TIMEOUT and every workgroup then
+// leaves.
 template <int kMode>
 __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int& s_task) {
+  __shared__ int s_next;  // a successor this workgroup released for itself, or -1
   double* scratch = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int tid = threadIdx.x;
+  if (tid == 0) s_next = -1;
   wg_ctr_init(a, lds);
   for (;;) {
     if (tid == 0) {
-      int t = -1;
-      int slot = atomicAdd(&a.qctl[0], 1);
-      if (slot < a.ntasks) {
+      int t = s_next;
+      s_next = -1;
+      bool stop = false;
+      while (t < 0 && !stop) {
+        const int slot = atomicAdd(&a.qctl[0], 1);
+        if (slot >= a.ntasks) break;
         const uint64_t t0 = wall_clock64();
+        int v;
         for (;;) {
-          t = __hip_atomic_load(&a.queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (t >= 0) break;
-          if (__hip_atomic_load(&a.qctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          v = __hip_atomic_load(&a.queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v != -1) break;
+          if (__hip_atomic_load(&a.qctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            stop = true;
+            break;
+          }
           if ((int64_t)(wall_clock64() - t0) > a.spin_limit) {
             atomicOr(&a.status[0], ST_TIMEOUT);
             __hip_atomic_store(&a.qctl[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = true;
             break;
           }
           __builtin_amdgcn_s_sleep(1);
         }
-        if (t >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!stop && v >= 0) {
+          t = v;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
       }
       s_task = t;
     }
@@ -2635,14 +2652,30 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
     __syncthreads();
     if (tid < 64) {
       const int b = a.succ_ptr[t], e = a.succ_ptr[t + 1];
-      for (int k = b + tid; k < e; k += 64) {
-        const int s = a.succ_idx[k];
-        int prev = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 1) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-          int pos = atomicAdd(&a.qctl[1], 1);
+      bool kept = false;
+      for (int k0 = b; k0 < e; k0 += 64) {
+        const int k = k0 + tid;
+        int s = -1;
+        bool rel = false;
+        if (k < e) {
+          s = a.succ_idx[k];
+          rel = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1;
+        }
+        if (rel) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        // substitution tasks only: the H-LU keeps its queue order
+        const bool can_keep = rel && (kMode == kModeSolve || (kMode == kModeFused && a.tasks[s].c1 == 1));
+        const unsigned long long m = __ballot(can_keep);
+        int keep = -1;
+        if (!kept && m) {
+          keep = __ffsll((long long)m) - 1;
+          kept = true;
+        }
+        if (rel) {
           if (a.trace) a.trace[(int64_t)kTraceWords * s + 7] = wall_clock64();
-          if (pos < a.ntasks) __hip_atomic_store(&a.queue[pos], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int pos = atomicAdd(&a.qctl[1], 1);
+          if (tid == keep) s_next = s;
+          if (pos < a.ntasks)
+            __hip_atomic_store(&a.queue[pos], tid == keep ? -2 : s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
