@@ -2419,7 +2419,16 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
 
 template <int kMode = kModeLU>
 __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
-  const Task& t = a.tasks[id];
+  // the record in LDS: one load phase instead of a chain of dependent
+  // global loads as the task's fields are used
+  Task* lt = (Task*)(lds + kLdsBytes + (kCtrSize + 6) * 8);
+  {
+    const int* src = (const int*)(a.tasks + id);
+    int* dst = (int*)lt;
+    for (int i = threadIdx.x; i < (int)(sizeof(Task) / 4); i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const Task& t = *lt;
   uint64_t t0 = 0;
   if (threadIdx.x == 0) {
     count_task(a, t, lds);
