@@ -2417,66 +2417,73 @@ enum ExecMode { kModeLU = 0, kModeSolve = 1, kModeFused = 2 };
 template <int kMode>
 __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, double* scratch);
 
+// The running task's record and start tick live in LDS after the counters.
+__device__ __forceinline__ Task* task_copy(char* lds) { return (Task*)(lds + kLdsBytes + (kCtrSize + 6) * 8); }
+__device__ __forceinline__ uint64_t* task_t0(char* lds) {
+  return (uint64_t*)(lds + kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task));
+}
+
+// Runs task id: its record is copied into LDS in one load phase (instead of
+// dependent global loads as its fields are used), then its body runs.  The
+// statistics are taken by account_task after the task, off the hand-off path.
 template <int kMode = kModeLU>
 __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) {
-  // the record in LDS: one load phase instead of a chain of dependent
-  // global loads as the task's fields are used
-  Task* lt = (Task*)(lds + kLdsBytes + (kCtrSize + 6) * 8);
+  Task* lt = task_copy(lds);
   {
     const int* src = (const int*)(a.tasks + id);
     int* dst = (int*)lt;
     for (int i = threadIdx.x; i < (int)(sizeof(Task) / 4); i += blockDim.x) dst[i] = src[i];
   }
-  __syncthreads();
-  const Task& t = *lt;
-  uint64_t t0 = 0;
-  if (threadIdx.x == 0) {
-    count_task(a, t, lds);
-    if (a.counters && a.trace)
+  if (threadIdx.x == 0 && a.counters) {
+    if (a.trace)
       for (int k = 0; k < 6; ++k) wg_ctr(lds)[kCtrSize + k] = 0;
-    t0 = wall_clock64();
+    *task_t0(lds) = wall_clock64();
   }
-  run_task_body<kMode>(a, t, lds, scratch);
-  if (a.counters) {
-    __syncthreads();
-    if (threadIdx.x == 0 && t.op >= 0 && t.op < OP_COUNT) {
-      const uint64_t t1 = wall_clock64();
-      wg_ctr(lds)[kCtrBusy + t.op] += t1 - t0;
-      wg_ctr(lds)[kCtrCount + t.op] += 1;
-      if (a.trace) {
-        uint64_t* tr = a.trace + (int64_t)kTraceWords * id;
-        tr[0] = t0;
-        tr[1] = t1;
-        uint64_t info = blockIdx.x & 0xffff;
-        if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
-          const LrDesc d = a.lr[t.lr];
-          uint64_t K = (uint64_t)resolve(a, t.a).cols;
-          if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
-          info |= (K & 0xffff) << 16 | (uint64_t)(d.m & 0xffff) << 32 | (uint64_t)(d.n & 0xffff) << 48;
-        } else {
-          // output rows / columns and the inner dimension
-          const View& o = (t.op == OP_GETRF) ? t.a : (t.op >= OP_TRSM_L && t.op <= OP_TRSM_U) ? t.x : t.y;
-          const RV r = resolve(a, o);
-          const int kd = (t.op == OP_GEMM || t.op == OP_LRGEMM) ? resolve(a, t.a).cols : t.a.rows;
-          info |= (uint64_t)(r.rows & 0xffff) << 16 | (uint64_t)(r.cols & 0xffff) << 32 | (uint64_t)(kd & 0xffff) << 48;
-        }
-        tr[2] = info;
-        uint64_t info2 = 0;
-        if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
-          const int* s_int = (const int*)(lds + kLdsBytes - 64);
-          info2 = (uint64_t)(s_int[12] & 0xff) | (uint64_t)(s_int[13] & 0xfff) << 8 |
-                  (uint64_t)((s_int[13] >> 16) & 0xfff) << 20 | (uint64_t)(s_int[14] & 0xff) << 32 |
-                  (uint64_t)((s_int[14] >> 16) & 0xff) << 40;
-        }
-        tr[3] = info2;
-        for (int k = 0; k < 3; ++k) {
-          const uint64_t lo = wg_ctr(lds)[kCtrSize + 2 * k], hi = wg_ctr(lds)[kCtrSize + 2 * k + 1];
-          tr[4 + k] = (lo > 0xffffffffull ? 0xffffffffull : lo) | (hi > 0xffffffffull ? 0xffffffffull : hi) << 32;
-        }
-        // tr[7]: the tick at which the task was pushed to the ready queue
-      }
-    }
+  __syncthreads();
+  run_task_body<kMode>(a, *lt, lds, scratch);
+}
+
+// Statistics of the task that just ran (one thread, after a barrier that
+// follows the task; the record copy is still in LDS).
+__device__ void account_task(const ExecArgs& a, int id, char* lds) {
+  if (!a.counters) return;
+  const Task& t = *task_copy(lds);
+  count_task(a, t, lds);
+  if (t.op < 0 || t.op >= OP_COUNT) return;
+  const uint64_t t0 = *task_t0(lds), t1 = wall_clock64();
+  wg_ctr(lds)[kCtrBusy + t.op] += t1 - t0;
+  wg_ctr(lds)[kCtrCount + t.op] += 1;
+  if (!a.trace) return;
+  uint64_t* tr = a.trace + (int64_t)kTraceWords * id;
+  tr[0] = t0;
+  tr[1] = t1;
+  uint64_t info = blockIdx.x & 0xffff;
+  if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
+    const LrDesc d = a.lr[t.lr];
+    uint64_t K = (uint64_t)resolve(a, t.a).cols;
+    if (t.op == OP_TRUNC2) K += (uint64_t)resolve(a, t.x).cols;
+    info |= (K & 0xffff) << 16 | (uint64_t)(d.m & 0xffff) << 32 | (uint64_t)(d.n & 0xffff) << 48;
+  } else {
+    // output rows / columns and the inner dimension
+    const View& o = (t.op == OP_GETRF) ? t.a : (t.op >= OP_TRSM_L && t.op <= OP_TRSM_U) ? t.x : t.y;
+    const RV r = resolve(a, o);
+    const int kd = (t.op == OP_GEMM || t.op == OP_LRGEMM) ? resolve(a, t.a).cols : t.a.rows;
+    info |= (uint64_t)(r.rows & 0xffff) << 16 | (uint64_t)(r.cols & 0xffff) << 32 | (uint64_t)(kd & 0xffff) << 48;
   }
+  tr[2] = info;
+  uint64_t info2 = 0;
+  if (t.op == OP_TRUNC || t.op == OP_TRUNC2) {
+    const int* s_int = (const int*)(lds + kLdsBytes - 64);
+    info2 = (uint64_t)(s_int[12] & 0xff) | (uint64_t)(s_int[13] & 0xfff) << 8 |
+            (uint64_t)((s_int[13] >> 16) & 0xfff) << 20 | (uint64_t)(s_int[14] & 0xff) << 32 |
+            (uint64_t)((s_int[14] >> 16) & 0xff) << 40;
+  }
+  tr[3] = info2;
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t lo = wg_ctr(lds)[kCtrSize + 2 * k], hi = wg_ctr(lds)[kCtrSize + 2 * k + 1];
+    tr[4 + k] = (lo > 0xffffffffull ? 0xffffffffull : lo) | (hi > 0xffffffffull ? 0xffffffffull : hi) << 32;
+  }
+  // tr[7]: the tick at which the task was pushed to the ready queue
 }
 
 template <int kMode>
@@ -2560,6 +2567,8 @@ __global__ void __launch_bounds__(kThreads, 2) exec_level_kernel(ExecArgs a, con
   for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
     run_task(a, order[i], lds, scratch);
     __syncthreads();
+    if (threadIdx.x == 0) account_task(a, order[i], lds);
+    __syncthreads();
   }
   wg_ctr_flush(a, lds);
 }
@@ -2572,6 +2581,8 @@ __global__ void __launch_bounds__(kThreads, 2) solve_level_kernel(ExecArgs a, co
   wg_ctr_init(a, lds);
   for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
     run_task<kModeSolve>(a, order[i], lds, scratch);
+    __syncthreads();
+    if (threadIdx.x == 0) account_task(a, order[i], lds);
     __syncthreads();
   }
   wg_ctr_flush(a, lds);
@@ -2687,6 +2698,8 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
             __hip_atomic_store(&a.queue[pos], tid == keep ? -2 : s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
+    } else if (tid == 64) {
+      account_task(a, t, lds);  // beside the hand-off, not before it
     }
     __syncthreads();
   }
