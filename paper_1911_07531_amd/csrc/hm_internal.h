@@ -145,8 +145,8 @@ constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COU
 // workgroup's statistics counters (flushed to ExecArgs::counters at exit),
 // then the current task's six truncation-phase tick counts (trace only)
 // executor LDS: the task arena, the per-workgroup counters, then a copy of
-// the running task's record and its start tick
-constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task) + 8;
+// the running task's record, its start tick and its successor range
+constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task) + 16;
 // words per task of the debug trace: start, end, info, info2, three words of
 // phase ticks (two 32-bit counts each), the tick the task was queued
 constexpr int kTraceWords = 8;

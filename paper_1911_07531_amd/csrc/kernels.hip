@@ -2422,6 +2422,10 @@ __device__ __forceinline__ Task* task_copy(char* lds) { return (Task*)(lds + kLd
 __device__ __forceinline__ uint64_t* task_t0(char* lds) {
   return (uint64_t*)(lds + kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task));
 }
+// the task's successor range [succ_ptr[id], succ_ptr[id + 1]), loaded with the record
+__device__ __forceinline__ int* task_succ(char* lds) {
+  return (int*)(lds + kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task) + 8);
+}
 
 // Runs task id: its record is copied into LDS in one load phase (instead of
 // dependent global loads as its fields are used), then its body runs.  The
@@ -2433,6 +2437,8 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
     const int* src = (const int*)(a.tasks + id);
     int* dst = (int*)lt;
     for (int i = threadIdx.x; i < (int)(sizeof(Task) / 4); i += blockDim.x) dst[i] = src[i];
+    const int w = (int)threadIdx.x - (int)(sizeof(Task) / 4);
+    if (w == 0 || w == 1) task_succ(lds)[w] = a.succ_ptr[id + w];
   }
   if (threadIdx.x == 0 && a.counters) {
     if (a.trace)
@@ -2671,7 +2677,7 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
     if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid < 64) {
-      const int b = a.succ_ptr[t], e = a.succ_ptr[t + 1];
+      const int b = task_succ(lds)[0], e = task_succ(lds)[1];
       bool kept = false;
       for (int k0 = b; k0 < e; k0 += 64) {
         const int k = k0 + tid;
