@@ -1267,25 +1267,6 @@ __device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, i
   }
 }
 
-// Copies rows [r0, r0 + rows) of the stacked panel st (K columns) into buf
-// (column c at buf + c * ld), four columns at a time so that several loads
-// per thread are in flight.
-__device__ __forceinline__ void stage_rows(const ExecArgs& a, const Stack& st, int K, int r0, int rows, double* buf,
-                                           int ld) {
-  for (int c0 = 0; c0 < K; c0 += 4) {
-    ColRef cr[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) cr[u] = stack_col(a, st, min(c0 + u, K - 1));
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
-      double v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = cr[u](r0 + i);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (c0 + u < K) buf[(c0 + u) * ld + i] = v[u];
-    }
-  }
-}
 
 // G = X^T X (K x K, row-major) for X = the stacked panel st (m x K), staged
 // through LDS in chunks of up to `cap_rows` rows.
@@ -1296,11 +1277,8 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* d
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // K*K <= 1024 entries: at most 4 per thread
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    // short chunks: one batch over all columns; tall ones: column groups
-    if (rows <= kThreads)
-      stage_desc(desc, K, r0, rows, buf, ld);
-    else
-      stage_rows(a, st, K, r0, rows, buf, ld);
+    // every chunk in batches of sixteen loads per thread over all columns
+    stage_desc(desc, K, r0, rows, buf, ld);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1470,11 +1448,8 @@ __device__ void rebuild_stream(const ExecArgs& a, const Stack& st, const ColDesc
   const int ld = cap_rows | 1;
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
-    // short chunks: one batch over all columns; tall ones: column groups
-    if (rows <= kThreads)
-      stage_desc(desc, K, r0, rows, buf, ld);
-    else
-      stage_rows(a, st, K, r0, rows, buf, ld);
+    // every chunk in batches of sixteen loads per thread over all columns
+    stage_desc(desc, K, r0, rows, buf, ld);
     __syncthreads();
     for (int e = tid; e < rows * kk; e += blockDim.x) {
       int i = e % rows, c = e / rows;
