@@ -115,3 +115,16 @@ def test_dag_is_forward_and_levels_consistent(prec):
     _, cl, _, bl = t.tables()
     ndiag = sum(1 for b in bl if b[2] == 1 and b[0] == b[1])
     assert len(getrf) == ndiag
+
+
+def test_fused_and_inspection_arguments_rejected(L):
+    """h_lu_solve, hm_dag_calls and hm_semiauto_dag reject bad arguments
+    before touching a device."""
+    h = ctypes.c_void_p()
+    info = ctypes.c_int64(0)
+    opts = hm.make_opts()
+    assert L.h_lu_solve(None, ctypes.byref(opts), None, 1, 1, None, ctypes.byref(h), ctypes.byref(info)) == hm.HM_EINVAL
+    t = hm.Tree(inputs.sphere_points(256, 0), hm.make_opts(leaf=32))
+    assert L.hm_semiauto_dag(t.h, 1, -1, None, None, None, None) == hm.HM_EINVAL
+    assert L.hm_dag_calls(t.h, ctypes.byref(opts), 3, None, None, None) == hm.HM_EINVAL
+    assert L.hm_dag_sizes(t.h, ctypes.byref(opts), 3, np.zeros(10, np.int64).ctypes.data) == hm.HM_EINVAL
