@@ -25,10 +25,10 @@
  *     FP64, column-major with a leading dimension.  Vector arguments are
  *     device pointers owned by the caller, and must stay valid until the
  *     work on `stream` has completed.
- *   - `stream` is a hipStream_t (NULL = default stream).  h_assemble and h_lu
- *     synchronise the stream before returning (they report pivot and rank
- *     status); h_matvec is stream-ordered and asynchronous; h_solve
- *     synchronises only when refinement is requested (it must read residuals).
+ *   - `stream` is a hipStream_t (NULL = default stream).  h_assemble, h_lu
+ *     and h_solve synchronise the stream before returning (they report pivot,
+ *     rank and executor status); h_matvec and h_solve_async are stream-ordered
+ *     and asynchronous.
  *   - Device memory of handles comes from the allocator installed with
  *     hm_set_allocator, else hipMalloc/hipFree.
  *   - Nothing here falls back to the CPU: the compute entry points return
@@ -46,12 +46,13 @@ extern "C" {
 
 typedef enum {
   HM_OK = 0,
-  HM_EINVAL = -1,     /* bad argument: n < 1, leaf < 1, eta <= 0, eps < 0, null pointer, ... */
+  HM_EINVAL = -1,     /* bad argument: n < 1, leaf < 1, eta <= 0, eps < 1e-8, null pointer, ... */
   HM_ENOMEM = -2,     /* host or device allocation failed */
   HM_ESINGULAR = -3,  /* exact zero pivot in a diagonal leaf; *info = permuted global row */
   HM_ENOCONV = -4,    /* refinement did not reach rtol within max_iter */
   HM_EDEVICE = -5,    /* HIP error, no usable device, or executor timeout */
-  HM_ERANK = -6       /* a truncation wanted more than the stored rank capacity (64) */
+  HM_ERANK = -6       /* with max_rank = 0: a truncation wanted more than the stored
+                         rank capacity (64); the result is kept at rank 64 */
 } hm_status;
 
 typedef enum {
@@ -75,7 +76,11 @@ typedef enum {
 typedef struct {
   int leaf;         /* cluster leaf size (Def. 2.1 stop criterion |t| <= leaf) */
   double eta;       /* admissibility parameter, min diam <= eta * dist */
-  double eps;       /* relative truncation accuracy (keep sigma_i > eps sigma_1) */
+  double eps;       /* relative truncation accuracy (keep sigma_i > eps sigma_1,
+                       Sec. 2.1 / 2.3); at least 1e-8: the truncation's FP64
+                       Gram-matrix route resolves directions down to about
+                       sqrt(u) of the largest, so smaller eps (and the exact
+                       case eps = 0) is rejected with HM_EINVAL */
   int max_rank;     /* rank cap, 0 = none (then the capacity 64 bounds it) */
   int prec;         /* hm_precision */
   int exec;         /* hm_exec of the factorization; the substitution DAGs of
@@ -100,7 +105,8 @@ typedef struct {
   int64_t flops_alg;
   double exec_ms;      /* device time of the executor launch(es), HIP events */
   int64_t temp_bytes;  /* temporaries of the traced DAG */
-  int64_t rank_overflows;
+  int64_t rank_overflows; /* truncations whose rank the cap (max_rank, else the
+                             capacity 64) or min(m, n) bounded */
   double op_busy_ms[12];  /* summed workgroup-busy time per task kind (index = task kind) */
   double trunc_phase_ms[12]; /* truncation phases Gram, Cholesky, core, SVD, solve, rebuild:
                                 [0..5] stacked rank <= 32, [6..11] larger */
@@ -151,14 +157,44 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
 hm_status h_lu_solve(hm_matrix A, const hm_opts* opts, double* B, int64_t ldb, int64_t nrhs, void* stream, hm_lu* out,
                      int64_t* info);
 
-/* Solve A X = B in place.  B: device, n x nrhs, column-major, leading
- * dimension ldb >= n.  With A_or_null != NULL the solution is refined with
- * r = b - A_H x (FP64 h_matvec) until every column has ||r|| / ||b|| <= rtol
- * or max_iter corrections were applied (then HM_ENOCONV, X still the last
- * iterate).  iters_host / relres_host (nrhs doubles) may be NULL.  A column's
- * result does not depend on the other columns of the call. */
+/* Solve A X = B in place through the factors: forward and backward block
+ * substitution (not in the paper; the textbook substitution through L and U
+ * of Sec. 2.2's A = LU, with the leaf pivots applied per diagonal leaf).
+ * B: device, n x nrhs, column-major, leading dimension ldb >= n, caller-owned.
+ * With A_or_null != NULL the solution is refined with r = b - A_H x (FP64
+ * h_matvec) until every column has ||r|| / ||b|| <= rtol or max_iter
+ * corrections were applied (then HM_ENOCONV, X still the last iterate).
+ * iters_host (ceil(nrhs / 64) ints: corrections per group of 64 columns) and
+ * relres_host (nrhs doubles: final relative residuals, NaN where no
+ * refinement ran) may be NULL.  A column's result does not depend on the
+ * other columns of the call.  Synchronises `stream`; HM_EDEVICE if the
+ * substitution executor gave up (X is then unspecified).  Allocates the
+ * refinement vectors on the first refined call and keeps them with F. */
 hm_status h_solve(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
                   void* stream, int* iters_host, double* relres_host);
+
+/* The substitution of h_solve without refinement, stream-ordered and
+ * asynchronous (for a serving loop that keeps factors resident and overlaps
+ * requests): returns once the work is queued on `stream`; when it completes,
+ * *status_dev (a device-accessible int32 owned by the caller) holds HM_OK or
+ * HM_EDEVICE (the executor gave up; B unspecified).  Argument errors are
+ * returned directly.  Calls on one F share its substitution workspace and
+ * must be ordered (one stream per F); calls on different factors may overlap. */
+hm_status h_solve_async(hm_lu F, double* B, int64_t ldb, int64_t nrhs, void* stream, int32_t* status_dev);
+
+/* h_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results, but the refinement vectors live in a fixed
+ * 32 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of memory allocated on the first call, and nothing is
+ * allocated.  Refinement runs on chunks of cw columns, the largest cw <= 64
+ * with (2 n cw + 4 cw) doubles <= 32 MiB; HM_EINVAL when even one column does
+ * not fit (n > ~2.1 million).  iters_host (may be NULL) receives one int: the
+ * largest number of corrections of any chunk.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.  Synchronises `stream`. */
+hm_status h_solve_noalloc(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t nrhs, double rtol,
+                          int max_iter, void* stream, int* iters_host, double* relres_host);
 
 /* Y = alpha A_H X + beta Y; X, Y device, n x nrhs column-major. */
 hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, double beta, double* Y, int64_t ldy,

@@ -44,6 +44,8 @@ __global__ void axpy_cols_kernel(double* y, int64_t ldy, const double* x, int64_
                                  const int32_t* active);
 __global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs);
 __global__ void set_i32_kernel(int32_t* p, int32_t v0, int32_t v1, int32_t v2, int32_t v3, int n);
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n);
+__global__ void status_word_kernel(const int32_t* exec_status, int32_t* out);
 }  // namespace hm
 
 using namespace hm;
@@ -327,10 +329,20 @@ static void exec_state_free(ExecState& es) {
 
 enum DagKind { DAG_LU = 0, DAG_SOLVE = 1, DAG_FUSED = 2 };
 
+// Wall-clock ticks a waiting executor workgroup polls an empty queue slot
+// before it raises ST_TIMEOUT and every workgroup leaves: 30 s.
+// HM_DEBUG_SPIN_TICKS overrides it (read at every launch), so that a test can
+// make the bounded wait give up from the host while every kernel still exits
+// normally.
+static int64_t spin_limit_ticks() {
+  if (const char* e = getenv("HM_DEBUG_SPIN_TICKS")) return std::max<int64_t>(0, atoll(e));
+  return g_clock_khz * 1000 * 30;
+}
+
 // Run a DAG on `s`; *ms receives the executor's device time.  The fused DAG
 // always runs on the persistent executor.
 static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, hipStream_t s, float* ms,
-                         int kind = DAG_LU) {
+                         int kind = DAG_LU, bool reset_status = true) {
   const bool solve = kind == DAG_SOLVE;
   if (kind == DAG_FUSED) mode = HM_EXEC_DATAFLOW;
   if (dd.ntasks == 0) {
@@ -356,14 +368,18 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     if (v >= 1 && v < nwg) nwg = v;
   }
   a.nwg = nwg;
-  a.spin_limit = g_clock_khz * 1000 * 30;  // 30 s of wall clock
-  hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
-  HIPCHK(hipMemsetAsync(es.counters.p, 0, kCtrSize * 8, s));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  a.spin_limit = spin_limit_ticks();
+  if (reset_status)
+    hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, s, (int32_t*)es.counters.p, 0, (int64_t)kCtrSize * 2);
+  // events only when the caller asks for the device time
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+  }
   if (mode == HM_EXEC_LEVEL) {
-    HIPCHK(hipEventRecord(e0, s));
+    if (ms) HIPCHK(hipEventRecord(e0, s));
     for (int64_t l = 0; l < dd.nlevels; ++l) {
       int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
       int grid = std::min(e - b, g_nwg);
@@ -375,13 +391,13 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
                            (const int32_t*)dd.order.p, b, e);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(e1, s));
+    if (ms) HIPCHK(hipEventRecord(e1, s));
   } else {
     int rg = (int)std::min<int64_t>(1024, (dd.ntasks + 255) / 256);
     hipLaunchKernelGGL(exec_reset_kernel, dim3(rg), dim3(256), 0, s, a, (const int32_t*)dd.indeg.p,
                        (const int32_t*)dd.roots.p, dd.nroots);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(e0, s));
+    if (ms) HIPCHK(hipEventRecord(e0, s));
     if (solve)
       hipLaunchKernelGGL(solve_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     else if (kind == DAG_FUSED)
@@ -389,14 +405,14 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     else
       hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(e1, s));
+    if (ms) HIPCHK(hipEventRecord(e1, s));
   }
   if (ms) {
     HIPCHK(hipEventSynchronize(e1));
     HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return HM_OK;
 }
 
@@ -414,8 +430,15 @@ static ExecArgs base_args(double* f64, float* f32, int32_t* piv, int32_t* ranks,
   return a;
 }
 
+// Smallest accepted truncation accuracy.  The truncation's R factors come
+// from Cholesky factorizations of FP64 Gram matrices (CholeskyQR), which
+// resolve directions down to about sqrt(u) = 1.5e-8 of the largest column;
+// a smaller eps (and eps = 0, the exact case) would keep ranks the route
+// cannot resolve, so it is rejected.
+constexpr double kMinEps = 1e-8;
+
 static bool valid_opts(const hm_opts* o) {
-  return o && o->leaf >= 1 && o->eta > 0 && o->eps >= 0 && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
+  return o && o->leaf >= 1 && o->eta > 0 && o->eps >= kMinEps && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
          (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL) &&
          (o->lazy == 0 || o->lazy == 1);
 }
@@ -938,9 +961,13 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
     return fail(HM_ESINGULAR, "exact zero pivot in a diagonal leaf");
   }
   *out = F.release();
+  // the columns beyond the fused panel are solved before a rank overflow is
+  // reported, so that every column of B holds the solution either way
+  if (fused && nrhs > nc) {
+    hm_status st2 = h_solve(*out, nullptr, B + (int64_t)nc * ldb, ldb, nrhs - nc, 0.0, 0, stream, nullptr, nullptr);
+    if (st2) return st2;
+  }
   if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "a truncation wanted more than 64 columns");
-  if (fused && nrhs > nc)
-    return h_solve(*out, nullptr, B + (int64_t)nc * ldb, ldb, nrhs - nc, 0.0, 0, stream, nullptr, nullptr);
   return HM_OK;
 }
 
@@ -979,8 +1006,36 @@ hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out) {
   return HM_OK;
 }
 
+// Fixed device scratch of h_solve_noalloc (refinement vectors), so that the
+// entry point allocates nothing.  Each device holds its own copy for the life
+// of the process.  In host code `scratch` names a host-side stand-in, not a
+// device address: kernels and copies take the address hipGetSymbolAddress
+// returns for the current device.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(4) << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;  // device -> device address of `scratch`
+
+static hm_status noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (double*)ptr).first;
+  }
+  *out = it->second;
+  return HM_OK;
+}
+
 // one pass of the traced forward/backward substitution on up to 64 columns in
-// permuted order held in the factor's panel
+// permuted order held in the factor's panel.  The executor status is not
+// reset here: the caller clears it once per call, so that a failure of any
+// pass survives until the call reads it.
 static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
   PlanEntry* pe = F->pe;
   hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)F->ranks.p + pe->plan.nrhs_slot, nc, 0, 0,
@@ -992,36 +1047,44 @@ static hm_status solve_pass(hm_lu F, int nc, hipStream_t s) {
   // per level instead.
   int mode = HM_EXEC_DATAFLOW;
   if (const char* e = getenv("HM_SOLVE_EXEC")) mode = e[0] == 'l' ? HM_EXEC_LEVEL : HM_EXEC_DATAFLOW;
-  return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, DAG_SOLVE);
+  return run_dag(pe->solve, a, F->solve_st, mode, s, nullptr, DAG_SOLVE, false);
 }
 
-hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
-                  void* stream, int* iters_host, double* relres_host) {
-  if (!F || !B) return fail(HM_EINVAL, "null pointer");
+static hm_status solve_status(hm_lu F) {
+  int32_t stv[4];
+  HIPCHK(hipMemcpy(stv, F->solve_st.status.p, 16, hipMemcpyDeviceToHost));
+  if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: a task the executor does not run");
+  return HM_OK;
+}
+
+// Doubles of refinement work for a chunk of cw columns: a copy of b and the
+// residual (n x cw each), norms (2 cw) and active flags (cw int32, rounded up).
+static int64_t solve_work_doubles(int64_t n, int64_t cw) { return 2 * n * cw + 4 * cw; }
+
+// The solve of h_solve, h_solve_async and h_solve_noalloc.  Columns go in
+// chunks of cw <= 64 (each column's result does not depend on the chunk).
+// work: solve_work_doubles(n, cw) doubles of device memory for refinement
+// (unused without A).  With status_dev != NULL nothing synchronises and the
+// executor status is written there stream-ordered instead of being returned.
+static hm_status solve_impl(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                            hipStream_t s, int* iters_host, double* relres_host, int64_t cw, double* work,
+                            int32_t* status_dev, int* iters_max = nullptr) {
   const int64_t n = F->tree->t.n;
-  if (nrhs < 0 || ldb < n || max_iter < 0) return fail(HM_EINVAL, "bad nrhs, ldb or max_iter");
-  if (A && A->tree != F->tree) return fail(HM_EINVAL, "matrix and factors are on different trees");
-  if (nrhs == 0) return HM_OK;
-  hm_status st = device_setup();
-  if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
   const Plan& p = F->pe->plan;
   double* panel = (double*)F->f64.p + p.panel_off;
-  const int64_t CW = p.nrhs_cap;
-  // work: b copy, residual (user order), norms, active flags
-  size_t need = (size_t)(3 * n * CW + 4 * CW) * 8;
-  if (F->work.bytes < need) {
-    HIPCHK(hipStreamSynchronize(s));
-    dev_free(F->work);
-    if (!dev_alloc(F->work, need, s)) return fail(HM_ENOMEM, "device allocation failed (solve work)");
-  }
-  double* bcopy = (double*)F->work.p;
-  double* R = bcopy + n * CW;
-  double* norms = R + n * CW;
-  int32_t* active = (int32_t*)(norms + 2 * CW);
+  hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)F->solve_st.status.p, 0, 0x7fffffff, 0, 0,
+                     4);
+  if (relres_host)
+    for (int64_t c = 0; c < nrhs; ++c) relres_host[c] = std::nan("");
+  double* bcopy = work;
+  double* R = A ? bcopy + n * cw : nullptr;
+  double* norms = A ? R + n * cw : nullptr;
+  int32_t* active = A ? (int32_t*)(norms + 2 * cw) : nullptr;
   bool all_conv = true;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += CW) {
-    const int nc = (int)std::min<int64_t>(CW, nrhs - c0);
+  hm_status st;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += cw) {
+    const int nc = (int)std::min<int64_t>(cw, nrhs - c0);
     double* Bc = B + c0 * ldb;
     const int64_t tot = n * nc;
     const unsigned g = (unsigned)((tot + 255) / 256);
@@ -1034,18 +1097,20 @@ hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, do
                        (const int64_t*)F->perm.p, n, nc, Bc, ldb, 1.0, 0.0);
     HIPCHK(hipGetLastError());
     if (!A) continue;
-    std::vector<double> bn(nc), rn(nc);
-    std::vector<int32_t> act(nc, 1);
+    double bn[64], rn[64];
+    int32_t act[64];
     hipLaunchKernelGGL(colnorm2_kernel, dim3(nc), dim3(kThreads), 0, s, (const double*)bcopy, n, n, norms);
-    HIPCHK(hipMemcpyAsync(bn.data(), norms, nc * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(bn, norms, nc * 8, hipMemcpyDeviceToHost, s));
     int it = 0;
     for (;;) {
       // r = b - A x
       HIPCHK(hipMemcpyAsync(R, bcopy, n * nc * 8, hipMemcpyDeviceToDevice, s));
       if ((st = matvec_impl(A, -1.0, Bc, ldb, 1.0, R, n, nc, s))) return st;
       hipLaunchKernelGGL(colnorm2_kernel, dim3(nc), dim3(kThreads), 0, s, (const double*)R, n, n, norms);
-      HIPCHK(hipMemcpyAsync(rn.data(), norms, nc * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(rn, norms, nc * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      // a failed substitution pass leaves x partly substituted: stop here
+      if ((st = solve_status(F))) return st;
       bool done = true;
       for (int c = 0; c < nc; ++c) {
         double rel = bn[c] > 0 ? std::sqrt(rn[c] / bn[c]) : std::sqrt(rn[c]);
@@ -1059,7 +1124,7 @@ hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, do
         break;
       }
       // x += solve(r) on the columns still above rtol
-      HIPCHK(hipMemcpyAsync(active, act.data(), nc * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(active, act, nc * 4, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, s, (const double*)R, n,
                          (const int64_t*)F->perm.p, n, nc, panel, n);
       if ((st = solve_pass(F, nc, s))) return st;
@@ -1070,16 +1135,85 @@ hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, do
       HIPCHK(hipGetLastError());
       ++it;
     }
-    if (iters_host) iters_host[c0 / CW] = it;
+    if (iters_host) iters_host[c0 / cw] = it;
+    if (iters_max) *iters_max = std::max(*iters_max, it);
   }
-  if (A) {
-    int32_t stv[4];
-    HIPCHK(hipMemcpy(stv, F->solve_st.status.p, 16, hipMemcpyDeviceToHost));
-    if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
-  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: a task the executor does not run");
+  if (status_dev) {
+    hipLaunchKernelGGL(status_word_kernel, dim3(1), dim3(64), 0, s, (const int32_t*)F->solve_st.status.p,
+                       status_dev);
+    HIPCHK(hipGetLastError());
+    return HM_OK;
   }
+  HIPCHK(hipStreamSynchronize(s));
+  if ((st = solve_status(F))) return st;
   if (!all_conv) return fail(HM_ENOCONV, "refinement did not reach rtol");
   return HM_OK;
+}
+
+static hm_status solve_args(hm_lu F, hm_matrix A, const double* B, int64_t ldb, int64_t nrhs, int max_iter) {
+  if (!F || !B) return fail(HM_EINVAL, "null pointer");
+  const int64_t n = F->tree->t.n;
+  if (nrhs < 0 || ldb < n || max_iter < 0) return fail(HM_EINVAL, "bad nrhs, ldb or max_iter");
+  if (A && A->tree != F->tree) return fail(HM_EINVAL, "matrix and factors are on different trees");
+  return HM_OK;
+}
+
+hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                  void* stream, int* iters_host, double* relres_host) {
+  hm_status st = solve_args(F, A, B, ldb, nrhs, max_iter);
+  if (st) return st;
+  if (nrhs == 0) return HM_OK;
+  if ((st = device_setup())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = F->tree->t.n;
+  const int64_t CW = F->pe->plan.nrhs_cap;
+  if (A) {
+    const size_t need = (size_t)solve_work_doubles(n, CW) * 8;
+    if (F->work.bytes < need) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_free(F->work);
+      if (!dev_alloc(F->work, need, s)) return fail(HM_ENOMEM, "device allocation failed (solve work)");
+    }
+  }
+  return solve_impl(F, A, B, ldb, nrhs, rtol, max_iter, s, iters_host, relres_host, CW, (double*)F->work.p,
+                    nullptr);
+}
+
+hm_status h_solve_noalloc(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                          void* stream, int* iters_host, double* relres_host) {
+  hm_status st = solve_args(F, A, B, ldb, nrhs, max_iter);
+  if (st) return st;
+  if (iters_host) *iters_host = 0;
+  if (nrhs == 0) return HM_OK;
+  if ((st = device_setup())) return st;
+  double* work = nullptr;
+  if ((st = noalloc_scratch(&work))) return st;
+  const int64_t n = F->tree->t.n;
+  int64_t cw = F->pe->plan.nrhs_cap;
+  if (A) {
+    while (cw > 0 && solve_work_doubles(n, cw) > kNoAllocScratchDoubles) --cw;
+    if (cw < 1)
+      return fail(HM_EINVAL, "n too large for the fixed scratch of h_solve_noalloc (refinement needs " +
+                                 std::to_string(solve_work_doubles(n, 1) * 8) + " bytes, the scratch holds " +
+                                 std::to_string(kNoAllocScratchDoubles * 8) + ")");
+  }
+  return solve_impl(F, A, B, ldb, nrhs, rtol, max_iter, (hipStream_t)stream, nullptr, relres_host, cw, work,
+                    nullptr, iters_host);
+}
+
+hm_status h_solve_async(hm_lu F, double* B, int64_t ldb, int64_t nrhs, void* stream, int32_t* status_dev) {
+  hm_status st = solve_args(F, nullptr, B, ldb, nrhs, 0);
+  if (st) return st;
+  if (!status_dev) return fail(HM_EINVAL, "null status word");
+  if ((st = device_setup())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (nrhs == 0) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, status_dev, 0, (int64_t)1);
+    HIPCHK(hipGetLastError());
+    return HM_OK;
+  }
+  return solve_impl(F, nullptr, B, ldb, nrhs, 0.0, 0, s, nullptr, nullptr, F->pe->plan.nrhs_cap, nullptr,
+                    status_dev);
 }
 
 hm_status hm_footprint(const void* handle, int kind, size_t* bytes) {

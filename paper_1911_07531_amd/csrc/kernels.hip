@@ -1653,7 +1653,7 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
   int kk = s_int[2];
   const int limit = min(d.cap, min(d.m, d.n));
   if (kk > limit) {
-    if (tid == 0 && a.max_rank == 0) atomicAdd(&a.status[2], 1);
+    if (tid == 0) atomicAdd(&a.status[2], 1);  // the capacity or the cap bound
     kk = limit;
   }
   if (kk == 0) {
@@ -1921,7 +1921,7 @@ __device__ int select_kept(const ExecArgs& a, const LrDesc& d, const double* Bp,
   int kk = s_int[2];
   const int limit = min(d.cap, min(d.m, d.n));
   if (kk > limit) {
-    if (tid == 0 && a.max_rank == 0) atomicAdd(&a.status[2], 1);
+    if (tid == 0) atomicAdd(&a.status[2], 1);  // the capacity or the cap bound
     kk = limit;
   }
   return kk;
@@ -3028,6 +3028,17 @@ __global__ void set_i32_kernel(int32_t* p, int32_t v0, int32_t v1, int32_t v2, i
     if (n > 2) p[2] = v2;
     if (n > 3) p[3] = v3;
   }
+}
+// p[0..n) = v (a fill kernel instead of a memset node, so that the clears
+// stay kernels when a caller captures the stream)
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+// The hm_status of a substitution from the executor's status word: 0, or
+// HM_EDEVICE (-5) after a timeout or an unexpected task.
+__global__ void status_word_kernel(const int32_t* exec_status, int32_t* out) {
+  if (threadIdx.x == 0) out[0] = (exec_status[0] & (ST_TIMEOUT | ST_BADOP)) ? -5 : 0;
 }
 // copy / convert one leaf-block arena region (A layout -> LU layout)
 __global__ void convert_blocks_kernel(const double* src, double* d64, float* d32, const CopyDesc* descs) {

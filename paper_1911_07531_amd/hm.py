@@ -58,7 +58,8 @@ def exported_symbols():
     """Names every build of libhm.so must export (the entry points of include/hm.h)."""
     return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu", "h_lu_solve",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
-            "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error"]
+            "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error",
+            "h_solve_async", "h_solve_noalloc"]
 
 
 def lib():
@@ -85,6 +86,8 @@ def lib():
         "h_lu": [vp, C.POINTER(Opts), vp, C.POINTER(vp), C.POINTER(i64)],
         "h_lu_solve": [vp, C.POINTER(Opts), vp, i64, i64, vp, C.POINTER(vp), C.POINTER(i64)],
         "h_solve": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
+        "h_solve_async": [vp, vp, i64, i64, vp, vp],
+        "h_solve_noalloc": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
         "hm_footprint": [vp, ip, C.POINTER(C.c_size_t)],
         "hm_export_leaf": [vp, ip, i64, vp, C.POINTER(C.c_int32), vp],
@@ -246,7 +249,10 @@ class Matrix:
 
     def __init__(self, tree: Tree, kernel: int, diag: float, opts: Opts, stream=None):
         h = C.c_void_p()
-        _check(lib().h_assemble(tree.h, kernel, diag, C.byref(opts), _stream_ptr(stream), C.byref(h)))
+        code = lib().h_assemble(tree.h, kernel, diag, C.byref(opts), _stream_ptr(stream), C.byref(h))
+        if code == HM_ERANK and h.value:
+            lib().hm_matrix_free(h)
+        _check(code)
         self.h = h
         self.tree = tree
         self.opts = opts
@@ -289,9 +295,9 @@ class LU:
         else:
             bp, ldb, k = _col_major(rhs)
             code = lib().h_lu_solve(a.h, C.byref(opts), bp, ldb, k, _stream_ptr(stream), C.byref(h), C.byref(info))
-        if code != HM_OK and code != HM_ERANK:
-            _check(code, info.value)
-        self.rank_overflow = code == HM_ERANK
+        if code == HM_ERANK and h.value:
+            lib().hm_lu_free(h)  # factors exist, but some block needed more than the capacity
+        _check(code, info.value)
         self.h = h
         self.a = a
         self.tree = a.tree
@@ -313,6 +319,29 @@ class LU:
             return b, iters, rel
         _check(code)
         return b, iters, rel
+
+    def solve_async(self, b, status, stream=None):
+        """Queue the substitution (no refinement) of the (n, nrhs) column-major float64 device
+        tensor b on `stream` (h_solve_async); status (an int32 device tensor) receives the
+        hm_status when the work completes.  Returns b."""
+        import torch
+        if not isinstance(status, torch.Tensor) or not status.is_cuda or status.dtype != torch.int32:
+            raise TypeError("status must be an int32 device tensor")
+        bp, ldb, k = _col_major(b)
+        _check(lib().h_solve_async(self.h, bp, ldb, k, _stream_ptr(stream), C.c_void_p(status.data_ptr())))
+        return b
+
+    def solve_noalloc(self, b, refine_with: Matrix | None = None, rtol=1e-10, max_iter=50, stream=None):
+        """h_solve_noalloc: as solve(), with the refinement vectors in the library's fixed scratch;
+        returns (b, max corrections over the chunks, relres)."""
+        bp, ldb, k = _col_major(b)
+        it = np.zeros(1, np.int32)
+        rel = np.zeros(max(1, k), np.float64)
+        code = lib().h_solve_noalloc(self.h, refine_with.h if refine_with is not None else None, bp, ldb, k, rtol,
+                                     max_iter, _stream_ptr(stream), it.ctypes.data, rel.ctypes.data)
+        if code != HM_ENOCONV:
+            _check(code)
+        return b, int(it[0]), rel
 
     def stats(self) -> dict:
         s = LuStats()

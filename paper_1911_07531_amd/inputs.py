@@ -95,3 +95,113 @@ def line_problem(n: int, seed: int = 0):
     """(points, diag) for the one-dimensional log-kernel workload of size n (no
     random draw: the mesh is uniform; ``seed`` is accepted for a common signature)."""
     return line_points(n), line_self_term(n)
+
+
+# ---------------------------------------------------------------------------
+# Further geometries of the batched workload: the unit-cube surface with the
+# 3D single layer kernel and a uniform grid on the unit square with the 2D
+# logarithmic kernel.  The self term is the kernel at half the mean spacing,
+# as for the sphere.
+# ---------------------------------------------------------------------------
+def cube_side(n: int) -> int:
+    """Grid side s of the cube-surface point set nearest to n points: n is rounded to 6 s^2."""
+    return max(1, int(round(math.sqrt(n / 6.0))))
+
+
+def cube_points(n: int, seed: int = 0, jitter: float = 0.1) -> np.ndarray:
+    """6 s^2 points on the surface of the unit cube [0, 1]^3, s = cube_side(n).
+
+    Each face carries the s x s cell centres of a uniform grid (spacing
+    h = 1/s), moved inside the face by jitter*h*(u1, u2), u ~ U[-1, 1]
+    (PCG64(seed)).  Faces in the order x=0, x=1, y=0, y=1, z=0, z=1; inside a
+    face row-major over its two free coordinates.  Returns (6 s^2, 3) float64.
+    """
+    s = cube_side(n)
+    h = 1.0 / s
+    g = (np.arange(s, dtype=np.float64) + 0.5) * h
+    a, b = np.meshgrid(g, g, indexing="ij")
+    a, b = a.ravel(), b.ravel()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    faces = []
+    for axis in range(3):
+        free = [d for d in range(3) if d != axis]
+        for val in (0.0, 1.0):
+            u = rng.uniform(-1.0, 1.0, size=(s * s, 2))
+            p = np.empty((s * s, 3))
+            p[:, axis] = val
+            p[:, free[0]] = a + jitter * h * u[:, 0]
+            p[:, free[1]] = b + jitter * h * u[:, 1]
+            faces.append(p)
+    return np.ascontiguousarray(np.concatenate(faces))
+
+
+def cube_self_term(n: int) -> float:
+    """a_ii = 2 / (4 pi h) with h = 1/s = sqrt(6 / n_actual): the kernel 1/(4 pi r) at r = h/2."""
+    return 2.0 / (4.0 * math.pi * (1.0 / cube_side(n)))
+
+
+def grid_side(n: int) -> int:
+    """Side s of the square grid nearest to n points: n is rounded to s^2."""
+    return max(1, int(round(math.sqrt(n))))
+
+
+def grid_points(n: int) -> np.ndarray:
+    """The s x s cell centres ((i + 1/2)/s, (j + 1/2)/s) of the unit square, s = grid_side(n),
+    row-major in i; returned as an (s^2, 2) float64 array (no random draw)."""
+    s = grid_side(n)
+    g = (np.arange(s, dtype=np.float64) + 0.5) / s
+    a, b = np.meshgrid(g, g, indexing="ij")
+    return np.ascontiguousarray(np.stack([a.ravel(), b.ravel()], axis=1))
+
+
+def grid_self_term(n: int) -> float:
+    """a_ii = -log(h/2) / (2 pi) with h = 1/s: the kernel -log r / (2 pi) at r = h/2."""
+    h = 1.0 / grid_side(n)
+    return -math.log(0.5 * h) / (2.0 * math.pi)
+
+
+def cube_problem(n: int, seed: int = 0):
+    """(points, diag) for the cube-surface single-layer workload (about n points)."""
+    return cube_points(n, seed), cube_self_term(n)
+
+
+def grid_problem(n: int, seed: int = 0):
+    """(points, diag) for the 2D logarithmic-kernel grid workload (about n points; no random draw)."""
+    return grid_points(n), grid_self_term(n)
+
+
+GEOMETRIES = ("sphere", "cube", "grid")
+# the kernel each geometry is assembled with: "laplace3d" = 1/(4 pi r), "log2d" = -log(r)/(2 pi)
+GEOMETRY_KERNEL = {"sphere": "laplace3d", "cube": "laplace3d", "grid": "log2d", "line": "log2d"}
+
+
+def problem(geometry: str, n: int, seed: int = 0):
+    """(points, diag) of a named geometry: sphere, cube, grid or line."""
+    if geometry == "sphere":
+        return sphere_problem(n, seed)
+    if geometry == "cube":
+        return cube_problem(n, seed)
+    if geometry == "grid":
+        return grid_problem(n, seed)
+    if geometry == "line":
+        return line_problem(n, seed)
+    raise ValueError(f"unknown geometry {geometry!r}")
+
+
+def batched_instances(count: int = 64, n_lo: int = 4096, n_hi: int = 65536, seed0: int = 100):
+    """The batched workload: instance i draws, from PCG64(seed0 + i), its size
+    n = round(exp(U[ln n_lo, ln n_hi])) and its leaf size from {32, 64, 128};
+    its geometry is GEOMETRIES[i mod 3] (the cube and grid round n to their
+    lattices).  Returns a list of dicts (geometry, kernel, n, leaf, seed)."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed0 + i))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        leaf = int((32, 64, 128)[int(rng.integers(0, 3))])
+        geo = GEOMETRIES[i % 3]
+        if geo == "cube":
+            n = 6 * cube_side(n) ** 2
+        elif geo == "grid":
+            n = grid_side(n) ** 2
+        out.append(dict(geometry=geo, kernel=GEOMETRY_KERNEL[geo], n=n, leaf=leaf, seed=seed0 + i))
+    return out

@@ -128,3 +128,24 @@ def test_fused_and_inspection_arguments_rejected(L):
     assert L.hm_semiauto_dag(t.h, 1, -1, None, None, None, None) == hm.HM_EINVAL
     assert L.hm_dag_calls(t.h, ctypes.byref(opts), 3, None, None, None) == hm.HM_EINVAL
     assert L.hm_dag_sizes(t.h, ctypes.byref(opts), 3, np.zeros(10, np.int64).ctypes.data) == hm.HM_EINVAL
+
+
+def test_eps_below_the_truncation_route_rejected(L):
+    """eps < 1e-8 (including the exact case eps = 0) is refused before any
+    device work: the truncation's CholeskyQR resolves directions only down to
+    about sqrt(u) of the largest."""
+    t = hm.Tree(inputs.sphere_points(256, 0), hm.make_opts(leaf=32))
+    h = ctypes.c_void_p()
+    for eps in (0.0, 1e-10, 9.9e-9, -1.0):
+        opts = hm.make_opts(leaf=32, eps=eps)
+        assert L.h_assemble(t.h, hm.LAPLACE3D, 1.0, ctypes.byref(opts), None, ctypes.byref(h)) == hm.HM_EINVAL
+        assert L.h_lu(None, ctypes.byref(opts), None, ctypes.byref(h), None) == hm.HM_EINVAL
+
+
+def test_solve_variants_reject_bad_arguments(L):
+    """h_solve, h_solve_async and h_solve_noalloc check their arguments before
+    touching a device."""
+    st = ctypes.c_int32(0)
+    assert L.h_solve(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
+    assert L.h_solve_async(None, None, 1, 1, None, ctypes.byref(st)) == hm.HM_EINVAL
+    assert L.h_solve_noalloc(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
