@@ -354,6 +354,34 @@ class Tracer {
     h.tr = !x.tr;
     return h;
   }
+  // Columns [a, b) of a view with a static column count.  A column slice of
+  // an identity is materialised: an m x (b - a) temporary with ones at
+  // (a + j, j).
+  HView cols(const HView& x, int32_t a, int32_t b) {
+    if (x.v.dyn & DYN_COLS) fail("column slice of a view with a run-time column count");
+    if (x.v.type == VT_IDENT) {
+      HView z = temp(x.v.rows, b - a, -1);
+      zero(z);
+      HView zr = rows(z, a, b);
+      HView e = ident(b - a);
+      Task t = blank(OP_COPY);
+      t.y = zr.v;
+      t.a = e.v;
+      emit(t, {{&zr, ACC_W}});
+      return z;
+    }
+    HView h = x;
+    h.v.off = x.v.off + (int64_t)a * x.v.cs;
+    h.v.cols = b - a;
+    if (!x.tr) {
+      h.rect.c0 = x.rect.c0 + a;
+      h.rect.c1 = x.rect.c0 + b;
+    } else {
+      h.rect.r0 = x.rect.r0 + a;
+      h.rect.r1 = x.rect.r0 + b;
+    }
+    return h;
+  }
   HView rows(const HView& x, int32_t a, int32_t b) {
     if (x.v.dyn & DYN_ROWS) fail("row slice of a view with a run-time row count");
     HView h = x;
@@ -773,6 +801,22 @@ class Tracer {
 
   void add_term_to_leaf(int c, const Term& tm) {
     const BlockNode& C = t_.bl[c];
+    // A term wider than half the stacked-rank limit (a dense-dense product
+    // over an inner leaf of more than 64 points, or an identity factor of
+    // such a leaf) is added as column chunks of at most 64, so that a
+    // truncation never stacks more than 128 columns.
+    constexpr int32_t kChunk = kMaxK / 2;
+    if (C.kind == BK_LOWRANK && tm.u.v.cols > kChunk) {
+      const int32_t k = tm.u.v.cols;
+      for (int32_t j0 = 0; j0 < k; j0 += kChunk) {
+        const int32_t j1 = std::min(k, j0 + kChunk);
+        Term part = tm;
+        part.u = cols(tm.u, j0, j1);
+        part.v = cols(tm.v, j0, j1);
+        add_term_to_leaf(c, part);
+      }
+      return;
+    }
     if (C.kind == BK_LOWRANK && lazy_ && scope_ > 0) {
       pin(tm.u, 1);
       pin(tm.v, 1);

@@ -29,17 +29,17 @@ class Problem:
     """A workload on both sides: the oracle's tree/assembly and the GPU's.
 
     geometry "sphere": the single layer potential on the sphere; "line": the
-    one-dimensional log-kernel model problem on [0, 1]."""
+    one-dimensional log-kernel model problem on [0, 1]; "cube": the single
+    layer kernel on the unit cube's surface; "grid": the 2D logarithmic
+    kernel on a uniform grid of the unit square (n rounded to the lattice)."""
 
     def __init__(self, n, leaf, eps, max_rank=0, eta=2.0, seed=0, prec=hm.FP64, exec_mode=hm.DATAFLOW,
                  oracle=True, geometry="sphere"):
         self.n, self.leaf, self.eps, self.max_rank = n, leaf, eps, max_rank
-        if geometry == "sphere":
-            self.pts, self.diag = inputs.sphere_problem(n, seed)
-            self.kernel, self.kname = hm.LAPLACE3D, "laplace3d"
-        else:
-            self.pts, self.diag = inputs.line_problem(n)
-            self.kernel, self.kname = hm.LOG2D, "log2d"
+        self.pts, self.diag = inputs.problem(geometry, n, seed)
+        self.kname = inputs.GEOMETRY_KERNEL[geometry]
+        self.kernel = hm.LAPLACE3D if self.kname == "laplace3d" else hm.LOG2D
+        n = self.n = len(self.pts)
         self.opts = hm.make_opts(leaf=leaf, eta=eta, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode)
         self.tree = hm.Tree(self.pts, self.opts)
         self.A = hm.Matrix(self.tree, self.kernel, self.diag, self.opts)

@@ -193,3 +193,25 @@ def test_fused_lu_solve_dag(lazy):
             assert np.allclose(x, H.solve(f, b), rtol=0, atol=1e-9 * np.abs(x).max())
         else:
             assert np.allclose(x, ref_x, rtol=0, atol=1e-9 * np.abs(ref_x).max())
+
+
+@pytest.mark.parametrize("lazy", [0, 1])
+def test_replay_leaf_128_within_bounds(lazy):
+    """Leaves of up to 128 points: dense-dense products over an inner leaf of
+    more than 64 points (and identity factors of such leaves) reach a
+    low-rank leaf as column chunks of at most 64, each truncated; the replay
+    stays within the parity bounds of the oracle (10 eps, ranks +-2)."""
+    n, leaf, eps = 1024, 128, 1e-6
+    t, opts, a = _setup(n, leaf, 2.0, eps, 0, lazy=lazy)
+    dag = t.dag(opts, 0)
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    rp = Replay(dag, eps, 0)
+    rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+    rp.run(np.random.default_rng(21))
+    f = _factors_from_replay(rp, t, a, dag)
+    pts, diag = inputs.sphere_problem(n, 0)
+    dense = H.kernel_block(pts, a.perm, a.clusters[0], a.clusters[0], diag)
+    assert H.lu_error_2norm(dense, f, exact=True) <= 10 * eps
+    ref = H.hlu(a, lazy=bool(lazy))
+    rr, rg = H.rank_table(ref), H.rank_table(f)
+    assert max(abs(rg[i] - rr[i]) for i in rr) <= 2

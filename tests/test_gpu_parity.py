@@ -284,3 +284,140 @@ def test_assembly_reproducible():
     for bi in np.nonzero(bl[:, 2] == 2)[0]:
         r = [m.leaf(int(bi)) for m in mats]
         assert all(np.array_equal(r[0][1], q[1]) and np.array_equal(r[0][2], q[2]) for q in r[1:]), bi
+
+
+def test_fused_lu_solve_against_oracle_c1(c1):
+    """h_lu_solve (H-LU and substitution in one DAG) against the oracle: the
+    unrefined solve residuals against the exact matrix are at most 2x the
+    oracle's, for 16 right-hand sides."""
+    p, _, of = c1
+    b = inputs.rhs(p.n, 16, seed=1)
+    xd = device_rhs(b)
+    hm.LU(p.A, p.opts, rhs=xd)
+    xg = to_host(xd)
+    xo = H.solve(of, b)
+    dense = p.dense_exact()
+    a_user = np.empty_like(dense)
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = dense
+    rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
+    ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    print("fused residual gpu / oracle", rg.max(), ro.max())
+    assert np.all(rg <= 2 * ro + 1e-12)
+
+
+def test_executor_wait_limit_reported(monkeypatch):
+    """The persistent executors' bounded wait: with a wait limit of zero ticks
+    (set from the host) a workgroup that finds its queue slot empty gives up,
+    raises the abort flag, and every workgroup leaves normally; h_lu and
+    h_solve report HM_EDEVICE, and the next calls with the normal limit
+    succeed on the same handles."""
+    p = Problem(1024, 32, 1e-6, oracle=False)
+    f = hm.LU(p.A, p.opts)
+    b = inputs.rhs(p.n, 3, seed=2)
+    ref = to_host(f.solve(device_rhs(b))[0])
+    monkeypatch.setenv("HM_DEBUG_SPIN_TICKS", "0")
+    with pytest.raises(hm.HmError) as ei:
+        hm.LU(p.A, p.opts)
+    assert ei.value.code == hm.HM_EDEVICE and "timed out" in str(ei.value)
+    with pytest.raises(hm.HmError) as ei:
+        f.solve(device_rhs(b))
+    assert ei.value.code == hm.HM_EDEVICE
+    with pytest.raises(hm.HmError) as ei:
+        f.solve(device_rhs(b), refine_with=p.A)
+    assert ei.value.code == hm.HM_EDEVICE
+    monkeypatch.delenv("HM_DEBUG_SPIN_TICKS")
+    g = hm.LU(p.A, p.opts)
+    assert np.array_equal(to_host(g.solve(device_rhs(b))[0]), ref)
+    assert np.array_equal(to_host(f.solve(device_rhs(b))[0]), ref)
+
+
+def test_solve_async_equals_solve(monkeypatch):
+    """h_solve_async queues the substitution and reports through a device
+    word: the same solution as h_solve, bit for bit, and status 0; with the
+    wait limit forced to zero the word reads HM_EDEVICE."""
+    import torch
+    p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False, prec=hm.MIXED)
+    f = hm.LU(p.A, p.opts)
+    b = inputs.rhs(p.n, 70, seed=9)
+    x1 = to_host(f.solve(device_rhs(b))[0])
+    st = torch.full((1,), 123, dtype=torch.int32, device="cuda")
+    xd = device_rhs(b)
+    f.solve_async(xd, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == hm.HM_OK
+    assert np.array_equal(to_host(xd), x1)
+    monkeypatch.setenv("HM_DEBUG_SPIN_TICKS", "0")
+    st.fill_(123)
+    f.solve_async(device_rhs(b), st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == hm.HM_EDEVICE
+    monkeypatch.delenv("HM_DEBUG_SPIN_TICKS")
+    xd = device_rhs(b)
+    f.solve_async(xd, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == hm.HM_OK and np.array_equal(to_host(xd), x1)
+
+
+def test_leaf_128_against_oracle():
+    """Leaves of up to 128 points (the batched workload's largest): diagonal
+    leaves of 65-128 rows take the getrf path in global memory (m > 97) and
+    the two-rows-per-lane triangular solves; dense-dense products over such
+    leaves reach low-rank targets in column chunks.  Bounds as for c1."""
+    p = Problem(4096, 128, 1e-6)
+    f = hm.LU(p.A, p.opts)
+    of = H.hlu(p.oa, lazy=True)
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    err = H.lu_error_2norm(dense, gf, exact=False)
+    assert err <= 10 * p.eps, err
+    orank, grank = H.rank_table(of), H.rank_table(gf)
+    assert max(abs(grank[k] - orank[k]) for k in orank) <= 2
+    # the diagonal leaves of 98-128 rows: interchanges bit-exact against LAPACK on the assembled block
+    _, cl, _, bl = p.tree.tables()
+    big = [i for i in range(len(bl)) if bl[i, 2] == 1 and bl[i, 0] == bl[i, 1] and cl[bl[i, 0], 1] - cl[bl[i, 0], 0] > 97]
+    assert big, "no diagonal leaf above 97 rows"
+    b = inputs.rhs(p.n, 8, seed=1)
+    xg = to_host(f.solve(device_rhs(b))[0])
+    xo = H.solve(of, b)
+    a_user = np.empty_like(dense)
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = dense
+    rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
+    ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rg <= 2 * ro + 1e-12), (rg, ro)
+
+
+def test_getrf_leaf_above_97_rows_bit_exact_pivots():
+    """A single diagonal leaf of 120 points (the global-memory getrf path):
+    interchanges bit-exact against LAPACK, values to rounding."""
+    p = Problem(120, 128, 1e-6, oracle=False)
+    f = hm.LU(p.A, p.opts)
+    kind, a, _ = p.A.leaf(0)
+    kind, lu, piv = f.leaf(0)
+    lu_ref, piv_ref = sla.lu_factor(a)
+    assert np.array_equal(piv, piv_ref)
+    assert np.max(np.abs(lu - lu_ref)) <= 1e-13 * np.abs(a).max() * 120
+
+
+@pytest.mark.parametrize("geometry,n,leaf", [("cube", 2400, 32), ("grid", 2048, 64)])
+def test_batched_geometries_against_oracle(geometry, n, leaf):
+    """The batched workload's other geometries (unit-cube surface with
+    1/(4 pi r), unit-square grid with -log r/(2 pi)), mixed precision at
+    eps = 1e-4, ranks capped at 64: ||PA - LU||_2/||A||_2 <= 10 eps, ranks
+    within +-2 of the FP64 oracle's, solve residuals <= 2x the oracle's."""
+    p = Problem(n, leaf, 1e-4, max_rank=64, prec=hm.MIXED, geometry=geometry)
+    f = hm.LU(p.A, p.opts)
+    of = H.hlu(p.oa, lazy=True)
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    err = H.lu_error_2norm(dense, gf, exact=True)
+    assert err <= 10 * p.eps, err
+    orank, grank = H.rank_table(of), H.rank_table(gf)
+    assert max(abs(grank[k] - orank[k]) for k in orank) <= 2
+    b = inputs.rhs(p.n, 8, seed=1)
+    xg = to_host(f.solve(device_rhs(b))[0])
+    xo = H.solve(of, b)
+    a_user = np.empty_like(dense)
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = dense
+    rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
+    ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rg <= 2 * ro + 1e-12), (rg, ro)
