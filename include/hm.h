@@ -182,6 +182,20 @@ hm_status h_solve(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t 
  * must be ordered (one stream per F); calls on different factors may overlap. */
 hm_status h_solve_async(hm_lu F, double* B, int64_t ldb, int64_t nrhs, void* stream, int32_t* status_dev);
 
+/* h_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results, but the refinement vectors live in a fixed
+ * 32 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of memory allocated on the first call, and nothing is
+ * allocated.  Refinement runs on chunks of cw columns, the largest cw <= 64
+ * with (2 n cw + 4 cw) doubles <= 32 MiB; HM_EINVAL when even one column does
+ * not fit (n > ~2.1 million).  iters_host (may be NULL) receives one int: the
+ * largest number of corrections of any chunk.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.  Synchronises `stream`. */
+hm_status h_solve_noalloc(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t nrhs, double rtol,
+                          int max_iter, void* stream, int* iters_host, double* relres_host);
+
 /* Y = alpha A_H X + beta Y; X, Y device, n x nrhs column-major. */
 hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, double beta, double* Y, int64_t ldy,
                    int64_t nrhs, void* stream);

@@ -1006,6 +1006,32 @@ hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out) {
   return HM_OK;
 }
 
+// Fixed device scratch of h_solve_noalloc (refinement vectors), so that the
+// entry point allocates nothing.  Each device holds its own copy for the life
+// of the process.  In host code `scratch` names a host-side stand-in, not a
+// device address: kernels and copies take the address hipGetSymbolAddress
+// returns for the current device.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(4) << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;  // device -> device address of `scratch`
+
+static hm_status noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (double*)ptr).first;
+  }
+  *out = it->second;
+  return HM_OK;
+}
+
 // one pass of the traced forward/backward substitution on up to 64 columns in
 // permuted order held in the factor's panel.  The executor status is not
 // reset here: the caller clears it once per call, so that a failure of any
@@ -1036,7 +1062,7 @@ static hm_status solve_status(hm_lu F) {
 // residual (n x cw each), norms (2 cw) and active flags (cw int32, rounded up).
 static int64_t solve_work_doubles(int64_t n, int64_t cw) { return 2 * n * cw + 4 * cw; }
 
-// The solve of h_solve and h_solve_async.  Columns go in
+// The solve of h_solve, h_solve_async and h_solve_noalloc.  Columns go in
 // chunks of cw <= 64 (each column's result does not depend on the chunk).
 // work: solve_work_doubles(n, cw) doubles of device memory for refinement
 // (unused without A).  With status_dev != NULL nothing synchronises and the
@@ -1151,6 +1177,28 @@ hm_status h_solve(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, do
   }
   return solve_impl(F, A, B, ldb, nrhs, rtol, max_iter, s, iters_host, relres_host, CW, (double*)F->work.p,
                     nullptr);
+}
+
+hm_status h_solve_noalloc(hm_lu F, hm_matrix A, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
+                          void* stream, int* iters_host, double* relres_host) {
+  hm_status st = solve_args(F, A, B, ldb, nrhs, max_iter);
+  if (st) return st;
+  if (iters_host) *iters_host = 0;
+  if (nrhs == 0) return HM_OK;
+  if ((st = device_setup())) return st;
+  double* work = nullptr;
+  if ((st = noalloc_scratch(&work))) return st;
+  const int64_t n = F->tree->t.n;
+  int64_t cw = F->pe->plan.nrhs_cap;
+  if (A) {
+    while (cw > 0 && solve_work_doubles(n, cw) > kNoAllocScratchDoubles) --cw;
+    if (cw < 1)
+      return fail(HM_EINVAL, "n too large for the fixed scratch of h_solve_noalloc (refinement needs " +
+                                 std::to_string(solve_work_doubles(n, 1) * 8) + " bytes, the scratch holds " +
+                                 std::to_string(kNoAllocScratchDoubles * 8) + ")");
+  }
+  return solve_impl(F, A, B, ldb, nrhs, rtol, max_iter, (hipStream_t)stream, nullptr, relres_host, cw, work,
+                    nullptr, iters_host);
 }
 
 hm_status h_solve_async(hm_lu F, double* B, int64_t ldb, int64_t nrhs, void* stream, int32_t* status_dev) {

@@ -59,7 +59,7 @@ def exported_symbols():
     return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu", "h_lu_solve",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
             "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error",
-            "h_solve_async"]
+            "h_solve_async", "h_solve_noalloc"]
 
 
 def lib():
@@ -87,6 +87,7 @@ def lib():
         "h_lu_solve": [vp, C.POINTER(Opts), vp, i64, i64, vp, C.POINTER(vp), C.POINTER(i64)],
         "h_solve": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_solve_async": [vp, vp, i64, i64, vp, vp],
+        "h_solve_noalloc": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
         "hm_footprint": [vp, ip, C.POINTER(C.c_size_t)],
         "hm_export_leaf": [vp, ip, i64, vp, C.POINTER(C.c_int32), vp],
@@ -329,6 +330,18 @@ class LU:
         bp, ldb, k = _col_major(b)
         _check(lib().h_solve_async(self.h, bp, ldb, k, _stream_ptr(stream), C.c_void_p(status.data_ptr())))
         return b
+
+    def solve_noalloc(self, b, refine_with: Matrix | None = None, rtol=1e-10, max_iter=50, stream=None):
+        """h_solve_noalloc: as solve(), with the refinement vectors in the library's fixed scratch;
+        returns (b, max corrections over the chunks, relres)."""
+        bp, ldb, k = _col_major(b)
+        it = np.zeros(1, np.int32)
+        rel = np.zeros(max(1, k), np.float64)
+        code = lib().h_solve_noalloc(self.h, refine_with.h if refine_with is not None else None, bp, ldb, k, rtol,
+                                     max_iter, _stream_ptr(stream), it.ctypes.data, rel.ctypes.data)
+        if code != HM_ENOCONV:
+            _check(code)
+        return b, int(it[0]), rel
 
     def stats(self) -> dict:
         s = LuStats()

@@ -143,8 +143,9 @@ def test_eps_below_the_truncation_route_rejected(L):
 
 
 def test_solve_variants_reject_bad_arguments(L):
-    """h_solve and h_solve_async check their arguments before
+    """h_solve, h_solve_async and h_solve_noalloc check their arguments before
     touching a device."""
     st = ctypes.c_int32(0)
     assert L.h_solve(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
     assert L.h_solve_async(None, None, 1, 1, None, ctypes.byref(st)) == hm.HM_EINVAL
+    assert L.h_solve_noalloc(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
