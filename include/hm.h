@@ -113,6 +113,23 @@ typedef struct {
   double trunc_mean_k, trunc_mean_mn; /* mean stacked rank K and mean m + n of truncations */
 } hm_lu_stats;
 
+/* Launch choices of the executors, set by the autotuner of the Python package
+ * (paper_1911_07531_amd/autotune.py) from timed candidates, process-wide.
+ *   exec_wg_per_cu  workgroups per compute unit of the H-LU executors (1 or
+ *                   2; 0 = as many as fit, which is 2)
+ *   solve_wg        workgroups of the persistent substitution executor
+ *                   (default 128, or HM_SOLVE_NWG)
+ *   batch_order     h_lu_batched queue order of the instances' first tasks:
+ *                   0 as given, 1 the instances with the most tasks first */
+typedef struct {
+  int exec_wg_per_cu;
+  int solve_wg;
+  int batch_order;
+  int reserved[5];
+} hm_tuning;
+hm_status hm_get_tuning(hm_tuning* out);
+hm_status hm_set_tuning(const hm_tuning* t); /* HM_EINVAL when a field is out of range */
+
 /* Device allocator hook; ctx is passed back.  Both may be NULL to restore
  * hipMalloc/hipFree. */
 hm_status hm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
@@ -156,6 +173,37 @@ hm_status h_lu(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* out, int64
  * is ignored (always the persistent executor).  Synchronises `stream`. */
 hm_status h_lu_solve(hm_matrix A, const hm_opts* opts, double* B, int64_t ldb, int64_t nrhs, void* stream, hm_lu* out,
                      int64_t* info);
+
+/* H-LU (Algorithm 2) of `count` independent H-matrices (each on its own tree,
+ * of any size, geometry and leaf size) as one task DAG on one launch: each
+ * matrix's traced DAG (Sec. 3) is relocated into one factor arena and the
+ * union runs on the persistent executor (opts->exec = HM_EXEC_DATAFLOW) or
+ * one launch per DAG level across all matrices (HM_EXEC_LEVEL), so that
+ * small and large factorizations fill the GPU together.  opts (eps, max_rank,
+ * prec, lazy) apply to every matrix; each A_i must have been assembled with
+ * opts->max_rank.  outs: count handles, each as from h_lu (their factors
+ * share one device allocation, released with the last of them; the same
+ * factors as h_lu of that matrix alone).  infos (may be NULL): count int64,
+ * all 0; on HM_ESINGULAR the permuted row of the first exact zero pivot at
+ * the instance that has it and -1 at every other (all outs NULL then).  The temporaries of the batch
+ * span HM_BATCH_TEMP_GB GiB (default 16) shared in proportion to n.
+ * hm_lu_stats of every handle describe the whole batch launch.
+ * Synchronises `stream`. */
+hm_status h_lu_batched(const hm_matrix* As, int count, const hm_opts* opts, void* stream, hm_lu* outs,
+                       int64_t* infos);
+
+/* The combined DAG of h_lu_batched over `count` trees (host only, for
+ * inspection and tests; the plans are traced as h_lu_batched traces them).
+ * sizes (7 int64): ntasks, nedges, nlevels, FP64 / FP32 / pivot arena
+ * elements, rank slots.  Any other output may be NULL: tasks (ntasks
+ * records), succ_ptr (ntasks + 1), succ_idx (nedges), order (ntasks, level
+ * order), level_ptr (nlevels + 1), lr (rank slots x 6 int64: u_off, v_off,
+ * m, n, cap, type; zeros at the slots of a solve's column count), bases
+ * (count x 8 int64: FP64, FP32 and pivot arena bases, first rank slot,
+ * first row, first task, first edge, tasks of the instance). */
+hm_status hm_batch_dag_export(const hm_tree* trees, int count, const hm_opts* opts, int64_t* sizes, void* tasks,
+                              int32_t* succ_ptr, int32_t* succ_idx, int32_t* order, int32_t* level_ptr, int64_t* lr,
+                              int64_t* bases);
 
 /* Solve A X = B in place through the factors: forward and backward block
  * substitution (not in the paper; the textbook substitution through L and U

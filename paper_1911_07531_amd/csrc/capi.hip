@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
@@ -11,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -74,6 +76,7 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipStream_t stream = nullptr;
+  bool owned = true;  // false: a slice of another allocation (batched factors)
 };
 
 // HM_DEBUG_POISON=1 fills every new allocation with all-ones bytes (NaN for
@@ -105,6 +108,11 @@ static bool dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
 
 static void dev_free(DevBuf& b) {
   if (!b.p) return;
+  if (!b.owned) {
+    b.p = nullptr;
+    b.bytes = 0;
+    return;
+  }
   if (g_dealloc)
     g_dealloc(b.p, b.bytes, (void*)b.stream, g_alloc_ctx);
   else
@@ -139,7 +147,7 @@ struct DevDag {
 struct PlanEntry {
   Plan plan;
   bool traced = false;
-  bool uploaded = false;
+  bool uploaded = false, solve_uploaded = false;
   bool fused_traced = false, fused_uploaded = false;
   DevDag lu, solve, fused;
   DevBuf lr;
@@ -149,7 +157,8 @@ struct PlanEntry {
 struct hm_tree_s {
   Tree t;
   hm_opts opts;
-  std::map<std::tuple<int, int, int>, std::unique_ptr<PlanEntry>> plans;  // (prec, max_rank, lazy)
+  // (prec, max_rank, lazy, span of the temporaries in MiB)
+  std::map<std::tuple<int, int, int, int64_t>, std::unique_ptr<PlanEntry>> plans;
   std::mutex mu;
   std::vector<int64_t> leaf_begin;  // leaf clusters in order
   std::vector<int32_t> leaf_size;
@@ -188,10 +197,24 @@ struct hm_lu_s {
   DevBuf work;  // solve/refinement vectors
   size_t work_cols = 0;
   hm_lu_stats stats;
+  // factors of h_lu_batched: f64 / f32 / piv / ranks are slices of one
+  // allocation shared by the batch, released with its last handle
+  std::shared_ptr<void> arena;
 };
 
-static int g_nwg = 0;
+static int g_nwg = 0;      // executor workgroups at full occupancy (scratch is sized for these)
+static int g_cus = 0;
 static int64_t g_clock_khz = 0;
+// Launch choices that the autotuner sets (hm_set_tuning); environment
+// variables give the defaults.
+static hm_tuning g_tuning = {0, 128, 0, {0, 0, 0, 0, 0}};
+
+// Workgroups of an H-LU executor launch under the current tuning.
+static int exec_workgroups() {
+  if (g_tuning.exec_wg_per_cu <= 0 || g_cus <= 0) return g_nwg;
+  return std::max(1, std::min(g_nwg, g_cus * g_tuning.exec_wg_per_cu));
+}
+static void batch_cache_drop(hm_tree t);
 
 static hm_status device_setup() {
   if (g_nwg > 0) return HM_OK;
@@ -220,6 +243,8 @@ static hm_status device_setup() {
       per_cu < 1)
     per_cu = 1;
   g_nwg = cus * per_cu;
+  g_cus = cus;
+  if (const char* e = getenv("HM_SOLVE_NWG")) g_tuning.solve_wg = std::max(1, atoi(e));
   // HM_DEBUG_MAX_WG caps the executor workgroups (1 = one task at a time)
   if (const char* e = getenv("HM_DEBUG_MAX_WG")) {
     int v = atoi(e);
@@ -251,9 +276,11 @@ static int32_t solve_split_rows() {
   return v;
 }
 
-static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out) {
+static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out,
+                          int64_t budget = -1) {
+  if (budget < 0) budget = temp_budget();
   std::lock_guard<std::mutex> lk(t->mu);
-  auto key = std::make_tuple(prec, max_rank, lazy);
+  auto key = std::make_tuple(prec, max_rank, lazy, budget >> 20);
   auto it = t->plans.find(key);
   PlanEntry* pe;
   if (it == t->plans.end()) {
@@ -265,7 +292,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
     pe = it->second.get();
   }
   if (need_trace && !pe->traced) {
-    if (!trace_lu(pe->plan, temp_budget(), lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_lu(pe->plan, budget, lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
     if (!trace_solve(pe->plan, solve_split_rows())) return fail(HM_EINVAL, pe->plan.err);
     pe->traced = true;
   }
@@ -299,12 +326,23 @@ static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
   return HM_OK;
 }
 
-static hm_status ensure_uploaded(PlanEntry* pe, hipStream_t s) {
-  if (pe->uploaded) return HM_OK;
+// The substitution DAG and the low-rank descriptors of a plan on the device
+// (what a solve on its factors needs).
+static hm_status ensure_solve_uploaded(PlanEntry* pe, hipStream_t s) {
+  if (pe->solve_uploaded) return HM_OK;
   hm_status st;
-  if ((st = upload_dag(pe->plan.lu, pe->lu, s))) return st;
   if ((st = upload_dag(pe->plan.solve, pe->solve, s))) return st;
   if ((st = upload(pe->lr, pe->plan.lr, s))) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  pe->solve_uploaded = true;
+  return HM_OK;
+}
+
+static hm_status ensure_uploaded(PlanEntry* pe, hipStream_t s) {
+  hm_status st;
+  if ((st = ensure_solve_uploaded(pe, s))) return st;
+  if (pe->uploaded) return HM_OK;
+  if ((st = upload_dag(pe->plan.lu, pe->lu, s))) return st;
   HIPCHK(hipStreamSynchronize(s));
   pe->uploaded = true;
   return HM_OK;
@@ -359,13 +397,13 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.status = (int32_t*)es.status.p;
   a.counters = (unsigned long long*)es.counters.p;
   a.trace = (uint64_t*)es.trace.p;
-  int nwg = g_nwg;
+  int nwg = exec_workgroups();
   // The substitution DAG has a few tasks per level: 128 persistent
-  // workgroups hold every ready task (HM_SOLVE_NWG overrides the count).
+  // workgroups hold every ready task (the tuning's solve_wg; HM_SOLVE_NWG
+  // sets its default).
   if (solve && mode != HM_EXEC_LEVEL) {
-    int v = 128;
-    if (const char* e = getenv("HM_SOLVE_NWG")) v = atoi(e);
-    if (v >= 1 && v < nwg) nwg = v;
+    const int v = g_tuning.solve_wg;
+    if (v >= 1 && v < g_nwg) nwg = v;
   }
   a.nwg = nwg;
   a.spin_limit = spin_limit_ticks();
@@ -382,7 +420,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     if (ms) HIPCHK(hipEventRecord(e0, s));
     for (int64_t l = 0; l < dd.nlevels; ++l) {
       int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
-      int grid = std::min(e - b, g_nwg);
+      int grid = std::min(e - b, nwg);
       if (solve)
         hipLaunchKernelGGL(solve_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
                            (const int32_t*)dd.order.p, b, e);
@@ -403,7 +441,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     else if (kind == DAG_FUSED)
       hipLaunchKernelGGL(fused_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     else
-      hipLaunchKernelGGL(exec_dataflow_kernel, dim3(g_nwg), dim3(kThreads), kLdsExecBytes, s, a);
+      hipLaunchKernelGGL(exec_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     HIPCHK(hipGetLastError());
     if (ms) HIPCHK(hipEventRecord(e1, s));
   }
@@ -449,6 +487,21 @@ static bool valid_opts(const hm_opts* o) {
 extern "C" {
 
 const char* hm_last_error(void) { return g_err.c_str(); }
+
+hm_status hm_get_tuning(hm_tuning* out) {
+  if (!out) return fail(HM_EINVAL, "null pointer");
+  *out = g_tuning;
+  return HM_OK;
+}
+
+hm_status hm_set_tuning(const hm_tuning* t) {
+  if (!t) return fail(HM_EINVAL, "null pointer");
+  if (t->exec_wg_per_cu < 0 || t->exec_wg_per_cu > 2 || t->solve_wg < 1 || t->solve_wg > 4096 ||
+      t->batch_order < 0 || t->batch_order > 1)
+    return fail(HM_EINVAL, "tuning out of range (exec_wg_per_cu 0..2, solve_wg 1..4096, batch_order 0..1)");
+  g_tuning = *t;
+  return HM_OK;
+}
 
 hm_status hm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*dealloc)(void*, size_t, void*, void*),
                            void* ctx) {
@@ -519,9 +572,10 @@ hm_status hm_tree_export(hm_tree t, int64_t* perm, int64_t* clusters, double* bo
 
 void hm_tree_free(hm_tree t) {
   if (!t) return;
+  batch_cache_drop(t);
   for (auto& kv : t->plans) {
     PlanEntry* pe = kv.second.get();
-    for (DevDag* dd : {&pe->lu, &pe->solve}) {
+    for (DevDag* dd : {&pe->lu, &pe->solve, &pe->fused}) {
       dev_free(dd->tasks);
       dev_free(dd->indeg);
       dev_free(dd->succ_ptr);
@@ -980,6 +1034,470 @@ hm_status h_lu_solve(hm_matrix A, const hm_opts* opts, double* B, int64_t ldb, i
   if (!B && nrhs > 0) return fail(HM_EINVAL, "null pointer");
   if (nrhs < 0) return fail(HM_EINVAL, "nrhs < 0");
   return lu_impl(A, opts, stream, out, info, B, ldb, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// h_lu_batched: the H-LUs of several matrices as one DAG on one launch
+// ---------------------------------------------------------------------------
+// The batch's factor storage: one arena per element type holding every
+// instance's plan layout at its own base; released with the last handle.
+struct BatchArena {
+  DevBuf f64, f32, piv, ranks;
+  ~BatchArena() {
+    dev_free(f64);
+    dev_free(f32);
+    dev_free(piv);
+    dev_free(ranks);
+  }
+};
+
+// Span of the temporaries of one instance of a batch: the batch's total
+// (HM_BATCH_TEMP_GB, default 16 GiB) shared in proportion to n, at least
+// 64 MiB and at most the single-matrix span.
+static int64_t batch_temp_budget(int64_t n, int64_t n_total) {
+  double gb = 16.0;
+  if (const char* e = getenv("HM_BATCH_TEMP_GB")) gb = std::max(1e-3, atof(e));
+  const double total = gb * (double)(1ll << 30);
+  int64_t b = (int64_t)(total * (double)n / (double)std::max<int64_t>(1, n_total));
+  b = std::max<int64_t>(b, int64_t(64) << 20);
+  return std::min<int64_t>(b, temp_budget()) >> 20 << 20;
+}
+
+static int64_t align64(int64_t x) { return (x + 63) / 64 * 64; }
+
+// Shift a task record of instance-local storage to the batch arena.
+static void relocate_task(Task& t, int64_t b64, int64_t b32, int64_t bpiv, int32_t brank, int32_t brow) {
+  for (View* v : {&t.y, &t.a, &t.b, &t.x}) {
+    if (v->type == VT_F64) v->off += b64;
+    else if (v->type == VT_F32) v->off += b32;
+    if (v->rank_id >= 0) v->rank_id += brank;
+    if ((v->dyn & DYN_COLS2) && v->rank_id2 >= 0) v->rank_id2 += brank;
+  }
+  if ((t.op == OP_TRUNC || t.op == OP_TRUNC2) && t.lr >= 0) t.lr += brank;
+  if ((t.op == OP_GETRF || t.op == OP_TRSM_L || t.op == OP_TRSM_UT || t.op == OP_TRSM_U) && t.piv >= 0)
+    t.piv += bpiv;
+  if (t.op == OP_GETRF) t.row0 += brow;
+}
+
+// Host side of a batch: every instance's traced plan and its bases in the
+// batch arena and the combined DAG.
+struct BatchLayout {
+  std::vector<PlanEntry*> pes;
+  std::vector<int64_t> b64, b32, bpiv, bt, be;
+  std::vector<int32_t> brank, brow;
+  int64_t n64 = 0, n32 = 0, npiv = 0, nrk = 0, ntask = 0, nedge = 0, nroot = 0, nrow = 0, nlev = 0;
+  std::vector<int32_t> level_ptr;  // levels of the union (level l = every instance's level l)
+};
+
+// Trace every tree's plan (in parallel threads, host only) and lay the batch out.
+static hm_status batch_layout(const std::vector<hm_tree>& trees, const hm_opts* opts, BatchLayout& L) {
+  const int count = (int)trees.size();
+  int64_t n_total = 0;
+  for (hm_tree t : trees) n_total += t->t.n;
+  L.pes.assign(count, nullptr);
+  std::vector<hm_status> sts(count, HM_OK);
+  std::vector<std::string> errs(count);
+  {
+    std::atomic<int> next{0};
+    const int nth = std::max(1, std::min<int>(count, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&]() {
+        for (int i = next++; i < count; i = next++) {
+          sts[i] = get_plan(trees[i], opts->prec, opts->max_rank, opts->lazy, true, &L.pes[i],
+                            batch_temp_budget(trees[i]->t.n, n_total));
+          if (sts[i]) errs[i] = g_err;
+        }
+      });
+    for (auto& th : pool) th.join();
+  }
+  for (int i = 0; i < count; ++i)
+    if (sts[i]) return fail(sts[i], "instance " + std::to_string(i) + ": " + errs[i]);
+  for (auto* v : {&L.b64, &L.b32, &L.bpiv, &L.bt, &L.be}) v->assign(count, 0);
+  L.brank.assign(count, 0);
+  L.brow.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    const Plan& p = L.pes[i]->plan;
+    L.b64[i] = L.n64;
+    L.b32[i] = L.n32;
+    L.bpiv[i] = L.npiv;
+    L.brank[i] = (int32_t)L.nrk;
+    L.brow[i] = (int32_t)L.nrow;
+    L.bt[i] = L.ntask;
+    L.be[i] = L.nedge;
+    L.n64 = align64(L.n64 + p.n_f64);
+    L.n32 = align64(L.n32 + p.n_f32);
+    L.npiv = align64(L.npiv + p.n_piv);
+    L.nrk += p.nranks;
+    L.nrow += trees[i]->t.n;
+    L.ntask += (int64_t)p.lu.tasks.size();
+    L.nedge += p.lu.nedges;
+    L.nroot += (int64_t)p.lu.roots.size();
+    L.nlev = std::max<int64_t>(L.nlev, (int64_t)p.lu.level_ptr.size() - 1);
+  }
+  if (L.ntask >= INT32_MAX || L.nedge >= INT32_MAX || L.nrk >= INT32_MAX || L.nrow >= INT32_MAX)
+    return fail(HM_EINVAL, "batch too large for 32-bit task, edge or rank indices");
+  L.level_ptr.assign((size_t)L.nlev + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    const Dag& d = L.pes[i]->plan.lu;
+    for (int64_t l = 0; l + 1 < (int64_t)d.level_ptr.size(); ++l)
+      L.level_ptr[l + 1] += d.level_ptr[l + 1] - d.level_ptr[l];
+  }
+  for (int64_t l = 0; l < L.nlev; ++l) L.level_ptr[l + 1] += L.level_ptr[l];
+  return HM_OK;
+}
+
+// Instance i's part of the combined DAG: relocated task records, successor
+// pointers (without the final entry) and successor indices.
+static void batch_instance(const BatchLayout& L, int i, std::vector<Task>& tk, std::vector<int32_t>& sp,
+                           std::vector<int32_t>& si) {
+  const Dag& d = L.pes[i]->plan.lu;
+  tk = d.tasks;
+  for (Task& t : tk) relocate_task(t, L.b64[i], L.b32[i], L.bpiv[i], L.brank[i], L.brow[i]);
+  sp.assign(d.succ_ptr.begin(), d.succ_ptr.end() - 1);
+  for (auto& x : sp) x += (int32_t)L.be[i];
+  si = d.succ_idx;
+  for (auto& x : si) x += (int32_t)L.bt[i];
+}
+
+// The low-rank descriptors of the batch, indexed like its rank slots (the
+// slots of a solve's column count get an empty descriptor).
+static std::vector<LrDesc> batch_lr(const BatchLayout& L) {
+  std::vector<LrDesc> lr((size_t)L.nrk);
+  std::memset(lr.data(), 0, lr.size() * sizeof(LrDesc));
+  for (size_t i = 0; i < L.pes.size(); ++i) {
+    const Plan& p = L.pes[i]->plan;
+    for (size_t k = 0; k < p.lr.size(); ++k) {
+      LrDesc d = p.lr[k];
+      d.u_off += d.type == VT_F64 ? L.b64[i] : L.b32[i];
+      d.v_off += d.type == VT_F64 ? L.b64[i] : L.b32[i];
+      lr[(size_t)L.brank[i] + k] = d;
+    }
+  }
+  return lr;
+}
+
+// Tasks of the union in level order (level l of every instance in turn).
+static std::vector<int32_t> batch_order(const BatchLayout& L) {
+  std::vector<int32_t> order((size_t)L.ntask);
+  std::vector<int64_t> pos(L.level_ptr.begin(), L.level_ptr.end() - 1);
+  for (size_t i = 0; i < L.pes.size(); ++i) {
+    const Dag& d = L.pes[i]->plan.lu;
+    for (int64_t l = 0; l + 1 < (int64_t)d.level_ptr.size(); ++l)
+      for (int32_t k = d.level_ptr[l]; k < d.level_ptr[l + 1]; ++k)
+        order[pos[l]++] = (int32_t)(d.level_order[k] + L.bt[i]);
+  }
+  return order;
+}
+
+// The device copy of the last batch's combined DAG, its low-rank descriptors
+// and the copy descriptors of every instance's A, kept for the next call on
+// the same plans (a batch refactored again skips the relocation and upload).
+struct BatchCache {
+  std::vector<PlanEntry*> key;
+  int order_mode = 0;
+  DevDag dd;
+  DevBuf lr;
+  std::vector<DevBuf> copies;
+  ~BatchCache() {
+    for (DevBuf* b : {&dd.tasks, &dd.indeg, &dd.succ_ptr, &dd.succ_idx, &dd.roots, &dd.order, &lr}) dev_free(*b);
+    for (DevBuf& b : copies) dev_free(b);
+  }
+};
+static std::mutex g_batch_mu;
+static std::unique_ptr<BatchCache> g_batch;
+
+static void batch_cache_drop(hm_tree t) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (!g_batch) return;
+  for (auto& kv : t->plans)
+    for (PlanEntry* pe : g_batch->key)
+      if (pe == kv.second.get()) {
+        g_batch.reset();
+        return;
+      }
+}
+
+// Relocate and upload the combined DAG of a batch.  order_mode 1 queues the
+// roots of the instances with the most tasks first.
+static hm_status batch_upload(const BatchLayout& L, const hm_matrix* As, int order_mode, hipStream_t s,
+                              BatchCache& bc) {
+  const int count = (int)L.pes.size();
+  DevDag& dd = bc.dd;
+  dd.ntasks = L.ntask;
+  dd.nedges = L.nedge;
+  dd.nlevels = L.nlev;
+  dd.nroots = (int32_t)L.nroot;
+  if (!dev_alloc(dd.tasks, (size_t)L.ntask * sizeof(Task), s) || !dev_alloc(dd.indeg, (size_t)L.ntask * 4, s) ||
+      !dev_alloc(dd.succ_ptr, (size_t)(L.ntask + 1) * 4, s) ||
+      !dev_alloc(dd.succ_idx, (size_t)std::max<int64_t>(1, L.nedge) * 4, s) ||
+      !dev_alloc(dd.roots, (size_t)std::max<int64_t>(1, L.nroot) * 4, s) ||
+      !dev_alloc(dd.order, (size_t)L.ntask * 4, s))
+    return fail(HM_ENOMEM, "device allocation failed (batch DAG)");
+  dd.level_ptr = L.level_ptr;
+  std::vector<int> inst(count);
+  for (int i = 0; i < count; ++i) inst[i] = i;
+  if (order_mode == 1)
+    std::stable_sort(inst.begin(), inst.end(), [&](int x, int y) {
+      return L.pes[x]->plan.lu.tasks.size() > L.pes[y]->plan.lu.tasks.size();
+    });
+  std::vector<int32_t> roots_all;
+  roots_all.reserve((size_t)L.nroot);
+  for (int i : inst)
+    for (int32_t r : L.pes[i]->plan.lu.roots) roots_all.push_back((int32_t)(r + L.bt[i]));
+  // relocation on several host threads, uploads in instance order
+  std::vector<std::vector<Task>> tk(count);
+  std::vector<std::vector<int32_t>> sp(count), si(count);
+  {
+    std::atomic<int> next{0};
+    const int nth = std::max(1, std::min<int>(count, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&]() {
+        for (int i = next++; i < count; i = next++) batch_instance(L, i, tk[i], sp[i], si[i]);
+      });
+    for (auto& th : pool) th.join();
+  }
+  for (int i = 0; i < count; ++i) {
+    const Dag& d = L.pes[i]->plan.lu;
+    if (!tk[i].empty()) {
+      HIPCHK(hipMemcpy((Task*)dd.tasks.p + L.bt[i], tk[i].data(), tk[i].size() * sizeof(Task),
+                       hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy((int32_t*)dd.indeg.p + L.bt[i], d.indeg.data(), d.indeg.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy((int32_t*)dd.succ_ptr.p + L.bt[i], sp[i].data(), sp[i].size() * 4, hipMemcpyHostToDevice));
+    }
+    if (!si[i].empty())
+      HIPCHK(hipMemcpy((int32_t*)dd.succ_idx.p + L.be[i], si[i].data(), si[i].size() * 4, hipMemcpyHostToDevice));
+    std::vector<Task>().swap(tk[i]);
+    std::vector<int32_t>().swap(sp[i]);
+    std::vector<int32_t>().swap(si[i]);
+  }
+  const int32_t last = (int32_t)L.nedge;
+  HIPCHK(hipMemcpy((int32_t*)dd.succ_ptr.p + L.ntask, &last, 4, hipMemcpyHostToDevice));
+  if (!roots_all.empty())
+    HIPCHK(hipMemcpy(dd.roots.p, roots_all.data(), roots_all.size() * 4, hipMemcpyHostToDevice));
+  const std::vector<int32_t> order_all = batch_order(L);
+  HIPCHK(hipMemcpy(dd.order.p, order_all.data(), order_all.size() * 4, hipMemcpyHostToDevice));
+  hm_status st;
+  if ((st = upload(bc.lr, batch_lr(L), s))) return st;
+  // copy descriptors of every instance's A (assembly layout -> batch layout)
+  bc.copies.resize(count);
+  for (int i = 0; i < count; ++i) {
+    hm_matrix A = As[i];
+    const Plan& p = L.pes[i]->plan;
+    const Plan& pa = A->pe->plan;
+    const Tree& tr = A->tree->t;
+    std::vector<CopyDesc> cd;
+    for (size_t b = 0; b < tr.bl.size(); ++b) {
+      const BlockNode& bn = tr.bl[b];
+      if (bn.kind == BK_DENSE) {
+        int64_t cnt = tr.cl[bn.tau].size() * tr.cl[bn.sigma].size();
+        int64_t dst = p.data_off[b] + (p.data_type[b] == VT_F64 ? L.b64[i] : L.b32[i]);
+        cd.push_back(CopyDesc{pa.data_off[b], dst, cnt, p.data_type[b], 0});
+      } else if (bn.kind == BK_LOWRANK) {
+        const LrDesc& da = pa.lr[pa.lr_index[b]];
+        const LrDesc& dl = p.lr[p.lr_index[b]];
+        const int64_t base = dl.type == VT_F64 ? L.b64[i] : L.b32[i];
+        cd.push_back(CopyDesc{da.u_off, dl.u_off + base, (int64_t)da.m * da.cap, dl.type, 0});
+        cd.push_back(CopyDesc{da.v_off, dl.v_off + base, (int64_t)da.n * da.cap, dl.type, 0});
+      }
+    }
+    if ((st = upload(bc.copies[i], cd, s))) return st;
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return HM_OK;
+}
+
+hm_status h_lu_batched(const hm_matrix* As, int count, const hm_opts* opts, void* stream, hm_lu* outs,
+                       int64_t* infos) {
+  if (!As || !outs || count < 1) return fail(HM_EINVAL, "null pointer or count < 1");
+  if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
+  for (int i = 0; i < count; ++i) {
+    outs[i] = nullptr;
+    if (infos) infos[i] = 0;
+    if (!As[i]) return fail(HM_EINVAL, "null matrix in the batch");
+    if (As[i]->max_rank != opts->max_rank) return fail(HM_EINVAL, "max_rank differs from an assembled matrix");
+  }
+  hm_status st = device_setup();
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hm_tree> trees(count);
+  for (int i = 0; i < count; ++i) trees[i] = As[i]->tree;
+  BatchLayout L;
+  if ((st = batch_layout(trees, opts, L))) return st;
+  const std::vector<PlanEntry*>& pes = L.pes;
+  const auto &b64 = L.b64, &b32 = L.b32, &bpiv = L.bpiv, &bt = L.bt, &be = L.be;
+  const auto &brank = L.brank, &brow = L.brow;
+  const int64_t n64 = L.n64, n32 = L.n32, npiv = L.npiv, nrk = L.nrk, ntask = L.ntask, nedge = L.nedge,
+                nroot = L.nroot, nlev = L.nlev;
+  for (int i = 0; i < count; ++i)
+    if ((st = ensure_solve_uploaded(pes[i], s))) return st;
+  auto arena = std::make_shared<BatchArena>();
+  if (!dev_alloc(arena->f64, (size_t)std::max<int64_t>(1, n64) * 8, s) ||
+      !dev_alloc(arena->f32, (size_t)std::max<int64_t>(1, n32) * 4, s) ||
+      !dev_alloc(arena->piv, (size_t)std::max<int64_t>(1, npiv) * 4, s) ||
+      !dev_alloc(arena->ranks, (size_t)std::max<int64_t>(1, nrk) * 4, s))
+    return fail(HM_ENOMEM, "device allocation failed (batch factors)");
+  std::lock_guard<std::mutex> cache_lock(g_batch_mu);
+  const int order_mode = g_tuning.batch_order;
+  if (!g_batch || g_batch->key != pes || g_batch->order_mode != order_mode) {
+    g_batch.reset();
+    auto bc = std::make_unique<BatchCache>();
+    bc->key = pes;
+    bc->order_mode = order_mode;
+    if ((st = batch_upload(L, As, order_mode, s, *bc))) return st;
+    g_batch = std::move(bc);
+  }
+  const DevDag& dd = g_batch->dd;
+  // every instance's A into its part of the arena (FP64 copy, or FP32 conversion
+  // of the off-diagonal blocks), ranks from the assembly
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(256), dim3(256), 0, s, (int32_t*)arena->ranks.p, 0, nrk);
+  for (int i = 0; i < count; ++i) {
+    HIPCHK(hipMemcpyAsync((int32_t*)arena->ranks.p + brank[i], As[i]->ranks.p, (size_t)pes[i]->plan.nlr_leaf * 4,
+                          hipMemcpyDeviceToDevice, s));
+    const DevBuf& cb = g_batch->copies[i];
+    const int64_t ncd = (int64_t)(cb.bytes / sizeof(CopyDesc));
+    if (ncd > 0)
+      hipLaunchKernelGGL(convert_blocks_kernel, dim3((unsigned)ncd), dim3(256), 0, s, (const double*)As[i]->f64.p,
+                         (double*)arena->f64.p, (float*)arena->f32.p, (const CopyDesc*)cb.p);
+  }
+  HIPCHK(hipGetLastError());
+  ExecState es;
+  if ((st = exec_state_alloc(es, ntask, s))) return st;
+  DevBuf scratch;
+  if (!dev_alloc(scratch, (size_t)g_nwg * kScratchPerWg * 8, s)) return fail(HM_ENOMEM, "device allocation failed");
+  ExecArgs a = base_args((double*)arena->f64.p, (float*)arena->f32.p, (int32_t*)arena->piv.p,
+                         (int32_t*)arena->ranks.p, (const LrDesc*)g_batch->lr.p, opts->eps, opts->max_rank);
+  a.scratch = (double*)scratch.p;
+  a.scratch_stride = kScratchPerWg;
+  float ms = 0.f;
+  st = run_dag(dd, a, es, opts->exec, s, &ms, DAG_LU);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  int32_t stv[4];
+  unsigned long long ctr[kCtrSize];
+  HIPCHK(hipMemcpy(stv, es.status.p, 16, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ctr, es.counters.p, sizeof(ctr), hipMemcpyDeviceToHost));
+  dev_free(scratch);
+  exec_state_free(es);
+  if (stv[0] & ST_TIMEOUT) return fail(HM_EDEVICE, "executor timed out waiting for a task");
+  if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: a task the executor does not run");
+  if (stv[0] & ST_SINGULAR) {
+    // the first exact zero pivot (smallest batch row): report it at its instance
+    int i = 0;
+    while (i + 1 < count && brow[i + 1] <= stv[1]) ++i;
+    if (infos)
+      for (int k = 0; k < count; ++k) infos[k] = k == i ? stv[1] - brow[i] : -1;
+    return fail(HM_ESINGULAR, "exact zero pivot in a diagonal leaf of instance " + std::to_string(i));
+  }
+  // one handle per instance over its slices of the arena
+  hm_lu_stats bst;
+  std::memset(&bst, 0, sizeof(bst));
+  for (int k = 0; k < OP_COUNT; ++k) bst.op_busy_ms[k] = (double)ctr[kCtrBusy + k] / (double)g_clock_khz;
+  for (int k = 0; k < 12; ++k) bst.trunc_phase_ms[k] = (double)ctr[kCtrPhase + k] / (double)g_clock_khz;
+  double ntr = (double)std::max<unsigned long long>(1, ctr[kCtrCount + OP_TRUNC] + ctr[kCtrCount + OP_TRUNC2]);
+  bst.trunc_mean_k = ctr[kCtrK] / ntr;
+  bst.trunc_mean_mn = ctr[kCtrMN] / ntr;
+  bst.ntasks = ntask;
+  bst.nedges = nedge;
+  bst.nlevels = nlev;
+  bst.bytes_alg = (int64_t)ctr[0];
+  bst.flops_alg = (int64_t)ctr[1];
+  bst.exec_ms = ms;
+  bst.rank_overflows = stv[2];
+  for (int i = 0; i < count; ++i)
+    for (const Task& tk : pes[i]->plan.lu.tasks)
+      if (tk.op >= 0 && tk.op < OP_COUNT) bst.tasks_by_op[tk.op]++;
+  std::vector<std::unique_ptr<hm_lu_s>> made(count);
+  for (int i = 0; i < count; ++i) {
+    const Plan& p = pes[i]->plan;
+    auto F = std::make_unique<hm_lu_s>();
+    F->tree = As[i]->tree;
+    F->pe = pes[i];
+    F->prec = opts->prec;
+    F->exec = opts->exec;
+    F->eps = opts->eps;
+    F->max_rank = opts->max_rank;
+    F->dag_ntasks = 0;
+    auto slice = [](DevBuf& dst, const DevBuf& src, int64_t off_bytes, int64_t bytes) {
+      dst.p = (char*)src.p + off_bytes;
+      dst.bytes = (size_t)bytes;
+      dst.stream = src.stream;
+      dst.owned = false;
+    };
+    slice(F->f64, arena->f64, b64[i] * 8, p.n_f64 * 8);
+    slice(F->f32, arena->f32, b32[i] * 4, p.n_f32 * 4);
+    slice(F->piv, arena->piv, bpiv[i] * 4, std::max<int64_t>(1, p.n_piv) * 4);
+    slice(F->ranks, arena->ranks, (int64_t)brank[i] * 4, (int64_t)p.nranks * 4);
+    F->arena = arena;
+    if ((st = upload(F->perm, F->tree->t.perm, s))) return st;
+    if ((st = exec_state_alloc(F->solve_st, pes[i]->solve.ntasks, s))) return st;
+    F->stats = bst;
+    made[i] = std::move(F);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) outs[i] = made[i].release();
+  if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "a truncation wanted more than 64 columns");
+  return HM_OK;
+}
+
+hm_status hm_batch_dag_export(const hm_tree* trees, int count, const hm_opts* opts, int64_t* sizes, void* tasks,
+                              int32_t* succ_ptr, int32_t* succ_idx, int32_t* order, int32_t* level_ptr, int64_t* lr,
+                              int64_t* bases) {
+  if (!trees || count < 1 || !opts || !sizes) return fail(HM_EINVAL, "bad argument");
+  if (opts->max_rank < 0 || opts->max_rank > kMaxCap) return fail(HM_EINVAL, "max_rank must be in [0, 64]");
+  std::vector<hm_tree> tv(trees, trees + count);
+  for (hm_tree t : tv)
+    if (!t) return fail(HM_EINVAL, "null tree in the batch");
+  BatchLayout L;
+  hm_status st = batch_layout(tv, opts, L);
+  if (st) return st;
+  sizes[0] = L.ntask;
+  sizes[1] = L.nedge;
+  sizes[2] = L.nlev;
+  sizes[3] = L.n64;
+  sizes[4] = L.n32;
+  sizes[5] = L.npiv;
+  sizes[6] = L.nrk;
+  std::vector<Task> tk;
+  std::vector<int32_t> sp, si;
+  for (int i = 0; i < count; ++i) {
+    if (!tasks && !succ_ptr && !succ_idx) break;
+    batch_instance(L, i, tk, sp, si);
+    if (tasks) std::memcpy((Task*)tasks + L.bt[i], tk.data(), tk.size() * sizeof(Task));
+    if (succ_ptr) std::memcpy(succ_ptr + L.bt[i], sp.data(), sp.size() * 4);
+    if (succ_idx) std::memcpy(succ_idx + L.be[i], si.data(), si.size() * 4);
+  }
+  if (succ_ptr) succ_ptr[L.ntask] = (int32_t)L.nedge;
+  if (order) {
+    const std::vector<int32_t> o = batch_order(L);
+    std::memcpy(order, o.data(), o.size() * 4);
+  }
+  if (level_ptr) std::memcpy(level_ptr, L.level_ptr.data(), L.level_ptr.size() * 4);
+  if (lr) {
+    const std::vector<LrDesc> d = batch_lr(L);
+    for (size_t k = 0; k < d.size(); ++k) {
+      lr[6 * k] = d[k].u_off;
+      lr[6 * k + 1] = d[k].v_off;
+      lr[6 * k + 2] = d[k].m;
+      lr[6 * k + 3] = d[k].n;
+      lr[6 * k + 4] = d[k].cap;
+      lr[6 * k + 5] = d[k].type;
+    }
+  }
+  if (bases)
+    for (int i = 0; i < count; ++i) {
+      int64_t* b = bases + 8 * i;
+      b[0] = L.b64[i];
+      b[1] = L.b32[i];
+      b[2] = L.bpiv[i];
+      b[3] = L.brank[i];
+      b[4] = L.brow[i];
+      b[5] = L.bt[i];
+      b[6] = L.be[i];
+      b[7] = (int64_t)L.pes[i]->plan.lu.tasks.size();
+    }
+  return HM_OK;
 }
 
 void hm_lu_free(hm_lu F) {

@@ -36,6 +36,12 @@ class Opts(C.Structure):
                 ("prec", C.c_int), ("exec", C.c_int), ("lazy", C.c_int)]
 
 
+class Tuning(C.Structure):
+    """hm_tuning: launch choices of the executors (set by autotune.py)."""
+    _fields_ = [("exec_wg_per_cu", C.c_int), ("solve_wg", C.c_int), ("batch_order", C.c_int),
+                ("reserved", C.c_int * 5)]
+
+
 class LuStats(C.Structure):
     _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
                 ("tasks_by_op", C.c_int64 * 12), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
@@ -59,7 +65,8 @@ def exported_symbols():
     return ["hm_set_allocator", "build_htree", "hm_tree_sizes", "hm_tree_export", "h_assemble", "h_lu", "h_lu_solve",
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
             "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error",
-            "h_solve_async", "h_solve_noalloc"]
+            "h_solve_async", "h_solve_noalloc", "h_lu_batched", "hm_batch_dag_export", "hm_get_tuning",
+            "hm_set_tuning"]
 
 
 def lib():
@@ -87,6 +94,10 @@ def lib():
         "h_lu_solve": [vp, C.POINTER(Opts), vp, i64, i64, vp, C.POINTER(vp), C.POINTER(i64)],
         "h_solve": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_solve_async": [vp, vp, i64, i64, vp, vp],
+        "h_lu_batched": [vp, ip, C.POINTER(Opts), vp, vp, vp],
+        "hm_batch_dag_export": [vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp],
+        "hm_get_tuning": [C.POINTER(Tuning)],
+        "hm_set_tuning": [C.POINTER(Tuning)],
         "h_solve_noalloc": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
         "hm_footprint": [vp, ip, C.POINTER(C.c_size_t)],
@@ -287,7 +298,10 @@ class LU:
     tensor) the factorization and the substitution of rhs run as one DAG
     (h_lu_solve) and rhs is overwritten by the solution."""
 
-    def __init__(self, a: Matrix, opts: Opts, stream=None, rhs=None):
+    def __init__(self, a: Matrix, opts: Opts, stream=None, rhs=None, _handle=None):
+        if _handle is not None:  # built by lu_batched
+            self.h, self.a, self.tree, self.opts = _handle, a, a.tree, opts
+            return
         h = C.c_void_p()
         info = C.c_int64(0)
         if rhs is None:
@@ -373,6 +387,70 @@ class LU:
         b = C.c_size_t()
         _check(lib().hm_footprint(self.h, kind, C.byref(b)))
         return b.value
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().hm_get_tuning(C.byref(t)))
+    return {"exec_wg_per_cu": t.exec_wg_per_cu, "solve_wg": t.solve_wg, "batch_order": t.batch_order}
+
+
+def set_tuning(exec_wg_per_cu=None, solve_wg=None, batch_order=None):
+    """Change some launch choices (hm_set_tuning); returns the previous ones."""
+    old = get_tuning()
+    t = Tuning()
+    _check(lib().hm_get_tuning(C.byref(t)))
+    if exec_wg_per_cu is not None:
+        t.exec_wg_per_cu = int(exec_wg_per_cu)
+    if solve_wg is not None:
+        t.solve_wg = int(solve_wg)
+    if batch_order is not None:
+        t.batch_order = int(batch_order)
+    _check(lib().hm_set_tuning(C.byref(t)))
+    return old
+
+
+def lu_batched(mats, opts: Opts, stream=None):
+    """h_lu_batched: the H-LUs of several matrices as one DAG on one launch; returns a list of LU."""
+    k = len(mats)
+    arr = (C.c_void_p * k)(*[m.h for m in mats])
+    outs = (C.c_void_p * k)()
+    infos = np.zeros(k, np.int64)
+    code = lib().h_lu_batched(arr, k, C.byref(opts), _stream_ptr(stream), outs, infos.ctypes.data)
+    hs = [outs[i] for i in range(k)]
+    if code != HM_OK:
+        for h in hs:
+            if h:
+                lib().hm_lu_free(C.c_void_p(h))
+        bad = int(np.nonzero(infos >= 0)[0][0]) if code == HM_ESINGULAR and np.any(infos >= 0) else -1
+        try:
+            _check(code, int(infos[bad]) if bad >= 0 else 0)
+        except HmError as e:
+            e.instance = bad
+            raise
+    return [LU(m, opts, _handle=C.c_void_p(h)) for m, h in zip(mats, hs)]
+
+
+def batch_dag(trees, opts: Opts):
+    """The combined DAG of h_lu_batched over the trees (host only): dict of numpy arrays."""
+    k = len(trees)
+    arr = (C.c_void_p * k)(*[t.h for t in trees])
+    sz = np.zeros(7, np.int64)
+    _check(lib().hm_batch_dag_export(arr, k, C.byref(opts), sz.ctypes.data, None, None, None, None, None, None,
+                                     None))
+    nt, ne, nl, n64, n32, npv, nrk = (int(x) for x in sz)
+    tasks = np.zeros(nt, TASK_DTYPE)
+    sp = np.zeros(nt + 1, np.int32)
+    si = np.zeros(max(1, ne), np.int32)
+    order = np.zeros(max(1, nt), np.int32)
+    lp = np.zeros(nl + 1, np.int32)
+    lr = np.zeros((max(1, nrk), 6), np.int64)
+    bases = np.zeros((k, 8), np.int64)
+    _check(lib().hm_batch_dag_export(arr, k, C.byref(opts), sz.ctypes.data, tasks.ctypes.data, sp.ctypes.data,
+                                     si.ctypes.data, order.ctypes.data, lp.ctypes.data, lr.ctypes.data,
+                                     bases.ctypes.data))
+    return dict(tasks=tasks, succ_ptr=sp, succ_idx=si[:ne], order=order[:nt], level_ptr=lp, lr=lr[:nrk],
+                bases=bases, n_f64=n64, n_f32=n32, n_piv=npv, nranks=nrk, nedges=ne, nlevels=nl)
 
 
 def export_leaf(handle, kind, block, tree: Tree):

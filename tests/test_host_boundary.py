@@ -149,3 +149,32 @@ def test_solve_variants_reject_bad_arguments(L):
     assert L.h_solve(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
     assert L.h_solve_async(None, None, 1, 1, None, ctypes.byref(st)) == hm.HM_EINVAL
     assert L.h_solve_noalloc(None, None, None, 1, 1, 1e-10, 5, None, None, None) == hm.HM_EINVAL
+
+
+def test_tuning_get_set_and_range(L):
+    """hm_set_tuning keeps the launch choices the autotuner picks and refuses
+    values outside their ranges (no device needed)."""
+    old = hm.get_tuning()
+    try:
+        hm.set_tuning(exec_wg_per_cu=1, solve_wg=64, batch_order=1)
+        assert hm.get_tuning() == {"exec_wg_per_cu": 1, "solve_wg": 64, "batch_order": 1}
+        for bad in (dict(exec_wg_per_cu=3), dict(solve_wg=0), dict(batch_order=2)):
+            with pytest.raises(hm.HmError) as ei:
+                hm.set_tuning(**bad)
+            assert ei.value.code == hm.HM_EINVAL
+        assert hm.get_tuning()["exec_wg_per_cu"] == 1
+    finally:
+        hm.set_tuning(**old)
+
+
+def test_batched_arguments_rejected(L):
+    """h_lu_batched and hm_batch_dag_export reject bad arguments before any device work."""
+    h = (ctypes.c_void_p * 2)()
+    opts = hm.make_opts()
+    assert L.h_lu_batched(None, 2, ctypes.byref(opts), None, h, None) == hm.HM_EINVAL
+    assert L.h_lu_batched(h, 0, ctypes.byref(opts), None, h, None) == hm.HM_EINVAL
+    mats = (ctypes.c_void_p * 2)(None, None)
+    assert L.h_lu_batched(mats, 2, ctypes.byref(opts), None, h, None) == hm.HM_EINVAL
+    sz = np.zeros(7, np.int64)
+    assert L.hm_batch_dag_export(mats, 2, ctypes.byref(opts), sz.ctypes.data, None, None, None, None, None, None,
+                                 None) == hm.HM_EINVAL
