@@ -51,8 +51,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sphere_n131072_eps1e-4_mixed", choices=sorted(WORKLOADS) + ["batched"])
+    ap.add_argument("--workload", default="sphere_n131072_eps1e-4_mixed", choices=sorted(WORKLOADS) + ["batched", "serving"])
     ap.add_argument("--batch-count", type=int, default=64, help="instances of the batched workload")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="requests of the serving workload")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (1/s)")
+    ap.add_argument("--serve-factors", type=int, default=8, help="resident factors of the serving workload")
     ap.add_argument("--exec", dest="exec_mode", default="dataflow", choices=["dataflow", "level"])
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--solves", type=int, default=10, help="solve requests timed for p50/p99")
@@ -206,6 +209,50 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serving(args):
+    """The serving workload: 8 resident mixed-precision H-LU factors of the sphere
+    problem (n cycling 16384 ... 262144), a seeded Poisson stream of solve requests
+    (1-64 N(0,1) right-hand sides each, 1% refactorize requests), continuous batching
+    and admission by device footprint; latency from arrival to result-ready."""
+    import torch
+    from paper_1911_07531_amd import hm, serve
+    sizes = [16384, 32768, 65536, 131072, 262144, 16384, 32768, 65536][:args.serve_factors]
+    os.environ.setdefault("HM_TEMP_BUDGET_GB", "2")  # temporaries of the resident plans
+    opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=32, prec=hm.MIXED)
+    t0 = time.perf_counter()
+    res = []
+    for k, n in enumerate(sizes):
+        res.append(serve.Resident("sphere", n, k, opts))
+        print(f"# serving: factor {k} n={n} resident ({res[-1].footprint() / 2**30:.2f} GiB), "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    free, total = torch.cuda.mem_get_info()
+    held = sum(r.footprint() for r in res)
+    budget = int(min(total * 0.85, held + free * 0.8))
+    srv = serve.Server(res, budget_bytes=budget)
+    # warm-up: one solve per factor (uploads the substitution DAGs)
+    warm = [serve.Request(-1 - k, 0.0, k, 4, 5) for k in range(len(res))]
+    srv.run(warm)
+    reqs = serve.poisson_stream(args.serve_requests, rate=args.serve_rate, factors=len(res), seed=7)
+    t1 = time.perf_counter()
+    srv.run(reqs)
+    wall = time.perf_counter() - t1
+    summ = serve.latency_summary(reqs)
+    bsizes = np.bincount([r.batch for r in reqs if r.kind == "solve"])
+    bsizes = bsizes[bsizes > 0]
+    out = {"metric": "solve serving p50/p99 latency (8 resident H-LU factors, Poisson arrivals)",
+           "value": summ["p99_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "serving", "factors_n": sizes, "rate_per_s": args.serve_rate,
+                      "requests": args.serve_requests, "rhs_per_request": "U{1..64}", "refactor_frac": 0.01,
+                      "max_cols_per_batch": srv.max_cols, "eps": 1e-4, "max_rank": 32},
+           "latency": summ, "wall_s": wall, "batches": int(srv.batches),
+           "requests_per_batch": {"mean": float(bsizes.mean()), "max": int(bsizes.max())},
+           "refactor_ms": srv.refactor_ms, "refactor_retries": srv.retries,
+           "offered_rhs_per_s": args.serve_rate * 32.5,
+           "memory": {"resident_bytes": held, "budget_bytes": budget}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -228,6 +275,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
     n, leaf, eps, max_rank, prec = WORKLOADS[args.workload]
     exec_mode = hm.DATAFLOW if args.exec_mode == "dataflow" else hm.LEVEL

@@ -215,7 +215,9 @@ hm_status hm_batch_dag_export(const hm_tree* trees, int count, const hm_opts* op
  * iters_host (ceil(nrhs / 64) ints: corrections per group of 64 columns) and
  * relres_host (nrhs doubles: final relative residuals, NaN where no
  * refinement ran) may be NULL.  A column's result does not depend on the
- * other columns of the call.  Synchronises `stream`; HM_EDEVICE if the
+ * other columns of the call beyond rounding: the substitution's FP64
+ * reductions are grouped by the number of columns, so a column solved alone
+ * and in a wider call agree to about 1e-15 relative, not always bit for bit.  Synchronises `stream`; HM_EDEVICE if the
  * substitution executor gave up (X is then unspecified).  Allocates the
  * refinement vectors on the first refined call and keeps them with F. */
 hm_status h_solve(hm_lu F, hm_matrix A_or_null, double* B, int64_t ldb, int64_t nrhs, double rtol, int max_iter,
