@@ -17,8 +17,13 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+# -amdgpu-spill-vgpr-to-agpr=0: the truncation routines are separate functions
+# of the persistent executors; letting them park values in accumulation
+# registers would count against the register budget of two workgroups per
+# compute unit (the executors' launch bound), halving the executors' occupancy.
 HIP_FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
 
 
 def _run(cmd):

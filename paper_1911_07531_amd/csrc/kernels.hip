@@ -58,10 +58,74 @@ __device__ __forceinline__ int64_t vbytes(const RV& v) {
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core (MFMA) steps: one wavefront multiplies a 16 x 4 by a 4 x 16
+// block into a 16 x 16 accumulator.  Operand lanes: lane l supplies
+// A(l mod 16, l / 16) and B(l / 16, l mod 16).  Entry r of the accumulator in
+// lane l is column l mod 16 and row row(l / 16, r): rows 4 (l / 16) + r for
+// the FP32 MFMA, rows 4 r + l / 16 for the FP64 MFMA (both measured with an
+// in-bounds probe on gfx950).  FP64 operands use the FP64 MFMA; FP32
+// operands the FP32 MFMA with FP32 accumulation.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename CT>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc_t = v4d;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * r + lk; }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = v4f;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// C = A B for operands staged in LDS (A m x k column-major with leading
+// dimension lda, B k x n column-major with leading dimension ldb, both
+// double), on the matrix cores: each wavefront takes 16 x 16 output tiles in
+// turn and sweeps k in steps of 4; st(i, j, value) receives every entry of C.
+template <typename CT, class ST>
+__device__ void mfma_lds_gemm(int m, int n, int k, const double* lA, int lda, const double* lB, int ldb, ST st) {
+  using M = Mfma<CT>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+  for (int tile = wave; tile < tm * tn; tile += nw) {
+    const int i0 = (tile % tm) << 4, j0 = (tile / tm) << 4;
+    const int ia = i0 + li, jb = j0 + li;
+    typename M::acc_t acc = M::zero();
+    for (int k0 = 0; k0 < k; k0 += 4) {
+      const int kk = k0 + lk;
+      const CT av = (ia < m && kk < k) ? (CT)lA[(int64_t)kk * lda + ia] : CT(0);
+      const CT bv = (jb < n && kk < k) ? (CT)lB[(int64_t)jb * ldb + kk] : CT(0);
+      acc = M::step(av, bv, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + M::row(lk, r);
+      if (i < m && jb < n) st(i, jb, (double)acc[r]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // tiled GEMM core: C(m x n) = sum_k A(i, k) B(k, j), 64x64 output tiles,
 // 16-deep k slices staged in LDS, 4x4 outputs per thread.
 // a_kcontig / b_kcontig choose which tile index consecutive threads walk so
-// that global loads are coalesced for the operand's storage order.
+// that global loads are coalesced for the operand's storage order.  (Scalar
+// FMA: these serve the products too large to stage whole, and an MFMA
+// version's accumulators pushed the persistent executors past the register
+// budget of two workgroups per compute unit.)
 // ---------------------------------------------------------------------------
 constexpr int TM = 64, TN = 64, TK = 16, TP = 4;
 
@@ -322,12 +386,9 @@ __device__ void op_gemm_ct(const ExecArgs& a, const Task& t, char* lds) {
     const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
     stage_views(a, {A, lA, nullptr}, {B, lB, nullptr}, beta != 0.0 ? StageSrc{y, lY, nullptr} : none, none);
     __syncthreads();
-    for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-      const int i = e % m, j = e / m;
-      double acc = 0.0;
-      for (int l = 0; l < k; ++l) acc += lA[l * m + i] * lB[j * k + l];
-      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[e]) + alpha * acc);
-    }
+    mfma_lds_gemm<CT>(m, n, k, lA, m, lB, k, [&](int i, int j, double v) {
+      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[i + j * m]) + alpha * v);
+    });
     __syncthreads();
     return;
   }
@@ -366,19 +427,12 @@ __device__ void op_lrgemm_ct(const ExecArgs& a, const Task& t, char* lds) {
     stage_views(a, {A, lA, nullptr}, {B, lB, nullptr}, {X, lX, nullptr},
                 beta != 0.0 ? StageSrc{y, lY, nullptr} : none);
     __syncthreads();
-    for (int e = threadIdx.x; e < k * c; e += blockDim.x) {  // T = b x (k x c)
-      const int i = e % k, j = e / k;
-      double acc = 0.0;
-      for (int l = 0; l < n2; ++l) acc += lB[l * k + i] * lX[j * n2 + l];
-      lT[e] = acc;
-    }
+    // T = b x (k x c), then y = beta y + alpha a T, both on the matrix cores
+    mfma_lds_gemm<CT>(k, c, n2, lB, k, lX, n2, [&](int i, int j, double v) { lT[i + j * k] = v; });
     __syncthreads();
-    for (int e = threadIdx.x; e < m * c; e += blockDim.x) {
-      const int i = e % m, j = e / m;
-      double acc = 0.0;
-      for (int l = 0; l < k; ++l) acc += lA[l * m + i] * lT[j * k + l];
-      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[e]) + alpha * acc);
-    }
+    mfma_lds_gemm<CT>(m, c, k, lA, m, lT, k, [&](int i, int j, double v) {
+      vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[i + j * m]) + alpha * v);
+    });
     __syncthreads();
     return;
   }
@@ -2282,7 +2336,7 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
 }
 
 // Returns the new rank.
-__device__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
+__device__ __noinline__ int trunc_core(const ExecArgs& a, const LrDesc& d, int lr_index, const Stack& su, const Stack& sv,
                           char* lds, double* scratch, double eps) {
   const int tid = threadIdx.x;
   const int K = su.kc + su.kp + su.kp2;
