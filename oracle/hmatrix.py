@@ -260,6 +260,19 @@ def kernel_block(points, perm, rows: Cluster, cols: Cluster, diag: float, r=None
     return a
 
 
+def _svd(a: np.ndarray, full_matrices: bool = True):
+    """The SVD a = W diag(s) Z^T of a finite matrix.  LAPACK's divide-and-conquer
+    driver (numpy's default) can report non-convergence on rare inputs; the
+    decomposition is then taken from the QR-iteration driver, which computes
+    the same factorization."""
+    if not np.all(np.isfinite(a)):
+        raise ValueError("non-finite entries in a matrix to be decomposed")
+    try:
+        return np.linalg.svd(a, full_matrices=full_matrices)
+    except np.linalg.LinAlgError:
+        return sla.svd(a, full_matrices=full_matrices, lapack_driver="gesvd")
+
+
 def truncation_rank(s: np.ndarray, eps: float, max_rank: int, limit: int) -> int:
     """Reading R2: count sigma_i > eps*sigma_1, then cap by max_rank (0 = none) and limit."""
     if s.size == 0 or s[0] <= 0.0:
@@ -271,7 +284,7 @@ def truncation_rank(s: np.ndarray, eps: float, max_rank: int, limit: int) -> int
 
 
 def _compress_dense(a: np.ndarray, eps: float, max_rank: int):
-    w, s, zt = np.linalg.svd(a, full_matrices=False)
+    w, s, zt = _svd(a, full_matrices=False)
     k = truncation_rank(s, eps, max_rank, min(a.shape))
     return w[:, :k] * s[:k], zt[:k].T.copy()
 
@@ -292,7 +305,7 @@ def _compress_randomized(apply, apply_t, m, n, eps, max_rank, seed):
             z, _ = np.linalg.qr(apply_t(q))
             q, _ = np.linalg.qr(apply(z))
         bt = apply_t(q)  # n x ell = (Q^T A)^T
-        zb, s, wt = np.linalg.svd(bt, full_matrices=False)
+        zb, s, wt = _svd(bt, full_matrices=False)
         if ell >= min(m, n) or s[-1] <= eps * s[0] / 10.0:
             k = truncation_rank(s, eps, max_rank, min(m, n))
             u = q @ (wt.T[:, :k] * s[:k])
@@ -407,7 +420,7 @@ def truncated_add_terms(c: Block, terms: list, eps: float, max_rank: int):
         col += kp
     qu, ru = np.linalg.qr(us)
     qv, rv = np.linalg.qr(vs)
-    w, s, zt = np.linalg.svd(ru @ rv.T)
+    w, s, zt = _svd(ru @ rv.T)
     kk = truncation_rank(s, eps, max_rank, min(m, n))
     c.U = qu @ (w[:, :kk] * s[:kk])
     c.V = qv @ zt[:kk].T
@@ -451,7 +464,7 @@ def truncated_add(c: Block, r0: int, c0: int, up: np.ndarray, vp: np.ndarray, ep
     vs[c0:c0 + vp.shape[0], kc:] = vp
     qu, ru = np.linalg.qr(us)
     qv, rv = np.linalg.qr(vs)
-    w, s, zt = np.linalg.svd(ru @ rv.T)
+    w, s, zt = _svd(ru @ rv.T)
     k = truncation_rank(s, eps, max_rank, min(m, n))
     c.U = qu @ (w[:, :k] * s[:k])
     c.V = qv @ zt[:k].T
