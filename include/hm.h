@@ -254,6 +254,20 @@ hm_status h_matvec(hm_matrix A, double alpha, const double* X, int64_t ldx, doub
  * (temporaries, scratch and DAG). */
 hm_status hm_footprint(const void* handle, int kind, size_t* bytes);
 
+/* An H-matrix from host leaf data on the block structure of t (parity hook,
+ * the inverse of hm_export_leaf kind 0): the matrix any outside assembly (for
+ * example an FP64 reference's truncated SVDs) produced, factored and applied
+ * by the device path as one assembled by h_assemble.  ranks: one int32 per
+ * block of hm_tree_export's table (read at low-rank leaves: their rank k;
+ * ignored elsewhere).  data (FP64, host, caller-owned, copied): the leaves in
+ * block-table order, a dense leaf as its m x n entries, a low-rank leaf as U
+ * (m x k) then V (n x k), all column-major; ndata = the total count.  Uses
+ * opts->max_rank (rank capacity; a larger k gives HM_ERANK) and eps (kept
+ * with the matrix).  HM_EINVAL when ndata does not match.  Synchronises
+ * `stream`. */
+hm_status hm_import(hm_tree t, const hm_opts* opts, const int32_t* ranks, const double* data, int64_t ndata,
+                    void* stream, hm_matrix* out);
+
 /* Copy one leaf block to the host in FP64 (parity hook).  kind 0: matrix,
  * 1: factors.  Dense leaf: data (m x n column-major), *rank = -1.  Low-rank
  * leaf: data = U (m x rank) then V (n x rank), column-major, *rank = rank

@@ -671,6 +671,72 @@ hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, 
 }
 
 // ----------------------------------------------------------------------------
+// The H-matvec tables of a matrix (leaf list, row segments per leaf cluster,
+// work vectors); used by h_assemble and hm_import.
+static hm_status matrix_tables(hm_matrix_s* A, hipStream_t s) {
+  hm_tree t = A->tree;
+  const Tree& tr = t->t;
+  const Plan& p = A->pe->plan;
+  hm_status st;
+  // matvec tables
+  std::vector<MvLeaf> leaves;
+  std::vector<int32_t> lr_leaves;
+  std::vector<int32_t> leaf_of_block(tr.bl.size(), -1);
+  for (size_t b = 0; b < tr.bl.size(); ++b) {
+    const BlockNode& bn = tr.bl[b];
+    if (bn.kind == BK_STRUCT) continue;
+    MvLeaf L;
+    L.r0 = tr.cl[bn.tau].begin;
+    L.c0 = tr.cl[bn.sigma].begin;
+    L.m = (int32_t)tr.cl[bn.tau].size();
+    L.n = (int32_t)tr.cl[bn.sigma].size();
+    L.type = VT_F64;
+    if (bn.kind == BK_DENSE) {
+      L.off = p.data_off[b];
+      L.u_off = L.v_off = 0;
+      L.lr = -1;
+    } else {
+      const LrDesc& d = p.lr[p.lr_index[b]];
+      L.off = 0;
+      L.u_off = d.u_off;
+      L.v_off = d.v_off;
+      L.lr = p.lr_index[b];
+      lr_leaves.push_back((int32_t)leaves.size());
+    }
+    leaf_of_block[b] = (int32_t)leaves.size();
+    leaves.push_back(L);
+  }
+  // row segments per leaf cluster
+  const auto& lb = t->leaf_begin;
+  std::vector<std::vector<MvRow>> per(lb.size());
+  for (size_t i = 0; i < leaves.size(); ++i) {
+    const MvLeaf& L = leaves[i];
+    auto it = std::lower_bound(lb.begin(), lb.end(), L.r0);
+    for (; it != lb.end() && *it < L.r0 + L.m; ++it) {
+      size_t rc = it - lb.begin();
+      per[rc].push_back(MvRow{(int32_t)i, (int32_t)(*it - L.r0)});
+    }
+  }
+  std::vector<int32_t> row_ptr(1, 0);
+  std::vector<MvRow> segs;
+  for (auto& v : per) {
+    segs.insert(segs.end(), v.begin(), v.end());
+    row_ptr.push_back((int32_t)segs.size());
+  }
+  if ((st = upload(A->mv_leaves, leaves, s))) return st;
+  if ((st = upload(A->mv_lr, lr_leaves, s))) return st;
+  if ((st = upload(A->mv_row_ptr, row_ptr, s))) return st;
+  if ((st = upload(A->mv_segs, segs, s))) return st;
+  if ((st = upload(A->mv_row_begin, t->leaf_begin, s))) return st;
+  if ((st = upload(A->mv_row_size, t->leaf_size, s))) return st;
+  A->n_lr_leaves = (int64_t)lr_leaves.size();
+  A->n_rows = (int64_t)lb.size();
+  if (!dev_alloc(A->mv_T, std::max<size_t>(1, p.lr.size()) * kMaxCap * 16 * 8, s) ||
+      !dev_alloc(A->mv_x, (size_t)tr.n * 16 * 8, s) || !dev_alloc(A->mv_y, (size_t)tr.n * 16 * 8, s))
+    return fail(HM_ENOMEM, "device allocation failed (matvec)");
+  return HM_OK;
+}
+
 hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, void* stream, hm_matrix* out) {
   if (!t || !out) return fail(HM_EINVAL, "null pointer");
   if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
@@ -764,66 +830,79 @@ hm_status h_assemble(hm_tree t, int kernel, double diag, const hm_opts* opts, vo
   dev_free(lrbuf);
   int32_t stv[4];
   HIPCHK(hipMemcpy(stv, A->status.p, 16, hipMemcpyDeviceToHost));
-  // matvec tables
-  std::vector<MvLeaf> leaves;
-  std::vector<int32_t> lr_leaves;
-  std::vector<int32_t> leaf_of_block(tr.bl.size(), -1);
-  for (size_t b = 0; b < tr.bl.size(); ++b) {
-    const BlockNode& bn = tr.bl[b];
-    if (bn.kind == BK_STRUCT) continue;
-    MvLeaf L;
-    L.r0 = tr.cl[bn.tau].begin;
-    L.c0 = tr.cl[bn.sigma].begin;
-    L.m = (int32_t)tr.cl[bn.tau].size();
-    L.n = (int32_t)tr.cl[bn.sigma].size();
-    L.type = VT_F64;
-    if (bn.kind == BK_DENSE) {
-      L.off = p.data_off[b];
-      L.u_off = L.v_off = 0;
-      L.lr = -1;
-    } else {
-      const LrDesc& d = p.lr[p.lr_index[b]];
-      L.off = 0;
-      L.u_off = d.u_off;
-      L.v_off = d.v_off;
-      L.lr = p.lr_index[b];
-      lr_leaves.push_back((int32_t)leaves.size());
-    }
-    leaf_of_block[b] = (int32_t)leaves.size();
-    leaves.push_back(L);
-  }
-  // row segments per leaf cluster
-  const auto& lb = t->leaf_begin;
-  std::vector<std::vector<MvRow>> per(lb.size());
-  for (size_t i = 0; i < leaves.size(); ++i) {
-    const MvLeaf& L = leaves[i];
-    auto it = std::lower_bound(lb.begin(), lb.end(), L.r0);
-    for (; it != lb.end() && *it < L.r0 + L.m; ++it) {
-      size_t rc = it - lb.begin();
-      per[rc].push_back(MvRow{(int32_t)i, (int32_t)(*it - L.r0)});
-    }
-  }
-  std::vector<int32_t> row_ptr(1, 0);
-  std::vector<MvRow> segs;
-  for (auto& v : per) {
-    segs.insert(segs.end(), v.begin(), v.end());
-    row_ptr.push_back((int32_t)segs.size());
-  }
-  if ((st = upload(A->mv_leaves, leaves, s))) return st;
-  if ((st = upload(A->mv_lr, lr_leaves, s))) return st;
-  if ((st = upload(A->mv_row_ptr, row_ptr, s))) return st;
-  if ((st = upload(A->mv_segs, segs, s))) return st;
-  if ((st = upload(A->mv_row_begin, t->leaf_begin, s))) return st;
-  if ((st = upload(A->mv_row_size, t->leaf_size, s))) return st;
-  A->n_lr_leaves = (int64_t)lr_leaves.size();
-  A->n_rows = (int64_t)lb.size();
-  if (!dev_alloc(A->mv_T, std::max<size_t>(1, p.lr.size()) * kMaxCap * 16 * 8, s) ||
-      !dev_alloc(A->mv_x, (size_t)tr.n * 16 * 8, s) || !dev_alloc(A->mv_y, (size_t)tr.n * 16 * 8, s))
-    return fail(HM_ENOMEM, "device allocation failed (matvec)");
+  if ((st = matrix_tables(A.get(), s))) return st;
   HIPCHK(hipStreamSynchronize(s));
   if (stv[0] & ST_BADOP) return fail(HM_EDEVICE, "internal: an ACA scratch slot is too small");
   *out = A.release();
   if (stv[2] > 0 && opts->max_rank == 0) return fail(HM_ERANK, "compression wanted more than 64 columns");
+  return HM_OK;
+}
+
+hm_status hm_import(hm_tree t, const hm_opts* opts, const int32_t* ranks, const double* data, int64_t ndata,
+                    void* stream, hm_matrix* out) {
+  if (!t || !out || !ranks || (!data && ndata > 0)) return fail(HM_EINVAL, "null pointer");
+  if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
+  const Tree& tr = t->t;
+  PlanEntry* pe;
+  hm_status st = get_plan(t, HM_FP64, opts->max_rank, 0, false, &pe);
+  if (st) return st;
+  const Plan& p = pe->plan;
+  // check the layout of `data` before touching a device
+  int64_t need = 0;
+  for (size_t b = 0; b < tr.bl.size(); ++b) {
+    const BlockNode& bn = tr.bl[b];
+    const int64_t m = tr.cl[bn.tau].size(), n = tr.cl[bn.sigma].size();
+    if (bn.kind == BK_DENSE) {
+      need += m * n;
+    } else if (bn.kind == BK_LOWRANK) {
+      const int32_t k = ranks[b];
+      if (k < 0) return fail(HM_EINVAL, "negative rank at low-rank block " + std::to_string(b));
+      if (k > p.lr[p.lr_index[b]].cap)
+        return fail(HM_ERANK, "rank " + std::to_string(k) + " above the capacity of block " + std::to_string(b));
+      need += (m + n) * k;
+    }
+  }
+  if (need != ndata) return fail(HM_EINVAL, "data holds " + std::to_string(ndata) + " values, the leaves need " +
+                                                std::to_string(need));
+  if ((st = device_setup())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  auto A = std::make_unique<hm_matrix_s>();
+  A->tree = t;
+  A->pe = pe;
+  A->kernel = -1;  // imported: no kernel function
+  A->diag = 0.0;
+  A->eps = opts->eps;
+  A->max_rank = opts->max_rank;
+  if (!dev_alloc(A->f64, p.blocks_f64 * 8, s) || !dev_alloc(A->ranks, ((size_t)p.nlr_leaf + 1) * 4, s) ||
+      !dev_alloc(A->status, 64, s))
+    return fail(HM_ENOMEM, "device allocation failed (matrix)");
+  HIPCHK(hipMemsetAsync(A->status.p, 0, 64, s));
+  if ((st = upload(A->pts, tr.pts_perm, s))) return st;
+  if ((st = upload(A->perm, tr.perm, s))) return st;
+  std::vector<int32_t> rk((size_t)p.nlr_leaf + 1, 0);
+  double* f = (double*)A->f64.p;
+  int64_t off = 0;
+  for (size_t b = 0; b < tr.bl.size(); ++b) {
+    const BlockNode& bn = tr.bl[b];
+    const int64_t m = tr.cl[bn.tau].size(), n = tr.cl[bn.sigma].size();
+    if (bn.kind == BK_DENSE) {
+      HIPCHK(hipMemcpy(f + p.data_off[b], data + off, (size_t)(m * n) * 8, hipMemcpyHostToDevice));
+      off += m * n;
+    } else if (bn.kind == BK_LOWRANK) {
+      const LrDesc& d = p.lr[p.lr_index[b]];
+      const int32_t k = ranks[b];
+      rk[p.lr_index[b]] = k;
+      if (k > 0) {
+        HIPCHK(hipMemcpy(f + d.u_off, data + off, (size_t)(m * k) * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(f + d.v_off, data + off + m * k, (size_t)(n * k) * 8, hipMemcpyHostToDevice));
+      }
+      off += (m + n) * k;
+    }
+  }
+  HIPCHK(hipMemcpy(A->ranks.p, rk.data(), rk.size() * 4, hipMemcpyHostToDevice));
+  if ((st = matrix_tables(A.get(), s))) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  *out = A.release();
   return HM_OK;
 }
 

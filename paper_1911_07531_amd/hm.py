@@ -66,7 +66,7 @@ def exported_symbols():
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
             "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error",
             "h_solve_async", "h_solve_noalloc", "h_lu_batched", "hm_batch_dag_export", "hm_get_tuning",
-            "hm_set_tuning"]
+            "hm_set_tuning", "hm_import"]
 
 
 def lib():
@@ -97,6 +97,7 @@ def lib():
         "h_lu_batched": [vp, ip, C.POINTER(Opts), vp, vp, vp],
         "hm_batch_dag_export": [vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp],
         "hm_get_tuning": [C.POINTER(Tuning)],
+        "hm_import": [vp, C.POINTER(Opts), vp, vp, i64, vp, C.POINTER(vp)],
         "hm_set_tuning": [C.POINTER(Tuning)],
         "h_solve_noalloc": [vp, vp, vp, i64, i64, dbl, ip, vp, vp, vp],
         "h_matvec": [vp, dbl, vp, i64, dbl, vp, i64, i64, vp],
@@ -258,7 +259,10 @@ class Tree:
 class Matrix:
     """H-matrix assembled on the device (h_assemble)."""
 
-    def __init__(self, tree: Tree, kernel: int, diag: float, opts: Opts, stream=None):
+    def __init__(self, tree: Tree, kernel: int, diag: float, opts: Opts, stream=None, _handle=None):
+        if _handle is not None:  # built by import_matrix
+            self.h, self.tree, self.opts = _handle, tree, opts
+            return
         h = C.c_void_p()
         code = lib().h_assemble(tree.h, kernel, diag, C.byref(opts), _stream_ptr(stream), C.byref(h))
         if code == HM_ERANK and h.value:
@@ -387,6 +391,31 @@ class LU:
         b = C.c_size_t()
         _check(lib().hm_footprint(self.h, kind, C.byref(b)))
         return b.value
+
+
+def import_matrix(tree: Tree, opts: Opts, leaves: dict, stream=None) -> Matrix:
+    """hm_import: an H-matrix from host leaves {block index: ('D', array) or ('R', U, V)}
+    on tree's block structure (every leaf block must be given)."""
+    _, cl, _, bl = tree.tables()
+    ranks = np.full(len(bl), -1, np.int32)
+    parts = []
+    for b in range(len(bl)):
+        if bl[b, 2] == 0:
+            continue
+        leaf = leaves[b]
+        if bl[b, 2] == 1:
+            parts.append(np.asarray(leaf[1], np.float64).ravel(order="F"))
+        else:
+            u, v = np.asarray(leaf[1], np.float64), np.asarray(leaf[2], np.float64)
+            ranks[b] = u.shape[1]
+            parts.append(u.ravel(order="F"))
+            parts.append(v.ravel(order="F"))
+    data = np.ascontiguousarray(np.concatenate(parts)) if parts else np.zeros(1)
+    n = sum(p.size for p in parts)
+    h = C.c_void_p()
+    _check(lib().hm_import(tree.h, C.byref(opts), ranks.ctypes.data, data.ctypes.data, n, _stream_ptr(stream),
+                           C.byref(h)))
+    return Matrix(tree, -1, 0.0, opts, _handle=h)
 
 
 def get_tuning() -> dict:

@@ -178,3 +178,24 @@ def test_batched_arguments_rejected(L):
     sz = np.zeros(7, np.int64)
     assert L.hm_batch_dag_export(mats, 2, ctypes.byref(opts), sz.ctypes.data, None, None, None, None, None, None,
                                  None) == hm.HM_EINVAL
+
+
+def test_import_arguments_rejected(L):
+    """hm_import checks the leaf data against the block structure before any
+    device work: a wrong value count is HM_EINVAL, a rank above the capacity
+    HM_ERANK."""
+    opts = hm.make_opts(leaf=32, eps=1e-6, max_rank=8)
+    t = hm.Tree(inputs.sphere_points(512, 0), opts)
+    _, cl, _, bl = t.tables()
+    ranks = np.zeros(len(bl), np.int32)
+    need = sum(int((cl[b[0], 1] - cl[b[0], 0]) * (cl[b[1], 1] - cl[b[1], 0])) for b in bl if b[2] == 1)
+    data = np.zeros(need + 5)
+    h = ctypes.c_void_p()
+    assert L.hm_import(t.h, ctypes.byref(opts), ranks.ctypes.data, data.ctypes.data, need + 5, None,
+                       ctypes.byref(h)) == hm.HM_EINVAL
+    lr = int(np.nonzero(bl[:, 2] == 2)[0][0])
+    ranks[lr] = 9
+    assert L.hm_import(t.h, ctypes.byref(opts), ranks.ctypes.data, data.ctypes.data, need + 5, None,
+                       ctypes.byref(h)) == hm.HM_ERANK
+    assert L.hm_import(None, ctypes.byref(opts), ranks.ctypes.data, data.ctypes.data, 0, None,
+                       ctypes.byref(h)) == hm.HM_EINVAL
