@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-fused", action="store_true",
                     help="skip timing h_lu_solve (H-LU and substitution as one DAG) against h_lu + h_solve")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--lazy", type=int, default=1, choices=[0, 1, 2],
+                    help="update scheme: 0 sequential, 1 collected per hmul call (default), "
+                         "2 accumulated H-LU (Algorithms 4-8)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")
     return ap.parse_args()
@@ -96,7 +99,10 @@ def cpu_baseline(workload, n_sample, leaf, eps, max_rank, lazy):
     root = H.build_block_tree(cl[0], 2.0)
     a = H.assemble(pts, perm, cl, root, diag, eps, max_rank, kernel=kname)
     t0 = time.perf_counter()
-    H.hlu(a, lazy=bool(lazy))
+    if lazy == 2:
+        H.hlu_accumulated(a)
+    else:
+        H.hlu(a, lazy=bool(lazy))
     dt = time.perf_counter() - t0
     return dt
 
@@ -283,7 +289,8 @@ def main():
     exec_mode = hm.DATAFLOW if args.exec_mode == "dataflow" else hm.LEVEL
     torch.cuda.set_device(0)
     pts, diag, kern, _ = problem(args.workload, n)
-    opts = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode)
+    opts = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode,
+                        lazy=args.lazy)
     t0 = time.perf_counter()
     tree = hm.Tree(pts, opts)
     t_tree = time.perf_counter() - t0
@@ -383,7 +390,8 @@ def main():
     fp64 = None
     if prec == hm.MIXED and not args.no_fp64_compare:
         # the same factorization with every block in FP64 (plain form), timed the same way
-        o64 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=hm.FP64, exec_mode=exec_mode)
+        o64 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=hm.FP64, exec_mode=exec_mode,
+                           lazy=args.lazy)
         A64 = hm.Matrix(tree, kern, diag, o64)
         f64 = hm.LU(A64, o64)  # warm-up (traces the FP64 plan)
         del f64
@@ -457,7 +465,8 @@ def main():
         "dtype": "f32+f64" if prec == hm.MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "leaf": leaf, "eta": 2.0, "eps": eps, "max_rank": max_rank,
-                   "nrhs": args.nrhs, "executor": args.exec_mode, "parallelism": "single GPU"},
+                   "nrhs": args.nrhs, "executor": args.exec_mode, "update_scheme": args.lazy,
+                   "parallelism": "single GPU"},
         "hlu_ms": {"median": float(np.median(lu_ms)), "min": float(np.min(lu_ms)), "max": float(np.max(lu_ms))},
         "executor_ms_median": med_exec,
         "achieved_hbm_gbs": ach,

@@ -39,6 +39,13 @@ Readings where the paper is silent (each one is listed in the design notes):
       top-level hmul call collects the exact low-rank terms it produces for
       every low-rank leaf and applies them in one truncation,
       C <- T_eps(C + sum of terms), when it returns.
+  R8  hlu_accumulated follows the accumulator H-LU of Algorithms 4-8: an
+      accumulator per block, low-rank (truncated on every addition, same
+      accuracy and cap as the blocks) or dense for dense leaves, pending
+      structured products split one level at a time by shift_upd, and updates
+      added into a leaf only right before it is factorized or solved.  A
+      product that evaluates to several low-rank terms (the special routines
+      after Algorithm 1) is added to the accumulator term by term.
   R7  the one-dimensional model problem of Sec. 5.1 uses the kernel
       -log|x - y| / (2 pi), a negative multiple of the printed log|x - y|
       (same block ranks, same pivot order in exact arithmetic, a positive
@@ -399,8 +406,12 @@ def hmat_tmul(b: Block, x: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Sec. 2.3: truncated low-rank addition
 # ---------------------------------------------------------------------------
+TRUNCATIONS = [0]  # truncated additions performed (for comparing update schemes)
+
+
 def truncated_add_terms(c: Block, terms: list, eps: float, max_rank: int):
     """C <- T_eps(U_C V_C^T + sum of zero-padded terms (r0, c0, U_p, V_p)), one truncation."""
+    TRUNCATIONS[0] += 1
     m, n = c.rows, c.cols
     kc = c.rank
     ks = [u.shape[1] for (_, _, u, _) in terms]
@@ -450,6 +461,7 @@ def truncated_add(c: Block, r0: int, c0: int, up: np.ndarray, vp: np.ndarray, ep
     SVD of the small core R_U R_V^T, keep the leading singular triplets
     (Reading R2) with Sigma folded into U.
     """
+    TRUNCATIONS[0] += 1
     m, n = c.rows, c.cols
     kc = c.rank
     kp = up.shape[1]
@@ -714,6 +726,143 @@ def hlu(a: HMatrix, eps: float | None = None, max_rank: int | None = None, lazy:
             _use(b)
     finally:
         _Mode.lazy = False
+    return f
+
+
+# ---------------------------------------------------------------------------
+# H-LU with accumulated updates (Sec. 2.3, Algorithms 4-8)
+# ---------------------------------------------------------------------------
+# Every block C_{t,s} owns an accumulator U_{t,s} (the sum of the updates whose
+# product could be evaluated: a dense array for a dense leaf, else low-rank
+# factors truncated on every addition) and a set P_{t,s} of pending products
+# (alpha, A, B) whose three blocks are all structured.  add_upd (Alg. 4)
+# collects, shift_upd (Alg. 6) moves U and P one level down, apply_upd (Alg. 5)
+# reaches the leaves and adds U into them.  hlu (Alg. 7) and the triangular
+# solves (Alg. 8 and its mirror) only collect updates and apply them when a
+# leaf is factorized or solved.
+class _Accumulators:
+    def __init__(self, eps: float, max_rank: int):
+        self.eps, self.max_rank = eps, max_rank
+        self.u: dict = {}   # block index -> dense array, or (U, V)
+        self.p: dict = {}   # block index -> list of (alpha, A, B)
+
+    def add_terms(self, c: Block, terms) -> None:
+        """U_{t,s} := U_{t,s} + sum of the terms (one truncated addition for low-rank form)."""
+        if not terms:
+            return
+        if c.kind == "D":
+            acc = self.u.get(c.index)
+            if acc is None:
+                acc = np.zeros((c.rows, c.cols))
+            for (r0, c0, u, v) in terms:
+                acc[r0:r0 + u.shape[0], c0:c0 + v.shape[0]] += u @ v.T
+            self.u[c.index] = acc
+            return
+        holder = Block(-1, c.tau, c.sigma, "R")
+        prev = self.u.get(c.index)
+        holder.U, holder.V = prev if prev is not None else (np.zeros((c.rows, 0)), np.zeros((c.cols, 0)))
+        truncated_add_terms(holder, list(terms), self.eps, self.max_rank)
+        self.u[c.index] = (holder.U, holder.V)
+
+    def add_upd(self, alpha: float, a: Block, b: Block, c: Block) -> None:
+        """Algorithm 4.  A product that evaluates to several low-rank terms (both
+        operands structured, target a leaf: the special routines after
+        Algorithm 1) is added to the accumulator term by term (reading R8)."""
+        if a.kind == "S" and b.kind == "S" and c.kind == "S":
+            self.p.setdefault(c.index, []).append((alpha, a, b))
+        else:
+            for term in product_terms(alpha, a, b):
+                self.add_terms(c, [term])
+
+    def shift_upd(self, c: Block) -> None:
+        """Algorithm 6 (C structured): U_{t',s'} += U_{t,s}|_{t',s'}; pending products split one level."""
+        acc = self.u.pop(c.index, None)
+        pend = self.p.pop(c.index, [])
+        for i in range(2):
+            for j in range(2):
+                son = c.sons[i][j]
+                r_lo, c_lo = son.tau.begin - c.tau.begin, son.sigma.begin - c.sigma.begin
+                if acc is not None:
+                    u, v = acc
+                    rt = _restrict((0, 0, u, v), r_lo, r_lo + son.rows, c_lo, c_lo + son.cols)
+                    if rt is not None and rt[2].shape[1] > 0:
+                        self.add_terms(son, [rt])
+                for (alpha, a, b) in pend:
+                    for l in range(2):
+                        self.add_upd(alpha, a.sons[i][l], b.sons[l][j], son)
+
+    def apply_upd(self, c: Block) -> None:
+        """Algorithm 5: reach the leaves and add the accumulated updates into them."""
+        if c.kind == "S":
+            self.shift_upd(c)
+            for i in range(2):
+                for j in range(2):
+                    self.apply_upd(c.sons[i][j])
+            return
+        acc = self.u.pop(c.index, None)
+        if acc is None:
+            return
+        if c.kind == "D":
+            c.D += acc
+        else:
+            truncated_add(c, 0, 0, acc[0], acc[1], self.eps, self.max_rank)
+
+    def htrsl(self, ld: Block, m: Block) -> None:
+        """Algorithm 8: L X = M, X overwrites M (corrected indices, reading C-4)."""
+        if m.kind == "S":
+            self.shift_upd(m)
+            for j in range(2):
+                self.htrsl(ld.sons[0][0], m.sons[0][j])
+            for j in range(2):
+                self.add_upd(-1.0, ld.sons[1][0], m.sons[0][j], m.sons[1][j])
+            for j in range(2):
+                self.htrsl(ld.sons[1][1], m.sons[1][j])
+            return
+        self.apply_upd(m)
+        panel_solve_lower(ld, m.D if m.kind == "D" else m.U)
+
+    def htrsu(self, ud: Block, m: Block) -> None:
+        """The mirror of Algorithm 8 for X U = M (reading R4)."""
+        if m.kind == "S":
+            self.shift_upd(m)
+            for j in range(2):
+                self.htrsu(ud.sons[0][0], m.sons[j][0])
+            for j in range(2):
+                self.add_upd(-1.0, m.sons[j][0], ud.sons[0][1], m.sons[j][1])
+            for j in range(2):
+                self.htrsu(ud.sons[1][1], m.sons[j][1])
+            return
+        self.apply_upd(m)
+        if m.kind == "D":
+            xt = np.ascontiguousarray(m.D.T)
+            panel_solve_upper_t(ud, xt)
+            m.D = xt.T.copy()
+        else:
+            panel_solve_upper_t(ud, m.V)
+
+    def hlu(self, a: Block) -> None:
+        """Algorithm 7 (update of A_{t1,t1} with L_{t1,t0} U_{t0,t1}, reading C-1)."""
+        if a.kind == "S":
+            self.shift_upd(a)
+            self.hlu(a.sons[0][0])
+            self.htrsu(a.sons[0][0], a.sons[1][0])
+            self.htrsl(a.sons[0][0], a.sons[0][1])
+            self.add_upd(-1.0, a.sons[1][0], a.sons[0][1], a.sons[1][1])
+            self.hlu(a.sons[1][1])
+            return
+        self.apply_upd(a)
+        a.piv = getrf_leaf(a.D, a.tau.begin)
+
+
+def hlu_accumulated(a: HMatrix, eps: float | None = None, max_rank: int | None = None) -> HMatrix:
+    """H-LU of a copy of ``a`` with accumulated updates (Algorithms 4-8); the input is not modified."""
+    eps = a.eps if eps is None else eps
+    max_rank = a.max_rank if max_rank is None else max_rank
+    f = HMatrix(_copy_block(a.root), a.perm, a.clusters, a.n, eps, max_rank)
+    acc = _Accumulators(eps, max_rank)
+    acc.hlu(f.root)
+    left = [k for k, v in acc.u.items() if v is not None] + [k for k, v in acc.p.items() if v]
+    assert not left, f"accumulated updates never applied to blocks {left[:5]}"
     return f
 
 

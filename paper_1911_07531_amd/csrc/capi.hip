@@ -292,7 +292,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
     pe = it->second.get();
   }
   if (need_trace && !pe->traced) {
-    if (!trace_lu(pe->plan, budget, lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_lu(pe->plan, budget, lazy)) return fail(HM_EINVAL, pe->plan.err);
     if (!trace_solve(pe->plan, solve_split_rows())) return fail(HM_EINVAL, pe->plan.err);
     pe->traced = true;
   }
@@ -304,7 +304,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
 static hm_status trace_fused(hm_tree t, PlanEntry* pe, int lazy) {
   std::lock_guard<std::mutex> lk(t->mu);
   if (!pe->fused_traced) {
-    if (!trace_lu_solve(pe->plan, temp_budget(), lazy != 0)) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_lu_solve(pe->plan, temp_budget(), lazy)) return fail(HM_EINVAL, pe->plan.err);
     pe->fused_traced = true;
   }
   return HM_OK;
@@ -478,7 +478,7 @@ constexpr double kMinEps = 1e-8;
 static bool valid_opts(const hm_opts* o) {
   return o && o->leaf >= 1 && o->eta > 0 && o->eps >= kMinEps && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
          (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL) &&
-         (o->lazy == 0 || o->lazy == 1);
+         (o->lazy >= 0 && o->lazy <= 2);
 }
 
 // ---------------------------------------------------------------------------

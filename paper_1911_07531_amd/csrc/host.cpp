@@ -14,7 +14,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <numeric>
+#include <tuple>
 
 namespace hm {
 
@@ -589,7 +591,11 @@ class Tracer {
     emit(t, {{&a, ACC_RW}});
   }
   void trunc(int c, const Term& term) {
-    int li = p_.lr_index[c];
+    HView cu = lr_u(c), cv = lr_v(c);
+    trunc_lr(p_.lr_index[c], cu, cv, term);
+  }
+  // C <- T_eps(C + term) for the low-rank factors (cu, cv) of lr index li
+  void trunc_lr(int li, const HView& cu, const HView& cv, const Term& term) {
     const LrDesc& d = p_.lr[li];
     int kb = term.u.v.cols;  // static bound of the term's rank
     if (d.cap + kb > kMaxK) fail("stacked rank above 128 in a truncated addition");
@@ -600,7 +606,6 @@ class Tracer {
     t.alpha = term.alpha;
     t.a = term.u.v;
     t.b = term.v.v;
-    HView cu = lr_u(c), cv = lr_v(c);
     emit(t, {{&term.u, ACC_R}, {&term.v, ACC_R}, {&cu, ACC_RW}, {&cv, ACC_RW}});
   }
 
@@ -975,6 +980,203 @@ class Tracer {
     }
   }
 
+  // ---- accumulated updates (Sec. 2.3, Algorithms 4-8), lazy mode 2 --------
+  // Every block that receives updates gets an accumulator: a dense m x n
+  // temporary for a dense leaf, else low-rank factors (temporaries of the
+  // block's shape and the plan's rank capacity, with their own rank slot)
+  // truncated on every addition.  Products whose three blocks are structured
+  // stay pending until shift_upd splits them one level.
+  struct Acc {
+    int li = -1;          // low-rank accumulator: its lr index, or -1
+    HView u, v;           // its factors
+    bool dense = false;   // dense accumulator of a dense leaf
+    HView d;
+    std::vector<std::tuple<double, int, int>> pend;  // pending (alpha, A, B)
+  };
+  Acc& acc(int c) {
+    auto it = accs_.find(c);
+    if (it == accs_.end()) it = accs_.emplace(c, Acc()).first;
+    return it->second;
+  }
+  // U_C := U_C + term (one truncation, or a GEMM into a dense accumulator)
+  void acc_add_term(int c, const Term& tm) {
+    const BlockNode& C = t_.bl[c];
+    const int32_t m = (int32_t)t_.cl[C.tau].size(), n = (int32_t)t_.cl[C.sigma].size();
+    Acc& A = acc(c);
+    if (C.kind == BK_DENSE) {
+      if (!A.dense) {
+        A.d = temp(m, n, -1);
+        zero(A.d);
+        pin(A.d, 1);
+        A.dense = true;
+      }
+      HView ys = rows(A.d, tm.r0, tm.r0 + tm.u.v.rows);
+      ys.v.off += (int64_t)tm.c0 * ys.v.cs;
+      ys.v.cols = tm.v.v.rows;
+      ys.rect.c0 = tm.c0;
+      ys.rect.c1 = tm.c0 + tm.v.v.rows;
+      gemm(ys, tm.alpha, tm.u, transpose(tm.v), 1.0);
+      return;
+    }
+    if (A.li < 0) {
+      LrDesc d;
+      d.m = m;
+      d.n = n;
+      d.cap = (int32_t)std::min<int64_t>(p_.cap, std::min(m, n));
+      A.u = temp(m, d.cap, -1);
+      A.v = temp(n, d.cap, -1);
+      d.u_off = A.u.v.off;
+      d.v_off = A.v.v.off;
+      d.type = temp_type_;
+      A.li = (int)p_.lr.size();
+      p_.lr.push_back(d);
+      p_.lr_block.push_back(-1);
+      lr_obj_.push_back({A.u.obj, A.v.obj});
+      A.u.v.dyn = A.v.v.dyn = DYN_COLS;
+      A.u.v.rank_id = A.v.v.rank_id = A.li;
+      pin(A.u, 1);
+      pin(A.v, 1);
+    }
+    // a term wider than half the stacked-rank limit goes in column chunks
+    constexpr int32_t kChunk = kMaxK / 2;
+    if (tm.u.v.cols > kChunk) {
+      for (int32_t j0 = 0; j0 < tm.u.v.cols; j0 += kChunk) {
+        const int32_t j1 = std::min(tm.u.v.cols, j0 + kChunk);
+        Term part = tm;
+        part.u = cols(tm.u, j0, j1);
+        part.v = cols(tm.v, j0, j1);
+        trunc_lr(A.li, A.u, A.v, part);
+      }
+      return;
+    }
+    trunc_lr(A.li, A.u, A.v, tm);
+  }
+  // Algorithm 4
+  void add_upd(double alpha, int a, int b, int c) {
+    const BlockNode& A = t_.bl[a];
+    const BlockNode& B = t_.bl[b];
+    const BlockNode& C = t_.bl[c];
+    if (A.kind == BK_STRUCT && B.kind == BK_STRUCT && C.kind == BK_STRUCT) {
+      acc(c).pend.emplace_back(alpha, a, b);
+      return;
+    }
+    const int prev = begin_call(PT_HMUL, a, b, c);
+    std::vector<Term> terms;
+    product_terms(alpha, a, b, 0, 0, terms);
+    for (const Term& tm : terms) acc_add_term(c, tm);
+    call_ = prev;
+  }
+  // Algorithm 6 (C structured)
+  void shift_upd(int c) {
+    auto it = accs_.find(c);
+    if (it == accs_.end()) return;
+    Acc A = std::move(it->second);
+    accs_.erase(it);
+    const BlockNode& C = t_.bl[c];
+    const int64_t rb = t_.cl[C.tau].begin, cb = t_.cl[C.sigma].begin;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        const int son = C.son[2 * i + j];
+        const Cluster& ct = t_.cl[t_.bl[son].tau];
+        const Cluster& cs = t_.cl[t_.bl[son].sigma];
+        if (A.li >= 0) {
+          Term r;
+          r.u = rows(A.u, (int32_t)(ct.begin - rb), (int32_t)(ct.end - rb));
+          r.v = rows(A.v, (int32_t)(cs.begin - cb), (int32_t)(cs.end - cb));
+          r.r0 = r.c0 = 0;
+          r.alpha = 1.0;
+          acc_add_term(son, r);
+        }
+        for (auto& pd : A.pend) {
+          const BlockNode& PA = t_.bl[std::get<1>(pd)];
+          const BlockNode& PB = t_.bl[std::get<2>(pd)];
+          for (int l = 0; l < 2; ++l) add_upd(std::get<0>(pd), PA.son[2 * i + l], PB.son[2 * l + j], son);
+        }
+      }
+    if (A.li >= 0) {
+      pin(A.u, -1);
+      pin(A.v, -1);
+    }
+  }
+  // Algorithm 5
+  void apply_upd(int c) {
+    const BlockNode& C = t_.bl[c];
+    if (C.kind == BK_STRUCT) {
+      shift_upd(c);
+      for (int k = 0; k < 4; ++k) apply_upd(C.son[k]);
+      return;
+    }
+    auto it = accs_.find(c);
+    if (it == accs_.end()) return;
+    Acc A = std::move(it->second);
+    accs_.erase(it);
+    if (A.dense) {
+      const int32_t n = (int32_t)t_.cl[C.sigma].size();
+      gemm(dense(c), 1.0, A.d, ident(n), 1.0);
+      pin(A.d, -1);
+    }
+    if (A.li >= 0) {
+      Term r;
+      r.u = A.u;
+      r.v = A.v;
+      r.r0 = r.c0 = 0;
+      r.alpha = 1.0;
+      trunc(c, r);
+      pin(A.u, -1);
+      pin(A.v, -1);
+    }
+  }
+  // Algorithm 8: L X = M (X overwrites M)
+  void htrsl_acc(int ld, int m) {
+    const BlockNode& M = t_.bl[m];
+    const BlockNode& L = t_.bl[ld];
+    if (M.kind == BK_STRUCT) {
+      shift_upd(m);
+      for (int j = 0; j < 2; ++j) htrsl_acc(L.son[0], M.son[j]);
+      for (int j = 0; j < 2; ++j) add_upd(-1.0, L.son[2], M.son[j], M.son[2 + j]);
+      for (int j = 0; j < 2; ++j) htrsl_acc(L.son[3], M.son[2 + j]);
+    } else {
+      apply_upd(m);
+      const int prev = begin_call(PT_HTRSL, ld, m, m);
+      solve_lower(ld, M.kind == BK_DENSE ? dense(m) : lr_u(m));
+      call_ = prev;
+    }
+  }
+  // the mirror of Algorithm 8: X U = M
+  void htrsu_acc(int ud, int m) {
+    const BlockNode& M = t_.bl[m];
+    const BlockNode& U = t_.bl[ud];
+    if (M.kind == BK_STRUCT) {
+      shift_upd(m);
+      for (int j = 0; j < 2; ++j) htrsu_acc(U.son[0], M.son[2 * j]);
+      for (int j = 0; j < 2; ++j) add_upd(-1.0, M.son[2 * j], U.son[1], M.son[2 * j + 1]);
+      for (int j = 0; j < 2; ++j) htrsu_acc(U.son[3], M.son[2 * j + 1]);
+    } else {
+      apply_upd(m);
+      const int prev = begin_call(PT_HTRSU, ud, m, m);
+      solve_upper_t(ud, M.kind == BK_DENSE ? transpose(dense(m)) : lr_v(m));
+      call_ = prev;
+    }
+  }
+  // Algorithm 7
+  void hlu_acc(int a) {
+    const BlockNode& A = t_.bl[a];
+    if (A.kind == BK_STRUCT) {
+      shift_upd(a);
+      hlu_acc(A.son[0]);
+      htrsu_acc(A.son[0], A.son[2]);
+      htrsl_acc(A.son[0], A.son[1]);
+      add_upd(-1.0, A.son[2], A.son[1], A.son[3]);
+      hlu_acc(A.son[3]);
+    } else {
+      apply_upd(a);
+      const int prev = begin_call(PT_HLU, a, a, a);
+      getrf(a);
+      call_ = prev;
+    }
+  }
+  bool accs_empty() const { return accs_.empty(); }
+
   // Panel solves over a diagonal block (leaf or structured).
   void solve_lower(int d, const HView& x) {
     const BlockNode& D = t_.bl[d];
@@ -1130,6 +1332,7 @@ class Tracer {
   std::vector<int> touched_;                   // leaves with collected updates in this call
   int scope_ = 0;                              // depth of nested hmul calls
   bool lazy_ = false;
+  std::map<int, Acc> accs_;                    // accumulators of the accumulated H-LU (lazy mode 2)
   int32_t split_ = 0;                          // row chunk of split low-rank products (solve DAGs)
   int32_t call_ = -1;                          // current paper-level leaf call (Dag::calls)
   bool sub_ = false;                           // emitting substitution tasks
@@ -1141,13 +1344,18 @@ class Tracer {
 
 }  // namespace
 
-bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
+bool trace_lu(Plan& p, int64_t temp_budget_bytes, int lazy) {
   p.lu = Dag();
   p.lr.resize(p.nlr_leaf);
   p.lr_block.resize(p.nlr_leaf);
   Tracer tr(p, p.lu, temp_budget_bytes);
-  tr.set_lazy(lazy);
-  tr.hlu(0);
+  if (lazy == 2) {
+    tr.hlu_acc(0);
+    if (tr.ok() && !tr.accs_empty()) tr.fail("internal: accumulated updates never applied");
+  } else {
+    tr.set_lazy(lazy != 0);
+    tr.hlu(0);
+  }
   tr.flush_all();
   if (!tr.ok()) {
     p.err = tr.err();
@@ -1169,7 +1377,7 @@ bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy) {
   return true;
 }
 
-bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy) {
+bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, int lazy) {
   p.fused = Dag();
   // the H-LU part registers its accumulators again, in the same order
   const std::vector<LrDesc> lr_saved = p.lr;
@@ -1178,8 +1386,12 @@ bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy) {
   p.lr_block.resize(p.nlr_leaf);
   Tracer tr(p, p.fused, temp_budget_bytes);
   tr.set_temp_base(p.lu_temp_base);
-  tr.set_lazy(lazy);
-  tr.hlu(0);
+  if (lazy == 2) {
+    tr.hlu_acc(0);
+  } else {
+    tr.set_lazy(lazy != 0);
+    tr.hlu(0);
+  }
   tr.flush_all();
   tr.begin_substitution();
   HView x = tr.panel();

@@ -90,16 +90,19 @@ struct Plan {
 // leaves FP64, all other blocks FP32.
 bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
 // Trace the H-LU (Algorithm 2) and the forward/backward solve into task DAGs.
-// lazy: collect the updates of each low-rank leaf and add them with a balanced
-// tree of truncations when the leaf is next read (accumulator arithmetic).
-bool trace_lu(Plan& p, int64_t temp_budget_bytes, bool lazy);
+// lazy: 0 truncate every update as produced (Algorithm 1's order); 1 collect
+// the updates one top-level hmul call makes to each low-rank leaf and add them
+// with a balanced tree of truncations when it returns; 2 the accumulated
+// H-LU of Algorithms 4-8 (accumulators per block, shifted down level by level
+// and added into a leaf right before it is factorized or solved).
+bool trace_lu(Plan& p, int64_t temp_budget_bytes, int lazy);
 bool trace_solve(Plan& p, int32_t split_rows);
 // The H-LU and the forward/backward substitution traced as one DAG (the
 // fusion of composed operations): a block row's substitution may start as
 // soon as its factors are final.  The H-LU part is task for task the DAG of
 // trace_lu (same temporaries, same accumulators); the substitution's tasks
 // carry c1 = 1 and its low-rank products are not split.  Requires trace_lu.
-bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, bool lazy);
+bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, int lazy);
 // The paper's semi-automatic construction of the H-LU task graph (Sec. 3,
 // Algorithms 9-11; with sparsify, Algorithm 12 after every refinement step,
 // paths of at most max_path edges, 0 = unbounded).  tasks: 4 ints per leaf

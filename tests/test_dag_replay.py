@@ -215,3 +215,22 @@ def test_replay_leaf_128_within_bounds(lazy):
     ref = H.hlu(a, lazy=bool(lazy))
     rr, rg = H.rank_table(ref), H.rank_table(f)
     assert max(abs(rg[i] - rr[i]) for i in rr) <= 2
+
+
+def test_replay_accumulated_matches_oracle():
+    """lazy mode 2 (the accumulated H-LU of Algorithms 4-8 on the device): the
+    traced DAG replayed in a random topological order equals the oracle's
+    hlu_accumulated to rounding, ranks exactly (accumulators, their shifts
+    and the application before each leaf's factorization or solve)."""
+    n, leaf, eps = 1024, 32, 1e-6
+    t, opts, a = _setup(n, leaf, 2.0, eps, 0, lazy=2)
+    dag = t.dag(opts, 0)
+    blocks = {b.index: b for b in H.leaf_blocks(a.root)}
+    rp = Replay(dag, eps, 0)
+    rp.load_matrix(blocks, dag["block_off"], dag["lr"])
+    rp.run(np.random.default_rng(13))
+    f = _factors_from_replay(rp, t, a, dag)
+    ref = H.hlu_accumulated(a)
+    assert H.rank_table(f) == H.rank_table(ref)
+    got, want = H.densify(f.root), H.densify(ref.root)
+    assert np.max(np.abs(got - want)) <= 1e-9 * np.abs(want).max()

@@ -421,3 +421,46 @@ def test_batched_geometries_against_oracle(geometry, n, leaf):
     rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
     ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
     assert np.all(rg <= 2 * ro + 1e-12), (rg, ro)
+
+
+@pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])
+def test_accumulated_hlu_against_oracle(prec):
+    """The accumulated H-LU (Algorithms 4-8, lazy = 2) on the device, given the
+    oracle's own assembly (hm_import), against the oracle's hlu_accumulated of
+    the identical matrix: ||PA - LU||_2/||A||_2 <= 10 eps against the exact
+    matrix, factor ranks within +-2, solve residuals <= 2x the oracle's."""
+    p = Problem(2048, 32, 1e-6, prec=prec)
+    leaves = {blk.index: ("D", blk.D) if blk.kind == "D" else ("R", blk.U, blk.V) for blk in H.leaf_blocks(p.oa.root)}
+    opts = hm.make_opts(leaf=32, eta=2.0, eps=1e-6, prec=prec, lazy=2)
+    B = hm.import_matrix(p.tree, opts, leaves)
+    f = hm.LU(B, opts)
+    of = H.hlu_accumulated(p.oa)
+    gf = p.gpu_as_oracle(1, f.h)
+    dense = p.dense_exact()
+    err = H.lu_error_2norm(dense, gf, exact=True)
+    orank, grank = H.rank_table(of), H.rank_table(gf)
+    d = np.array([grank[k] - orank[k] for k in orank])
+    print(f"accumulated H-LU: ||PA-LU||/||A|| {err:.2e}, rank differences", np.unique(d, return_counts=True))
+    assert err <= 10 * p.eps
+    assert np.abs(d).max() <= 2
+    b = inputs.rhs(p.n, 8, seed=1)
+    xg = to_host(f.solve(device_rhs(b))[0])
+    xo = H.solve(of, b)
+    a_user = np.empty_like(dense)
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = dense
+    rg = np.linalg.norm(b - a_user @ xg, axis=0) / np.linalg.norm(b, axis=0)
+    ro = np.linalg.norm(b - a_user @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rg <= 2 * ro + 1e-12), (rg, ro)
+
+
+def test_accumulated_hlu_executors_identical():
+    """lazy = 2 on the persistent executor and level by level: bit-identical factors."""
+    p = Problem(4096, 64, 1e-4, max_rank=64, prec=hm.MIXED, oracle=False)
+    b = inputs.rhs(p.n, 3, seed=2)
+    out = []
+    for mode in (hm.DATAFLOW, hm.LEVEL):
+        opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=64, prec=hm.MIXED, exec_mode=mode, lazy=2)
+        x = device_rhs(b)
+        hm.LU(p.A, opts).solve(x)
+        out.append(to_host(x))
+    assert np.array_equal(out[0], out[1])

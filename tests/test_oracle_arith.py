@@ -320,6 +320,41 @@ def test_hlu_lazy_error_bound_c1(c1):
     assert min(lz[i] - seq[i] for i in seq) >= -2
 
 
+@pytest.mark.parametrize("geometry", ["sphere", "line"])
+def test_hlu_accumulated_eps0_equals_dense_block_lu(geometry):
+    """The accumulated H-LU (Algorithms 4-8) only regroups the updates: at
+    eps = 0 (every accumulator and block kept at full rank) the factors equal
+    the dense leaf-pivoted block LU, pivots included."""
+    a, dense = _problem(512, 32, 2.0, 0.0, geometry=geometry)
+    f = H.hlu_accumulated(a)
+    leaves = sorted({(c.begin, c.end) for c in a.clusters if c.is_leaf})
+    ref, pivs = _dense_block_lu(dense, leaves)
+    assert np.max(np.abs(H.densify(f.root) - ref)) <= 1e-11 * np.abs(dense).max()
+    diag = {b.tau.begin: b.piv for b in H.leaf_blocks(f.root) if b.tau is b.sigma}
+    for (r0, _), piv in zip(leaves, pivs):
+        assert np.array_equal(diag[r0], piv)
+
+
+def test_hlu_accumulated_error_bound_and_fewer_truncations():
+    """Accumulated updates meet the 10 eps bound against the exact matrix and
+    need fewer truncated additions than the sequential H-LU of Algorithm 2
+    (the saving the accumulators are for, Sec. 2.3)."""
+    a, dense = _problem(1024, 32, 2.0, 1e-6)
+    H.TRUNCATIONS[0] = 0
+    fs = H.hlu(a)
+    n_seq = H.TRUNCATIONS[0]
+    H.TRUNCATIONS[0] = 0
+    fa = H.hlu_accumulated(a)
+    n_acc = H.TRUNCATIONS[0]
+    assert H.lu_error_2norm(dense, fa, exact=True) <= 10 * 1e-6
+    assert n_acc < n_seq, (n_acc, n_seq)
+    # accumulators truncated against their own largest singular value keep a
+    # little more than the sequential chain, never less
+    rs, ra = H.rank_table(fs), H.rank_table(fa)
+    assert min(ra[i] - rs[i] for i in rs) >= -2
+    assert fs is not fa
+
+
 def test_log_kernel_row_sums_are_the_integral():
     """h * sum_j a_ij approximates the integral of -log|x_i - y| / (2 pi) over
     [0, 1], which is (1 - x log x - (1 - x) log(1 - x)) / (2 pi): the own cell
