@@ -91,7 +91,12 @@ typedef struct {
                        1: collect the updates of a low-rank leaf and add them
                        with a balanced tree of truncations when the leaf is
                        next read (the accumulator arithmetic of Sec. 2.3,
-                       applied per leaf) */
+                       applied per leaf);
+                       2: the accumulated H-LU of Algorithms 4-8: every block
+                       carries an accumulator and pending products, shifted
+                       to its sons at each recursion (shift_upd) and applied
+                       before a leaf is factored, solved with or read
+                       (apply_upd).  Other values: HM_EINVAL */
 } hm_opts;
 
 typedef struct hm_tree_s* hm_tree;
