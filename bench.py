@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--lazy", type=int, default=1, choices=[0, 1, 2],
                     help="update scheme: 0 sequential, 1 collected per hmul call (default), "
                          "2 accumulated H-LU (Algorithms 4-8)")
+    ap.add_argument("--coarsen", type=int, default=0,
+                    help="substitution: diagonal blocks of at most this many rows run as one task (0 = leaf tasks)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")
     return ap.parse_args()
@@ -224,7 +226,7 @@ def run_serving(args):
     from paper_1911_07531_amd import hm, serve
     sizes = [16384, 32768, 65536, 131072, 262144, 16384, 32768, 65536][:args.serve_factors]
     os.environ.setdefault("HM_TEMP_BUDGET_GB", "2")  # temporaries of the resident plans
-    opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=32, prec=hm.MIXED)
+    opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=32, prec=hm.MIXED, coarsen=args.coarsen)
     t0 = time.perf_counter()
     res = []
     for k, n in enumerate(sizes):
@@ -290,7 +292,7 @@ def main():
     torch.cuda.set_device(0)
     pts, diag, kern, _ = problem(args.workload, n)
     opts = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=prec, exec_mode=exec_mode,
-                        lazy=args.lazy)
+                        lazy=args.lazy, coarsen=args.coarsen)
     t0 = time.perf_counter()
     tree = hm.Tree(pts, opts)
     t_tree = time.perf_counter() - t0
@@ -359,6 +361,22 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
         print(f"# solve request {k}: {lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+    # one forward/backward substitution without refinement, 1 / 32 / 64 right-hand sides
+    subst = {}
+    for nr in (1, 32, 64):
+        bs = torch.randn(n, nr, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(nr))
+        xs = bs.t().contiguous().t()
+        f.solve(xs)  # warm-up
+        tt = []
+        for k in range(max(3, args.solves)):
+            xs = bs.t().contiguous().t()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            f.solve(xs)
+            torch.cuda.synchronize()
+            tt.append((time.perf_counter() - t1) * 1e3)
+        subst[f"nrhs{nr}"] = {"p50": float(np.percentile(tt, 50)), "p99": float(np.percentile(tt, 99))}
+        print(f"# substitution pass, {nr} RHS: p50 {subst[f'nrhs{nr}']['p50']:.1f} ms", file=sys.stderr, flush=True)
     fused = None
     if not args.no_fused:
         # factorize-and-solve of the 32 RHS (no refinement): one fused DAG vs h_lu then h_solve
@@ -391,7 +409,7 @@ def main():
     if prec == hm.MIXED and not args.no_fp64_compare:
         # the same factorization with every block in FP64 (plain form), timed the same way
         o64 = hm.make_opts(leaf=leaf, eta=2.0, eps=eps, max_rank=max_rank, prec=hm.FP64, exec_mode=exec_mode,
-                           lazy=args.lazy)
+                           lazy=args.lazy, coarsen=args.coarsen)
         A64 = hm.Matrix(tree, kern, diag, o64)
         f64 = hm.LU(A64, o64)  # warm-up (traces the FP64 plan)
         del f64
@@ -466,12 +484,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "leaf": leaf, "eta": 2.0, "eps": eps, "max_rank": max_rank,
                    "nrhs": args.nrhs, "executor": args.exec_mode, "update_scheme": args.lazy,
-                   "parallelism": "single GPU"},
+                   "coarsen": args.coarsen, "parallelism": "single GPU"},
         "hlu_ms": {"median": float(np.median(lu_ms)), "min": float(np.min(lu_ms)), "max": float(np.max(lu_ms))},
         "executor_ms_median": med_exec,
         "achieved_hbm_gbs": ach,
         "solve_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                      "requests": len(lat), "nrhs": args.nrhs},
+        "substitution_ms": subst,
+        "solve_dag": tree.dag_sizes(opts, 1),
         "ir_iterations": [int(i) for i in iters],
         "max_rel_residual": float(rel.max()),
         "dag": {"tasks": st["ntasks"], "edges": st["nedges"], "levels": st["nlevels"],

@@ -97,6 +97,14 @@ typedef struct {
                        to its sons at each recursion (shift_upd) and applied
                        before a leaf is factored, solved with or read
                        (apply_upd).  Other values: HM_EINVAL */
+  int coarsen;      /* stop refining the substitution at diagonal blocks of at
+                       most this many rows (the remark after Algorithm 11 on
+                       stopping task refinement at a block size): each such
+                       block's forward or backward substitution runs as one
+                       task with the block's panel rows on chip, and the
+                       product from the neighbouring block joins it; 0 = off
+                       (leaf-level tasks), at most 1024, else HM_EINVAL.  The
+                       H-LU's DAG is not coarsened. */
 } hm_opts;
 
 typedef struct hm_tree_s* hm_tree;
@@ -105,14 +113,14 @@ typedef struct hm_lu_s* hm_lu;
 
 typedef struct {
   int64_t ntasks, nedges, nlevels;
-  int64_t tasks_by_op[12];
+  int64_t tasks_by_op[16]; /* tasks per task kind (index = task kind) */
   int64_t bytes_alg;   /* algorithmic bytes of the executed tasks (run-time ranks) */
   int64_t flops_alg;
   double exec_ms;      /* device time of the executor launch(es), HIP events */
   int64_t temp_bytes;  /* temporaries of the traced DAG */
   int64_t rank_overflows; /* truncations whose rank the cap (max_rank, else the
                              capacity 64) or min(m, n) bounded */
-  double op_busy_ms[12];  /* summed workgroup-busy time per task kind (index = task kind) */
+  double op_busy_ms[16];  /* summed workgroup-busy time per task kind (index = task kind) */
   double trunc_phase_ms[12]; /* truncation phases Gram, Cholesky, core, SVD, solve, rebuild:
                                 [0..5] stacked rank <= 32, [6..11] larger */
   double trunc_mean_k, trunc_mean_mn; /* mean stacked rank K and mean m + n of truncations */
@@ -296,6 +304,15 @@ hm_status hm_export_leaf(const void* handle, int kind, int64_t block, double* da
  * counts per word, low half first. */
 hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz);
 
+/* The timeline of the last substitution pass of h_solve on F (recorded when
+ * HM_DEBUG_TRACE=1 was set before h_lu), one record of 8 words per task of
+ * the substitution DAG, laid out as in hm_lu_trace.  For a coarsened block
+ * (task kind 12) info's bits 48-63 hold its micro-operation count and words
+ * 4-6 the ticks of its triangular solves and dense products, of its low-rank
+ * products and panel copies, and the counts of its triangular solves and
+ * products (two 32-bit counts per word, low half first). */
+hm_status hm_solve_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz);
+
 /* Statistics of the last h_lu on F. */
 hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out);
 
@@ -310,6 +327,13 @@ hm_status hm_lu_stats_get(hm_lu F, hm_lu_stats* out);
 hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes);
 hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, int32_t* succ_ptr, int32_t* succ_idx,
                         int32_t* level, int64_t* block_off, int64_t* lr);
+
+/* The micro-operations of the coarsened substitution blocks of a traced DAG
+ * (host only; opts->coarsen > 0, which = 1): *nseq records of task_bytes each,
+ * copied to seq when it is not NULL.  An OP_SEQ task runs records
+ * [piv, piv + lr) in order; views flagged block-local address the block's
+ * rows of the panel relative to its first row. */
+hm_status hm_dag_seq_export(hm_tree t, const hm_opts* opts, int which, int64_t* nseq, void* seq);
 
 /* The paper-level leaf call of every traced task (host only): ncalls calls of
  * 4 int32 each (kind 0 hlu, 1 htrsl, 2 htrsu, 3 hmul; then the blocks: hlu

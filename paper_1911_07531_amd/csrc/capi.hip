@@ -140,6 +140,7 @@ static hm_status device_ok() {
 struct DevDag {
   int64_t ntasks = 0, nlevels = 0, nedges = 0;
   DevBuf tasks, indeg, succ_ptr, succ_idx, roots, order;
+  DevBuf seq;  // micro-operations of coarsened substitution blocks (OP_SEQ)
   int32_t nroots = 0;
   std::vector<int32_t> level_ptr;
 };
@@ -158,7 +159,7 @@ struct hm_tree_s {
   Tree t;
   hm_opts opts;
   // (prec, max_rank, lazy, span of the temporaries in MiB)
-  std::map<std::tuple<int, int, int, int64_t>, std::unique_ptr<PlanEntry>> plans;
+  std::map<std::tuple<int, int, int, int64_t, int>, std::unique_ptr<PlanEntry>> plans;
   std::mutex mu;
   std::vector<int64_t> leaf_begin;  // leaf clusters in order
   std::vector<int32_t> leaf_size;
@@ -203,6 +204,7 @@ struct hm_lu_s {
 };
 
 static int g_nwg = 0;      // executor workgroups at full occupancy (scratch is sized for these)
+static int g_seq_panel = 0;  // doubles of on-chip panel storage per substitution workgroup (OP_SEQ)
 static int g_cus = 0;
 static int64_t g_clock_khz = 0;
 // Launch choices that the autotuner sets (hm_set_tuning); environment
@@ -215,6 +217,9 @@ static int exec_workgroups() {
   return std::max(1, std::min(g_nwg, g_cus * g_tuning.exec_wg_per_cu));
 }
 static void batch_cache_drop(hm_tree t);
+
+// dynamic LDS of a substitution executor launch
+static int solve_lds_bytes() { return g_seq_panel > 0 ? kSeqPanelOff + g_seq_panel * 8 : kLdsExecBytes; }
 
 static hm_status device_setup() {
   if (g_nwg > 0) return HM_OK;
@@ -230,10 +235,17 @@ static hm_status device_setup() {
   (void)hipFuncSetAttribute((const void*)exec_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)exec_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
+  // the substitution executors also hold a coarsened block's panel rows
+  // (OP_SEQ) after their task area, as much as the workgroup's LDS allows
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_max = 0;
+  hipFuncAttributes fa{};
+  const int fixed = hipFuncGetAttributes(&fa, (const void*)solve_dataflow_kernel) == hipSuccess ? (int)fa.sharedSizeBytes : 0;
+  g_seq_panel = std::max(0, std::min(kSeqPanelMax, (lds_max - fixed - kSeqPanelOff) / 8));
   (void)hipFuncSetAttribute((const void*)solve_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsExecBytes);
+                            solve_lds_bytes());
   (void)hipFuncSetAttribute((const void*)solve_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsExecBytes);
+                            solve_lds_bytes());
   (void)hipFuncSetAttribute((const void*)fused_dataflow_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsExecBytes);
   (void)hipFuncSetAttribute((const void*)assemble_aca_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
@@ -277,10 +289,10 @@ static int32_t solve_split_rows() {
 }
 
 static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need_trace, PlanEntry** out,
-                          int64_t budget = -1) {
+                          int64_t budget = -1, int coarsen = 0) {
   if (budget < 0) budget = temp_budget();
   std::lock_guard<std::mutex> lk(t->mu);
-  auto key = std::make_tuple(prec, max_rank, lazy, budget >> 20);
+  auto key = std::make_tuple(prec, max_rank, lazy, budget >> 20, coarsen);
   auto it = t->plans.find(key);
   PlanEntry* pe;
   if (it == t->plans.end()) {
@@ -293,7 +305,7 @@ static hm_status get_plan(hm_tree t, int prec, int max_rank, int lazy, bool need
   }
   if (need_trace && !pe->traced) {
     if (!trace_lu(pe->plan, budget, lazy)) return fail(HM_EINVAL, pe->plan.err);
-    if (!trace_solve(pe->plan, solve_split_rows())) return fail(HM_EINVAL, pe->plan.err);
+    if (!trace_solve(pe->plan, solve_split_rows(), coarsen)) return fail(HM_EINVAL, pe->plan.err);
     pe->traced = true;
   }
   *out = pe;
@@ -323,6 +335,7 @@ static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
   if ((st = upload(dd.succ_idx, d.succ_idx, s))) return st;
   if ((st = upload(dd.roots, d.roots, s))) return st;
   if ((st = upload(dd.order, d.level_order, s))) return st;
+  if (!d.seq.empty() && (st = upload(dd.seq, d.seq, s))) return st;
   return HM_OK;
 }
 
@@ -395,8 +408,13 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.queue = (int32_t*)es.queue.p;
   a.qctl = (int32_t*)es.qctl.p;
   a.status = (int32_t*)es.status.p;
-  a.counters = (unsigned long long*)es.counters.p;
+  // no statistics for substitutions (nothing reads them) unless their
+  // timeline is recorded: their tasks skip the per-task accounting
+  a.counters = solve && !es.trace.p ? nullptr : (unsigned long long*)es.counters.p;
   a.trace = (uint64_t*)es.trace.p;
+  a.seq = (const Task*)dd.seq.p;
+  a.seq_panel = g_seq_panel;
+  if (dd.seq.p && g_seq_panel < 1) return fail(HM_EDEVICE, "no LDS left for coarsened substitution blocks");
   int nwg = exec_workgroups();
   // The substitution DAG has a few tasks per level: 128 persistent
   // workgroups hold every ready task (the tuning's solve_wg; HM_SOLVE_NWG
@@ -409,7 +427,8 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.spin_limit = spin_limit_ticks();
   if (reset_status)
     hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)es.status.p, 0, 0x7fffffff, 0, 0, 4);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, s, (int32_t*)es.counters.p, 0, (int64_t)kCtrSize * 2);
+  if (a.counters)
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, s, (int32_t*)es.counters.p, 0, (int64_t)kCtrSize * 2);
   // events only when the caller asks for the device time
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
@@ -422,7 +441,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
       int b = dd.level_ptr[l], e = dd.level_ptr[l + 1];
       int grid = std::min(e - b, nwg);
       if (solve)
-        hipLaunchKernelGGL(solve_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
+        hipLaunchKernelGGL(solve_level_kernel, dim3(grid), dim3(kThreads), solve_lds_bytes(), s, a,
                            (const int32_t*)dd.order.p, b, e);
       else
         hipLaunchKernelGGL(exec_level_kernel, dim3(grid), dim3(kThreads), kLdsExecBytes, s, a,
@@ -437,7 +456,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
     HIPCHK(hipGetLastError());
     if (ms) HIPCHK(hipEventRecord(e0, s));
     if (solve)
-      hipLaunchKernelGGL(solve_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
+      hipLaunchKernelGGL(solve_dataflow_kernel, dim3(nwg), dim3(kThreads), solve_lds_bytes(), s, a);
     else if (kind == DAG_FUSED)
       hipLaunchKernelGGL(fused_dataflow_kernel, dim3(nwg), dim3(kThreads), kLdsExecBytes, s, a);
     else
@@ -478,7 +497,7 @@ constexpr double kMinEps = 1e-8;
 static bool valid_opts(const hm_opts* o) {
   return o && o->leaf >= 1 && o->eta > 0 && o->eps >= kMinEps && o->max_rank >= 0 && o->max_rank <= kMaxCap &&
          (o->prec == HM_FP64 || o->prec == HM_MIXED) && (o->exec == HM_EXEC_DATAFLOW || o->exec == HM_EXEC_LEVEL) &&
-         (o->lazy >= 0 && o->lazy <= 2);
+         (o->lazy >= 0 && o->lazy <= 2) && o->coarsen >= 0 && o->coarsen <= kMaxCoarsen;
 }
 
 // ---------------------------------------------------------------------------
@@ -582,6 +601,7 @@ void hm_tree_free(hm_tree t) {
       dev_free(dd->succ_idx);
       dev_free(dd->roots);
       dev_free(dd->order);
+      dev_free(dd->seq);
     }
     dev_free(pe->lr);
   }
@@ -592,7 +612,7 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
   if (!t || !opts || !sizes || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
   if (opts->max_rank < 0 || opts->max_rank > kMaxCap) return fail(HM_EINVAL, "max_rank must be in [0, 64]");
   PlanEntry* pe;
-  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe, -1, opts->coarsen);
   if (st) return st;
   if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
   const Dag& d = which == 0 ? pe->plan.lu : which == 1 ? pe->plan.solve : pe->plan.fused;
@@ -611,7 +631,7 @@ hm_status hm_dag_sizes(hm_tree t, const hm_opts* opts, int which, int64_t* sizes
 hm_status hm_dag_calls(hm_tree t, const hm_opts* opts, int which, int64_t* ncalls, int32_t* calls, int32_t* task_call) {
   if (!t || !opts || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
   PlanEntry* pe;
-  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe, -1, opts->coarsen);
   if (st) return st;
   if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
   const Plan& p = pe->plan;
@@ -642,7 +662,7 @@ hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, 
                         int32_t* level, int64_t* block_off, int64_t* lr) {
   if (!t || !opts || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
   PlanEntry* pe;
-  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe);
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe, -1, opts->coarsen);
   if (st) return st;
   const Plan& p = pe->plan;
   if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
@@ -667,6 +687,20 @@ hm_status hm_dag_export(hm_tree t, const hm_opts* opts, int which, void* tasks, 
       lr[6 * i + 4] = p.lr[i].cap;
       lr[6 * i + 5] = p.lr[i].type;
     }
+  return HM_OK;
+}
+
+hm_status hm_dag_seq_export(hm_tree t, const hm_opts* opts, int which, int64_t* nseq, void* seq) {
+  if (!t || !opts || !nseq || which < 0 || which > 2) return fail(HM_EINVAL, "bad argument");
+  if (!valid_opts(opts)) return fail(HM_EINVAL, "invalid options");
+  PlanEntry* pe;
+  hm_status st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe, -1, opts->coarsen);
+  if (st) return st;
+  if (which == 2 && (st = trace_fused(t, pe, opts->lazy))) return st;
+  const Plan& p = pe->plan;
+  const Dag& d = which == 0 ? p.lu : which == 1 ? p.solve : p.fused;
+  *nseq = (int64_t)d.seq.size();
+  if (seq) std::memcpy(seq, d.seq.data(), d.seq.size() * sizeof(Task));
   return HM_OK;
 }
 
@@ -981,7 +1015,7 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
   hipStream_t s = (hipStream_t)stream;
   hm_tree t = A->tree;
   PlanEntry* pe;
-  if ((st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe))) return st;
+  if ((st = get_plan(t, opts->prec, opts->max_rank, opts->lazy, true, &pe, -1, opts->coarsen))) return st;
   if (fused && (st = get_fused(t, pe, opts->lazy, s))) return st;
   if ((st = ensure_uploaded(pe, s))) return st;
   const Plan& p = pe->plan;
@@ -1010,6 +1044,13 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
       HIPCHK(hipMemsetAsync(F->lu_st.trace.p, 0, (size_t)dag.ntasks * kTraceWords * 8, s));
     }
   if ((st = exec_state_alloc(F->solve_st, pe->solve.ntasks, s))) return st;
+  // and of every substitution task (the last pass of h_solve is kept)
+  if (const char* e = getenv("HM_DEBUG_TRACE"))
+    if (e[0] == '1') {
+      if (!dev_alloc(F->solve_st.trace, (size_t)std::max<int64_t>(1, pe->solve.ntasks) * kTraceWords * 8, s))
+        return fail(HM_ENOMEM, "device allocation failed (trace)");
+      HIPCHK(hipMemsetAsync(F->solve_st.trace.p, 0, (size_t)std::max<int64_t>(1, pe->solve.ntasks) * kTraceWords * 8, s));
+    }
   // copy A into the factor layout
   HIPCHK(hipMemsetAsync(F->ranks.p, 0, p.nranks * 4, s));
   HIPCHK(hipMemcpyAsync(F->ranks.p, A->ranks.p, (size_t)p.nlr_leaf * 4, hipMemcpyDeviceToDevice, s));
@@ -1184,7 +1225,7 @@ static hm_status batch_layout(const std::vector<hm_tree>& trees, const hm_opts* 
       pool.emplace_back([&]() {
         for (int i = next++; i < count; i = next++) {
           sts[i] = get_plan(trees[i], opts->prec, opts->max_rank, opts->lazy, true, &L.pes[i],
-                            batch_temp_budget(trees[i]->t.n, n_total));
+                            batch_temp_budget(trees[i]->t.n, n_total), opts->coarsen);
           if (sts[i]) errs[i] = g_err;
         }
       });
@@ -1594,6 +1635,18 @@ hm_status hm_lu_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_kh
   if (!out) return HM_OK;
   if (!F->lu_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
   HIPCHK(hipMemcpy(out, F->lu_st.trace.p, (size_t)F->dag_ntasks * kTraceWords * 8, hipMemcpyDeviceToHost));
+  return HM_OK;
+}
+
+hm_status hm_solve_trace(hm_lu F, uint64_t* out, int64_t* ntasks, int64_t* clock_khz) {
+  if (!F) return fail(HM_EINVAL, "null pointer");
+  const int64_t nt = F->pe->solve.ntasks;
+  if (ntasks) *ntasks = nt;
+  if (clock_khz) *clock_khz = g_clock_khz;
+  if (!out) return HM_OK;
+  if (!F->solve_st.trace.p) return fail(HM_EINVAL, "no trace recorded (set HM_DEBUG_TRACE=1 before h_lu)");
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(out, F->solve_st.trace.p, (size_t)nt * kTraceWords * 8, hipMemcpyDeviceToHost));
   return HM_OK;
 }
 

@@ -23,13 +23,15 @@ constexpr int kLdsBytes = 76 * 1024;  // dynamic LDS per workgroup (two workgrou
 constexpr double kInnerEps = 0.1;
 
 enum ViewType : int32_t { VT_F64 = 0, VT_F32 = 1, VT_IDENT = 2, VT_NONE = 3 };
-enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2, DYN_COLS2 = 4 };
+enum DynFlags : int32_t { DYN_ROWS = 1, DYN_COLS = 2, DYN_COLS2 = 4, DYN_LOCAL = 8 };
 
 // Strided matrix view: element (i, j) lives at arena[off + i*rs + j*cs].
 // With DYN_ROWS / DYN_COLS the extent is ranks[rank_id] (a low-rank leaf's
 // current rank, or the nrhs of a solve), bounded by rows / cols; with
 // DYN_COLS2 the column count is ranks[rank_id2] instead (a view whose rows
-// follow a rank and whose columns follow the nrhs).
+// follow a rank and whose columns follow the nrhs).  DYN_LOCAL marks a view of
+// the solve panel inside a coarsened block (OP_SEQ): off is then the first row
+// relative to the block, and the rows live in the block's on-chip copy.
 struct View {
   int64_t off;
   int32_t rows, cols;
@@ -43,7 +45,8 @@ struct View {
 enum Op : int32_t {
   OP_NOP = 0,
   OP_GETRF = 1,    // a: diagonal leaf (f64, m x m, col-major), piv: int32 offset
-  OP_TRSM_L = 2,   // x <- L^{-1} P x     (a: packed LU of a diagonal leaf, piv)
+  OP_TRSM_L = 2,   // x <- L^{-1} P x     (a: packed LU of a diagonal leaf, piv; in substitutions
+                   //                      b: the leaf's L^{-1}, U^{-1} from OP_TRTRI)
   OP_TRSM_UT = 3,  // x <- U^{-T} x
   OP_TRSM_U = 4,   // x <- U^{-1} x
   OP_GEMM = 5,     // y <- beta y + alpha a b
@@ -53,8 +56,13 @@ enum Op : int32_t {
   OP_COPY = 9,     // y <- a (element type conversion allowed)
   OP_TRUNC2 = 10,  // accumulator lr <- T_eps(alpha pad(a) pad(b)^T + beta pad(x) pad(y)^T)
   OP_GEMMP = 11,   // y <- y + alpha a (b_0 + ... + b_{r0-1}), b_p = b shifted by p * piv elements
-  OP_COUNT = 12,
+  OP_SEQ = 12,     // substitution of a coarsened diagonal block: y = its rows of the solve panel,
+                   // micro-operations seq[piv .. piv + lr) (TRSM_L / TRSM_U / GEMM / LRGEMM) in order
+  OP_TRTRI = 13,   // y (m x 2m, f64) <- [L^{-1}, U^{-1}] of the packed LU a of a factored diagonal leaf
+  OP_COUNT = 14,
 };
+constexpr int kOpSlots = 16;  // per-kind statistics slots of the public structures
+static_assert(OP_COUNT <= kOpSlots, "task kinds exceed the statistics slots");
 
 struct Task {
   int32_t op;
@@ -104,6 +112,11 @@ struct ExecArgs {
   // ranks K, [kCtrMN] sum of m + n (null: off)
   unsigned long long* counters;
   uint64_t* trace;  // optional: per task (start tick, end tick, workgroup)
+  // coarsened substitution blocks (OP_SEQ): their micro-operations, and the
+  // doubles of on-chip panel storage the launch provides after kSeqLdsOff
+  const Task* seq;
+  int32_t seq_panel;
+  int32_t pad1_;
 };
 
 
@@ -147,6 +160,12 @@ constexpr int kCtrBusy = 2, kCtrCount = 2 + OP_COUNT, kCtrPhase = 2 + 2 * OP_COU
 // executor LDS: the task arena, the per-workgroup counters, then a copy of
 // the running task's record, its start tick and its successor range
 constexpr int kLdsExecBytes = kLdsBytes + (kCtrSize + 6) * 8 + (int)sizeof(Task) + 16;
+// substitution executors: two micro-operation records of a coarsened block,
+// then its rows of the panel (ExecArgs::seq_panel doubles)
+constexpr int kSeqLdsOff = (kLdsExecBytes + 15) / 16 * 16;
+constexpr int kSeqPanelOff = kSeqLdsOff + (2 * (int)sizeof(Task) + 15) / 16 * 16;
+constexpr int kSeqPanelMax = 10240;  // doubles (80 KiB): 256 rows x 40 columns
+constexpr int kMaxCoarsen = 1024;    // largest coarsening block (rows)
 // words per task of the debug trace: start, end, info, info2, three words of
 // phase ticks (two 32-bit counts each), the tick the task was queued
 constexpr int kTraceWords = 8;

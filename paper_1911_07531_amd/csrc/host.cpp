@@ -162,6 +162,7 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p) {
   p.data_type.assign(nb, -1);
   p.lr_index.assign(nb, -1);
   p.piv_off.assign(nb, -1);
+  p.inv_off.assign(nb, -1);
   p.lr.clear();
   p.lr_block.clear();
   p.diag_leaves.clear();
@@ -211,6 +212,14 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p) {
   p.blocks_f32 = align_up(f32, A);
   p.panel_off = p.blocks_f64;
   p.n_f64 = p.panel_off + t.n * (int64_t)nrhs_cap;
+  // inverses of the factored diagonal leaves (for the substitution)
+  for (int d : p.diag_leaves) {
+    const int64_t m = t.cl[t.bl[d].tau].size();
+    p.n_f64 = align_up(p.n_f64, A);
+    p.inv_off[d] = p.n_f64;
+    p.n_f64 += 2 * m * m;
+  }
+  p.n_f64 = align_up(p.n_f64, A);
   p.n_f32 = p.blocks_f32;
   p.n_piv = piv;
   p.nlr_leaf = (int)p.lr.size();
@@ -274,6 +283,8 @@ class Tracer {
     size_t nb = t_.bl.size();
     obj_a_.assign(nb, -1);
     obj_b_.assign(nb, -1);
+    inv_obj_.assign(nb, -1);
+    for (int d : p.diag_leaves) inv_obj_[d] = new_obj();
     for (size_t b = 0; b < nb; ++b) {
       if (t_.bl[b].kind == BK_DENSE) obj_a_[b] = new_obj();
       if (t_.bl[b].kind == BK_LOWRANK) {
@@ -293,13 +304,22 @@ class Tracer {
   // Substitution DAGs: temporaries in FP64 after the factor's FP64 arena, and
   // low-rank products with a side of at least 2 * rows rows split into
   // partial products of about `rows` rows (0 = never split).
-  void set_solve(int32_t split_rows) {
+  void set_solve(int32_t split_rows, int32_t coarsen = 0) {
     tsize_ = 8;
     temp_type_ = VT_F64;
     temp_base_ = temp_top_ = p_.n_f64;
     split_ = split_rows;
     sub_ = true;
+    coarsen_ = coarsen;
+    if (coarsen_ > 0) {
+      cb_of_row_.assign((size_t)t_.n, -1);
+      coarse_blocks(0);
+      cb_sweep_.assign(cb_begin_.size(), 0);
+      deferred_.assign(cb_begin_.size(), {});
+    }
   }
+  // +1 before the forward substitution, -1 before the backward one
+  void set_sweep(int dir) { sweep_ = dir; }
   void set_temp_base(int64_t b) { temp_base_ = temp_top_ = b; }
   // tasks emitted from now on belong to a substitution (flag c1 = 1)
   void begin_substitution() { sub_ = true; }
@@ -474,6 +494,11 @@ class Tracer {
   // ---- task emission with dependency tracking (Def. 3.2 + WAR/WAW) -----------
   void emit(Task tk, std::initializer_list<std::pair<const HView*, int>> acc) {
     if (sub_) tk.c1 = 1;
+    if (in_seq_) {
+      seq_op(tk);
+      return;
+    }
+    if (coarsen_ > 0 && sub_ && (tk.op == OP_GEMM || tk.op == OP_LRGEMM) && defer_neighbour(tk)) return;
     // a low-rank leaf with collected updates gets them applied before any
     // other task touches it
     for (auto& a : acc)
@@ -574,13 +599,44 @@ class Tracer {
     t.y = full.v;
     emit(t, {{&full, ACC_W}});
   }
+  // L^{-1} (inv = 0) or U^{-1} (inv = 1) of a factored diagonal leaf, or both
+  // (inv = 2: the m x 2m region OP_TRTRI writes)
+  HView inverse(int d, int inv) {
+    const int32_t m = (int32_t)t_.cl[t_.bl[d].tau].size();
+    HView h;
+    const int64_t off = p_.inv_off[d] + (inv == 1 ? (int64_t)m * m : 0);
+    const int32_t cols = inv == 2 ? 2 * m : m;
+    h.v = View{off, m, cols, 1, m, VT_F64, 0, -1, 0};
+    h.obj = inv_obj_[d];
+    h.rect = Rect{0, m, inv == 1 ? m : 0, inv == 1 ? 2 * m : cols};
+    h.tr = false;
+    return h;
+  }
+  // In a substitution the leaf solves apply the inverses of the triangles
+  // (computed once per factorization by OP_TRTRI): a product instead of a
+  // chain of dependent steps.
   void trsm(int op, int d, const HView& x) {
     Task t = blank(op);
     HView a = dense(d);
     t.a = a.v;
     t.piv = p_.piv_off[d];
     t.x = x.v;
+    if (sub_ && (op == OP_TRSM_L || op == OP_TRSM_U) && p_.inv_off[d] >= 0) {
+      HView iv = inverse(d, op == OP_TRSM_L ? 0 : 1);
+      t.b = iv.v;
+      emit(t, {{&a, ACC_R}, {&iv, ACC_R}, {&x, ACC_RW}});
+      return;
+    }
     emit(t, {{&a, ACC_R}, {&x, ACC_RW}});
+  }
+  void trtri(int d) {
+    Task t = blank(OP_TRTRI);
+    HView a = dense(d);
+    HView y = inverse(d, 2);
+    t.a = a.v;
+    t.y = y.v;
+    t.piv = p_.piv_off[d];
+    emit(t, {{&a, ACC_R}, {&y, ACC_W}});
   }
   void getrf(int d) {
     Task t = blank(OP_GETRF);
@@ -636,7 +692,7 @@ class Tracer {
   // that one product runs on P + Q workgroups instead of one.
   void lr_mul_into(const HView& y, double alpha, const HView& U, const HView& V, const HView& x) {
     const int32_t m = y.v.rows, n2 = V.v.rows;
-    if (split_ <= 0 || std::max(m, n2) < 2 * split_) {
+    if (split_ <= 0 || in_seq_ || folds_into_block(y.v, x.v) || std::max(m, n2) < 2 * split_) {
       lrgemm(y, alpha, U, transpose(V), x, 1.0);
       return;
     }
@@ -1172,6 +1228,7 @@ class Tracer {
       apply_upd(a);
       const int prev = begin_call(PT_HLU, a, a, a);
       getrf(a);
+      trtri(a);
       call_ = prev;
     }
   }
@@ -1180,6 +1237,10 @@ class Tracer {
   // Panel solves over a diagonal block (leaf or structured).
   void solve_lower(int d, const HView& x) {
     const BlockNode& D = t_.bl[d];
+    if (coarsen_ > 0 && !in_seq_ && t_.cl[D.tau].size() <= coarsen_) {
+      seq_block(d, x, false);
+      return;
+    }
     if (D.kind == BK_DENSE) {
       trsm(OP_TRSM_L, d, x);
       return;
@@ -1204,6 +1265,10 @@ class Tracer {
   }
   void solve_upper(int d, const HView& x) {
     const BlockNode& D = t_.bl[d];
+    if (coarsen_ > 0 && !in_seq_ && t_.cl[D.tau].size() <= coarsen_) {
+      seq_block(d, x, true);
+      return;
+    }
     if (D.kind == BK_DENSE) {
       trsm(OP_TRSM_U, d, x);
       return;
@@ -1213,6 +1278,101 @@ class Tracer {
     solve_upper(D.son[3], x1);
     hmat_mul_into(x0, -1.0, D.son[1], x1);
     solve_upper(D.son[0], x0);
+  }
+
+  // ---- coarsened substitution (the remark after Algorithm 11) ---------------
+  // Diagonal blocks of at most coarsen_ rows are the coarse blocks: the first
+  // ones on each path from the root (a larger diagonal leaf is none).
+  void coarse_blocks(int d) {
+    const BlockNode& D = t_.bl[d];
+    const Cluster& c = t_.cl[D.tau];
+    if (c.size() <= coarsen_) {
+      const int id = (int)cb_begin_.size();
+      cb_begin_.push_back(c.begin);
+      cb_end_.push_back(c.end);
+      for (int64_t r = c.begin; r < c.end; ++r) cb_of_row_[(size_t)r] = id;
+      return;
+    }
+    if (D.kind != BK_STRUCT) return;
+    coarse_blocks(D.son[0]);
+    coarse_blocks(D.son[3]);
+  }
+  bool is_panel(const View& v) const {
+    return v.type == VT_F64 && (v.dyn & DYN_COLS) && v.rank_id == p_.nrhs_slot && v.off >= p_.panel_off &&
+           v.off < p_.panel_off + t_.n;
+  }
+  // coarse block holding every row of a panel view, or -1
+  int block_of(const View& v) const {
+    const int64_t r = v.off - p_.panel_off;
+    if (v.rows <= 0) return -1;
+    const int b = cb_of_row_[(size_t)r];
+    return b >= 0 && cb_of_row_[(size_t)(r + v.rows - 1)] == b ? b : -1;
+  }
+  // A product y += alpha A x (or alpha U (V^T x)) whose rows y lie in a coarse
+  // block and whose source x is the whole neighbouring block just solved in
+  // this sweep is folded into y's block task: it is the last update the block
+  // waits for, and inside the task it needs no hand-off.
+  bool folds_into_block(const View& y, const View& x) const {
+    if (coarsen_ <= 0 || !sub_ || !is_panel(y) || !is_panel(x)) return false;
+    const int by = block_of(y), bx = block_of(x);
+    return by >= 0 && bx >= 0 && bx == by - sweep_ && cb_sweep_[by] != sweep_;
+  }
+  bool defer_neighbour(const Task& tk) {
+    const View& x = tk.op == OP_GEMM ? tk.b : tk.x;
+    if (tk.beta != 1.0 || !folds_into_block(tk.y, x)) return false;
+    const int by = block_of(tk.y);
+    Task u = tk;
+    u.y.off = tk.y.off - p_.panel_off - cb_begin_[by];
+    u.y.dyn |= DYN_LOCAL;
+    deferred_[by].push_back(u);
+    return true;
+  }
+  // micro-operation of the open block: panel views become block-local
+  void seq_op(Task tk) {
+    if (tk.op != OP_TRSM_L && tk.op != OP_TRSM_U && tk.op != OP_GEMM && tk.op != OP_LRGEMM)
+      return fail("internal: task kind inside a coarsened block");
+    if ((tk.op == OP_GEMM || tk.op == OP_LRGEMM) && tk.beta != 1.0)
+      return fail("internal: overwriting product inside a coarsened block");
+    for (View* v : {&tk.y, &tk.a, &tk.b, &tk.x}) {
+      if (!is_panel(*v)) continue;
+      const int64_t r = v->off - p_.panel_off - seq_w0_;
+      if (r < 0 || r + v->rows > seq_W_ || v->rs != 1) return fail("internal: panel view outside its coarsened block");
+      v->off = r;
+      v->dyn |= DYN_LOCAL;
+    }
+    seq_cur_.push_back(tk);
+  }
+  // One task for the substitution of diagonal block d (rows x): its leaf
+  // triangular solves and products in the order of the recursion, after the
+  // product from the neighbouring block if that was folded in.
+  void seq_block(int d, const HView& x, bool upper) {
+    const int b = block_of(x.v);
+    if (b < 0 || x.v.rows != cb_end_[b] - cb_begin_[b]) return fail("internal: coarsened block off its rows");
+    in_seq_ = true;
+    seq_w0_ = x.v.off - p_.panel_off;
+    seq_W_ = x.v.rows;
+    seq_cur_.assign(deferred_[b].begin(), deferred_[b].end());
+    const bool folded = !deferred_[b].empty();
+    deferred_[b].clear();
+    if (upper)
+      solve_upper(d, x);
+    else
+      solve_lower(d, x);
+    in_seq_ = false;
+    cb_sweep_[b] = sweep_;
+    Task t = blank(OP_SEQ);
+    t.y = x.v;
+    t.piv = (int64_t)d_.seq.size();
+    t.lr = (int32_t)seq_cur_.size();
+    d_.seq.insert(d_.seq.end(), seq_cur_.begin(), seq_cur_.end());
+    seq_cur_.clear();
+    if (folded) {
+      const int nb = b - sweep_;
+      HView src = rows(panel(), (int32_t)cb_begin_[nb], (int32_t)cb_end_[nb]);
+      emit(t, {{&src, ACC_R}, {&x, ACC_RW}});
+    } else {
+      emit(t, {{&x, ACC_RW}});
+    }
   }
 
   // Algorithm 3: L X = M (X overwrites M)
@@ -1255,6 +1415,7 @@ class Tracer {
     } else {
       const int prev = begin_call(PT_HLU, a, a, a);
       getrf(a);
+      trtri(a);
       call_ = prev;
     }
   }
@@ -1325,6 +1486,7 @@ class Tracer {
   int64_t temp_base_, temp_top_;
   int panel_obj_ = -1;
   std::vector<int> obj_a_, obj_b_;
+  std::vector<int> inv_obj_;                   // inverses of the diagonal leaves
   std::vector<ObjState> objs_;
   std::vector<int> owner_;                     // low-rank leaf owning an object, or -1
   std::vector<std::pair<int, int>> lr_obj_;    // U / V objects of every low-rank index
@@ -1334,6 +1496,17 @@ class Tracer {
   bool lazy_ = false;
   std::map<int, Acc> accs_;                    // accumulators of the accumulated H-LU (lazy mode 2)
   int32_t split_ = 0;                          // row chunk of split low-rank products (solve DAGs)
+  // coarsened substitution (OP_SEQ): diagonal blocks of at most coarsen_ rows
+  int32_t coarsen_ = 0;
+  int sweep_ = 0;                              // +1 forward, -1 backward substitution
+  std::vector<int32_t> cb_of_row_;             // coarse block of each panel row, -1 outside
+  std::vector<int64_t> cb_begin_, cb_end_;     // panel rows of each coarse block
+  std::vector<int> cb_sweep_;                  // the sweep whose block task was emitted
+  std::vector<std::vector<Task>> deferred_;    // neighbour products folded into a block's task
+  bool in_seq_ = false;                        // collecting a block's micro-operations
+  int64_t seq_w0_ = 0;
+  int32_t seq_W_ = 0;
+  std::vector<Task> seq_cur_;
   int32_t call_ = -1;                          // current paper-level leaf call (Dag::calls)
   bool sub_ = false;                           // emitting substitution tasks
   std::vector<Pool> pools_;
@@ -1411,12 +1584,14 @@ bool trace_lu_solve(Plan& p, int64_t temp_budget_bytes, int lazy) {
   return true;
 }
 
-bool trace_solve(Plan& p, int32_t split_rows) {
+bool trace_solve(Plan& p, int32_t split_rows, int32_t coarsen) {
   p.solve = Dag();
   Tracer tr(p, p.solve, 0);
-  tr.set_solve(split_rows);
+  tr.set_solve(split_rows, coarsen);
   HView x = tr.panel();
+  tr.set_sweep(1);
   tr.solve_lower(0, x);
+  tr.set_sweep(-1);
   tr.solve_upper(0, x);
   if (!tr.ok()) {
     p.err = tr.err();

@@ -57,6 +57,7 @@ struct Dag {
   std::vector<int32_t> level_ptr;   // start of each level in level_order
   std::vector<int32_t> roots;
   int64_t nedges = 0;
+  std::vector<Task> seq;            // micro-operations of the OP_SEQ tasks
 };
 
 struct Plan {
@@ -70,6 +71,7 @@ struct Plan {
   std::vector<int32_t> data_type;
   std::vector<int32_t> lr_index;   // low-rank leaves
   std::vector<int64_t> piv_off;    // diagonal dense leaves
+  std::vector<int64_t> inv_off;    // diagonal dense leaves: L^{-1} then U^{-1} (f64, m x m each)
   std::vector<LrDesc> lr;
   std::vector<int32_t> lr_block;
   std::vector<int32_t> diag_leaves;  // diagonal dense leaves in order
@@ -96,7 +98,10 @@ bool make_layout(const Tree& t, int prec, int max_rank, int nrhs_cap, Plan& p);
 // H-LU of Algorithms 4-8 (accumulators per block, shifted down level by level
 // and added into a leaf right before it is factorized or solved).
 bool trace_lu(Plan& p, int64_t temp_budget_bytes, int lazy);
-bool trace_solve(Plan& p, int32_t split_rows);
+// coarsen > 0: diagonal blocks of at most that many rows become one OP_SEQ
+// task each (micro-operations in Dag::seq), with the product from the
+// neighbouring block folded in.
+bool trace_solve(Plan& p, int32_t split_rows, int32_t coarsen = 0);
 // The H-LU and the forward/backward substitution traced as one DAG (the
 // fusion of composed operations): a block row's substitution may start as
 // soon as its factors are final.  The H-LU part is task for task the DAG of

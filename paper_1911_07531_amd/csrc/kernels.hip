@@ -365,6 +365,23 @@ __device__ __forceinline__ void stage_views(const ExecArgs& a, const StageSrc& s
 
 constexpr int kLdsDoubles = kLdsBytes / 8;
 
+// Debug timeline: ticks of a task's phases, added to the running task's six
+// phase slots (thread 0, only while a timeline is recorded).
+struct PhaseClock {
+  unsigned long long* s;
+  uint64_t t;
+  __device__ PhaseClock(const ExecArgs& a, char* lds)
+      : s(a.trace && threadIdx.x == 0 ? (unsigned long long*)(lds + kLdsBytes) + kCtrSize : nullptr),
+        t(s ? wall_clock64() : 0) {}
+  __device__ __forceinline__ void mark(int k) {
+    if (s) {
+      const uint64_t n = wall_clock64();
+      s[k] += n - t;
+      t = n;
+    }
+  }
+};
+
 // y <- beta y + alpha a b
 template <typename CT>
 __device__ void op_gemm_ct(const ExecArgs& a, const Task& t, char* lds) {
@@ -424,16 +441,20 @@ __device__ void op_lrgemm_ct(const ExecArgs& a, const Task& t, char* lds) {
     double* lY = lX + n2 * c;
     double* lT = lY + m * c;
     const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+    PhaseClock pc(a, lds);
     stage_views(a, {A, lA, nullptr}, {B, lB, nullptr}, {X, lX, nullptr},
                 beta != 0.0 ? StageSrc{y, lY, nullptr} : none);
     __syncthreads();
+    pc.mark(0);
     // T = b x (k x c), then y = beta y + alpha a T, both on the matrix cores
     mfma_lds_gemm<CT>(k, c, n2, lB, k, lX, n2, [&](int i, int j, double v) { lT[i + j * k] = v; });
     __syncthreads();
+    pc.mark(1);
     mfma_lds_gemm<CT>(m, c, k, lA, m, lT, k, [&](int i, int j, double v) {
       vst(a, y, i, j, (beta == 0.0 ? 0.0 : beta * lY[i + j * m]) + alpha * v);
     });
     __syncthreads();
+    pc.mark(2);
     return;
   }
   CT* sA = (CT*)lds;
@@ -636,11 +657,14 @@ __device__ void op_gemm_skinny(const ExecArgs& a, const Task& t, char* lds) {
   const RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
   const int m = y.rows, n = y.cols;
   if (m == 0 || n == 0) return;
+  PhaseClock pc(a, lds);
   double* work = (double*)lds;
   const SkinnyMap mp(m, n);
   double acc[4][4];
   skinny_ab(a, A, B, work, kLdsDoubles, mp, acc);
+  pc.mark(0);
   reduce_groups(work, mp, acc);
+  pc.mark(1);
   if (mp.grp == 0)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -650,6 +674,7 @@ __device__ void op_gemm_skinny(const ExecArgs& a, const Task& t, char* lds) {
         if (i < m && j < n) vst(a, y, i, j, (t.beta == 0.0 ? 0.0 : t.beta * vld(a, y, i, j)) + t.alpha * acc[r][c]);
       }
   __syncthreads();
+  pc.mark(2);
 }
 
 // T (k x c, LDS) from registers of group 0
@@ -834,9 +859,11 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
 // i + 64 when R = 2) of the group in registers; step k broadcasts the finished row k
 // (scaled by 1/U_kk for the U solves) and updates the rows it feeds, so the
 // steps need no workgroup barrier.  T: the packed LU, column-major.
-template <int R, int CW>
-__device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m, int kind, const int32_t* perm,
-                          int c, const double* sx, const double* rdiag) {
+// ld(i, src, j): the right-hand side entry of row i (source row src after
+// the interchanges) in column j; st(i, j, v) stores the solution.
+template <int R, int CW, class LD, class ST>
+__device__ void trsm_wave_core(const double* T, int m, int kind, const int32_t* perm, int c, const double* rdiag,
+                               LD ld, ST st) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j0 = wave * CW; j0 < c; j0 += nw * CW) {
     const int cw = min(CW, c - j0);
@@ -846,8 +873,7 @@ __device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m
       const int i = lane + 64 * r;
       const int src = i < m ? (kind == 0 ? perm[i] : i) : 0;
 #pragma unroll
-      for (int q = 0; q < CW; ++q)
-        x[r][q] = (i < m && q < cw) ? (sx ? sx[(j0 + q) * m + i] : vld(a, X, src, j0 + q)) : 0.0;
+      for (int q = 0; q < CW; ++q) x[r][q] = (i < m && q < cw) ? ld(i, src, j0 + q) : 0.0;
     }
     const bool fwd = kind != 2;
     for (int s = 0; s < m; ++s) {
@@ -882,18 +908,44 @@ __device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m
       const int i = lane + 64 * r;
 #pragma unroll
       for (int q = 0; q < CW; ++q)
-        if (i < m && q < cw) vst(a, X, i, j0 + q, x[r][q]);
+        if (i < m && q < cw) st(i, j0 + q, x[r][q]);
     }
   }
 }
 
+template <int R, int CW>
+__device__ void trsm_wave(const ExecArgs& a, const RV& X, const double* T, int m, int kind, const int32_t* perm,
+                          int c, const double* sx, const double* rdiag) {
+  trsm_wave_core<R, CW>(
+      T, m, kind, perm, c, rdiag,
+      [&](int i, int src, int j) { return sx ? sx[j * m + i] : vld(a, X, src, j); },
+      [&](int i, int j, double v) { vst(a, X, i, j, v); });
+}
+
 __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
+  PhaseClock pc(a, lds);
   const int m = t.a.rows;
   RV X = resolve(a, t.x);
   const int c = X.cols;
   if (m == 0 || c == 0) return;
   const double* g = a.f64 + t.a.off;
   const int32_t* perm = a.piv + t.piv + m;  // row permutation of the leaf (kind 0)
+  if (t.b.type == VT_F64 && (int64_t)m * m + (int64_t)m * c <= kLdsDoubles) {
+    // substitution with the inverse of the triangle: x <- T^{-1} (P x), one
+    // product on the matrix cores from operands staged in one phase
+    double* lI = (double*)lds;
+    double* lX = lI + m * m;
+    const RV inv{t.b.off, m, m, 1, m, VT_F64};
+    const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+    stage_views(a, {inv, lI, nullptr}, {X, lX, kind == 0 ? perm : nullptr}, none, none);
+    __syncthreads();
+    pc.mark(0);
+    mfma_lds_gemm<double>(m, c, m, lI, m, lX, m, [&](int i, int j, double v) { vst(a, X, i, j, v); });
+    pc.mark(2);
+    __syncthreads();
+    pc.mark(3);
+    return;
+  }
   double* sL = (double*)lds;
   const double* sx = nullptr;
   bool tri_lds = false;
@@ -911,6 +963,7 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
     __syncthreads();
     tri_lds = true;
   }
+  pc.mark(0);
   const double* T = tri_lds ? sL : g;
   // reciprocal diagonal for the U solves, after the staged data when room is left
   double* rdiag = nullptr;
@@ -919,6 +972,7 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) rdiag[i] = 1.0 / T[i * m + i];
     __syncthreads();
   }
+  pc.mark(1);
   // columns per wavefront: spread the panel over all four
   const int per = (c + 3) / 4;
   if (m <= 64) {
@@ -936,7 +990,290 @@ __device__ void op_trsm(const ExecArgs& a, const Task& t, char* lds, int kind) {
     else
       trsm_wave<2, 8>(a, X, T, m, kind, perm, c, sx, rdiag);
   }
+  pc.mark(2);
   __syncthreads();
+  pc.mark(3);
+}
+
+// Inverses of the triangles of a factored diagonal leaf (its packed LU, a):
+// y = [L^{-1}, U^{-1}], each m x m column-major, column j solving against the
+// unit vector e_j.  The substitution applies them as products.
+__device__ void op_trtri(const ExecArgs& a, const Task& t, char* lds) {
+  const int m = t.a.rows;
+  if (m == 0) return;
+  const double* g = a.f64 + t.a.off;
+  double* Li = a.f64 + t.y.off;
+  double* Ui = Li + (int64_t)m * m;
+  double* sL = (double*)lds;
+  const double* T = g;
+  double* rdiag = nullptr;
+  if ((int64_t)m * m + m <= kLdsDoubles) {
+    copy_batched(sL, g, m * m);
+    __syncthreads();
+    T = sL;
+    rdiag = sL + m * m;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) rdiag[i] = 1.0 / sL[i * m + i];
+    __syncthreads();
+  }
+  // the right-hand sides are unit vectors; the interchanges are not applied
+  // (kind 0 reads perm, which these sides ignore)
+  const int32_t* perm = a.piv + t.piv + m;
+  auto unit = [](int i, int, int j) { return i == j ? 1.0 : 0.0; };
+  auto stL = [&](int i, int j, double v) { Li[i + (int64_t)j * m] = v; };
+  auto stU = [&](int i, int j, double v) { Ui[i + (int64_t)j * m] = v; };
+  if (m <= 64) {
+    trsm_wave_core<1, 16>(T, m, 0, perm, m, nullptr, unit, stL);
+    trsm_wave_core<1, 16>(T, m, 2, perm, m, rdiag, unit, stU);
+  } else {
+    trsm_wave_core<2, 8>(T, m, 0, perm, m, nullptr, unit, stL);
+    trsm_wave_core<2, 8>(T, m, 2, perm, m, rdiag, unit, stU);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Coarsened substitution block (OP_SEQ).  Task refinement may stop at a block
+// size (the remark after Algorithm 11): one task then runs the forward (or
+// backward) substitution of a diagonal block of at most a few hundred rows,
+// in the order of the recursion, with the block's rows of the panel held in
+// LDS from its first micro-operation to its last.  The micro-operations (leaf
+// triangular solves, dense and low-rank leaf products) read the factors from
+// global memory; a product from the neighbouring block (folded into the task
+// because it is the last update the block waits for) reads its source rows
+// from the global panel.  A panel wider than the LDS copy holds is done in
+// column sweeps.
+// ---------------------------------------------------------------------------
+struct SeqPanel {
+  double* p;  // the block's rows of columns [j0, j0 + cw), leading dimension W
+  int W, cw, j0;
+};
+
+// block rows y += alpha A x; A global (m x k); x block rows or global rows
+__device__ void seq_gemm(const ExecArgs& a, const Task& u, const SeqPanel& sp, char* lds) {
+  const RV A = resolve(a, u.a);
+  const int m = A.rows, k = A.cols, cw = sp.cw;
+  if (m == 0 || k == 0) return;
+  double* Y = sp.p + u.y.off;
+  const bool xl = (u.b.dyn & DYN_LOCAL) != 0;
+  const RV B = resolve(a, u.b);
+  const double alpha = u.alpha;
+  const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+  const int kc = min(k, kLdsDoubles / (m + (xl ? 0 : cw)));
+  double* lA = (double*)lds;
+  for (int k0 = 0; k0 < k; k0 += kc) {
+    const int kk = min(kc, k - k0);
+    double* lX = lA + m * kk;
+    RV As = A;
+    As.off += (int64_t)k0 * A.cs;
+    As.cols = kk;
+    StageSrc sx = none;
+    if (!xl) {
+      RV Bs = B;
+      Bs.off += (int64_t)k0 * B.rs + (int64_t)sp.j0 * B.cs;
+      Bs.rows = kk;
+      Bs.cols = cw;
+      sx = StageSrc{Bs, lX, nullptr};
+    }
+    stage_views(a, {As, lA, nullptr}, sx, none, none);
+    __syncthreads();
+    const double* xs = xl ? sp.p + u.b.off + k0 : lX;
+    const int ldx = xl ? sp.W : kk;
+    mfma_lds_gemm<double>(m, cw, kk, lA, m, xs, ldx, [&](int i, int j, double v) { Y[i + j * sp.W] += alpha * v; });
+    __syncthreads();
+  }
+}
+
+// block rows y += alpha U (V^T x); U (m x k) and V^T (k x n2) global
+__device__ void seq_lrgemm(const ExecArgs& a, const Task& u, const SeqPanel& sp, char* lds) {
+  const RV U = resolve(a, u.a), Vt = resolve(a, u.b);
+  const int m = U.rows, k = U.cols, n2 = Vt.cols, cw = sp.cw;
+  if (m == 0 || k == 0 || n2 == 0) return;
+  double* Y = sp.p + u.y.off;
+  const bool xl = (u.x.dyn & DYN_LOCAL) != 0;
+  const RV X = resolve(a, u.x);
+  const double alpha = u.alpha;
+  const StageSrc none{RV{0, 0, 0, 1, 1, VT_NONE}, nullptr, nullptr};
+  const int room = kLdsDoubles - k * cw;
+  double* lB = (double*)lds;
+  double* lT = lB + room;  // T = V^T x (k x cw)
+  const int nc = min(n2, room / (k + (xl ? 0 : cw)));
+  for (int c0 = 0; c0 < n2; c0 += nc) {
+    const int nn = min(nc, n2 - c0);
+    double* lX = lB + k * nn;
+    RV Bs = Vt;
+    Bs.off += (int64_t)c0 * Vt.cs;
+    Bs.cols = nn;
+    StageSrc sx = none;
+    if (!xl) {
+      RV Xs = X;
+      Xs.off += (int64_t)c0 * X.rs + (int64_t)sp.j0 * X.cs;
+      Xs.rows = nn;
+      Xs.cols = cw;
+      sx = StageSrc{Xs, lX, nullptr};
+    }
+    stage_views(a, {Bs, lB, nullptr}, sx, none, none);
+    __syncthreads();
+    const double* xs = xl ? sp.p + u.x.off + c0 : lX;
+    const int ldx = xl ? sp.W : nn;
+    const bool first = c0 == 0;
+    mfma_lds_gemm<double>(k, cw, nn, lB, k, xs, ldx,
+                          [&](int i, int j, double v) { lT[i + j * k] = first ? v : lT[i + j * k] + v; });
+    __syncthreads();
+  }
+  const int mc = min(m, room / k);
+  for (int r0 = 0; r0 < m; r0 += mc) {
+    const int mm = min(mc, m - r0);
+    RV Us = U;
+    Us.off += (int64_t)r0 * U.rs;
+    Us.rows = mm;
+    stage_views(a, {Us, lB, nullptr}, none, none, none);
+    __syncthreads();
+    mfma_lds_gemm<double>(mm, cw, k, lB, mm, lT, k,
+                          [&](int i, int j, double v) { Y[r0 + i + j * sp.W] += alpha * v; });
+    __syncthreads();
+  }
+}
+
+// triangular solve of a diagonal leaf on the block rows (kind 0: L with the
+// leaf's interchanges, kind 2: U)
+__device__ void seq_trsm(const ExecArgs& a, const Task& u, const SeqPanel& sp, char* lds, int kind) {
+  const int m = u.a.rows, c = sp.cw, W = sp.W;
+  if (m == 0) return;
+  double* X = sp.p + u.x.off;
+  const double* g = a.f64 + u.a.off;
+  const int32_t* perm = a.piv + u.piv + m;
+  if (u.b.type == VT_F64 && (int64_t)m * m + (int64_t)m * c <= kLdsDoubles) {
+    // x <- T^{-1} (P x) with the leaf's inverse (see op_trsm)
+    double* lI = (double*)lds;
+    double* lX = lI + m * m;
+    copy_batched(lI, a.f64 + u.b.off, m * m);
+    for (int e = threadIdx.x; e < m * c; e += blockDim.x) {
+      const int i = e % m, j = e / m;
+      lX[e] = X[(kind == 0 ? perm[i] : i) + j * W];
+    }
+    __syncthreads();
+    mfma_lds_gemm<double>(m, c, m, lI, m, lX, m, [&](int i, int j, double v) { X[i + j * W] = v; });
+    return;
+  }
+  double* sL = (double*)lds;
+  const double* T = g;
+  double* rdiag = nullptr;
+  if ((int64_t)m * m + m <= kLdsDoubles) {
+    copy_batched(sL, g, m * m);
+    __syncthreads();
+    T = sL;
+    if (kind == 2) {
+      rdiag = sL + m * m;
+      for (int i = threadIdx.x; i < m; i += blockDim.x) rdiag[i] = 1.0 / sL[i * m + i];
+      __syncthreads();
+    }
+  }
+  auto ld = [&](int, int src, int j) { return X[src + j * W]; };
+  auto st = [&](int i, int j, double v) { X[i + j * W] = v; };
+  const int per = (c + 3) / 4;
+  if (m <= 64) {
+    if (per <= 2)
+      trsm_wave_core<1, 2>(T, m, kind, perm, c, rdiag, ld, st);
+    else if (per <= 4)
+      trsm_wave_core<1, 4>(T, m, kind, perm, c, rdiag, ld, st);
+    else if (per <= 8)
+      trsm_wave_core<1, 8>(T, m, kind, perm, c, rdiag, ld, st);
+    else
+      trsm_wave_core<1, 16>(T, m, kind, perm, c, rdiag, ld, st);
+  } else {
+    if (per <= 2)
+      trsm_wave_core<2, 2>(T, m, kind, perm, c, rdiag, ld, st);
+    else
+      trsm_wave_core<2, 8>(T, m, kind, perm, c, rdiag, ld, st);
+  }
+}
+
+__device__ void op_seq(const ExecArgs& a, const Task& t, char* lds) {
+  const RV P = resolve(a, t.y);
+  const int W = P.rows, c = P.cols, n = t.lr;
+  if (W == 0 || c == 0 || n == 0) return;
+  const int cmax = a.seq_panel / W;
+  if (cmax < 1 || P.rs != 1 || !a.seq) {
+    if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
+    return;
+  }
+  const int nsw = (c + cmax - 1) / cmax, cwid = (c + nsw - 1) / nsw;
+  double* pl = (double*)(lds + kSeqPanelOff);
+  Task* rec = (Task*)(lds + kSeqLdsOff);
+  constexpr int kWords = (int)(sizeof(Task) / 4);
+  const int* src = (const int*)(a.seq + t.piv);
+  const int tid = threadIdx.x;
+  // timeline (debug): ticks of the triangular solves, dense products,
+  // low-rank products and panel copies, and the counts of the first two kinds
+  unsigned long long* ph = a.trace ? (unsigned long long*)(lds + kLdsBytes) + kCtrSize : nullptr;
+  uint64_t tk0 = 0;
+  for (int j0 = 0; j0 < c; j0 += cwid) {
+    const int cw = min(cwid, c - j0), tot = W * cw;
+    double* g = a.f64 + P.off + (int64_t)j0 * P.cs;
+    if (ph && tid == 0) tk0 = wall_clock64();
+    for (int base = 0; base < tot; base += 8 * kThreads) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = base + q * kThreads + tid;
+        v[q] = e < tot ? g[e % W + (int64_t)(e / W) * P.cs] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = base + q * kThreads + tid;
+        if (e < tot) pl[e] = v[q];
+      }
+    }
+    if (tid < kWords) ((int*)rec)[tid] = src[tid];
+    __syncthreads();
+    if (ph && tid == 0) {
+      ph[3] += wall_clock64() - tk0;
+      tk0 = wall_clock64();
+    }
+    const SeqPanel sp{pl, W, cw, j0};
+    for (int k = 0; k < n; ++k) {
+      const Task& u = rec[k & 1];
+      const int uop = u.op;
+      // the next record is loaded while this micro-operation runs
+      int nxt = 0;
+      if (k + 1 < n && tid < kWords) nxt = src[(k + 1) * kWords + tid];
+      switch (u.op) {
+        case OP_TRSM_L:
+          seq_trsm(a, u, sp, lds, 0);
+          break;
+        case OP_TRSM_U:
+          seq_trsm(a, u, sp, lds, 2);
+          break;
+        case OP_GEMM:
+          seq_gemm(a, u, sp, lds);
+          break;
+        case OP_LRGEMM:
+          seq_lrgemm(a, u, sp, lds);
+          break;
+        default:
+          if (tid == 0) atomicOr(&a.status[0], ST_BADOP);
+          break;
+      }
+      if (k + 1 < n && tid < kWords) ((int*)&rec[(k + 1) & 1])[tid] = nxt;
+      __syncthreads();
+      if (ph && tid == 0) {
+        const uint64_t t1 = wall_clock64();
+        const int slot = (uop == OP_TRSM_L || uop == OP_TRSM_U) ? 0 : uop == OP_GEMM ? 1 : 2;
+        ph[slot] += t1 - tk0;
+        ph[slot == 0 ? 4 : 5] += 1;
+        tk0 = t1;
+      }
+    }
+    for (int base = 0; base < tot; base += 8 * kThreads) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = base + q * kThreads + tid;
+        if (e < tot) g[e % W + (int64_t)(e / W) * P.cs] = pl[e];
+      }
+    }
+    __syncthreads();
+    if (ph && tid == 0) ph[3] += wall_clock64() - tk0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2415,7 +2752,7 @@ __device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
     RV x = resolve(a, t.x);
     int64_t m = t.a.rows;
     bytes = m * m * 8 + 2 * vbytes(x);
-    flops = m * m * x.cols;
+    flops = (t.b.type == VT_F64 ? 2 : 1) * m * m * x.cols;
   } else if (t.op == OP_GEMM) {
     RV y = resolve(a, t.y), A = resolve(a, t.a), B = resolve(a, t.b);
     bytes = vbytes(A) + vbytes(B) + (t.beta != 0.0 ? 2 : 1) * vbytes(y);
@@ -2433,6 +2770,12 @@ __device__ void count_task(const ExecArgs& a, const Task& t, char* lds) {
   } else if (t.op == OP_COPY) {
     RV y = resolve(a, t.y);
     bytes = 2 * vbytes(y);
+  } else if (t.op == OP_TRTRI) {
+    int64_t m = t.a.rows;
+    bytes = 3 * m * m * 8;
+    flops = 2 * m * m * m / 3;
+  } else if (t.op == OP_SEQ) {
+    bytes = 2 * vbytes(resolve(a, t.y));  // the block's panel rows (its micro-operations are not counted)
   }
   wg_ctr(lds)[0] += bytes;
   wg_ctr(lds)[1] += flops;
@@ -2502,7 +2845,7 @@ __device__ void account_task(const ExecArgs& a, int id, char* lds) {
     // output rows / columns and the inner dimension
     const View& o = (t.op == OP_GETRF) ? t.a : (t.op >= OP_TRSM_L && t.op <= OP_TRSM_U) ? t.x : t.y;
     const RV r = resolve(a, o);
-    const int kd = (t.op == OP_GEMM || t.op == OP_LRGEMM) ? resolve(a, t.a).cols : t.a.rows;
+    const int kd = (t.op == OP_GEMM || t.op == OP_LRGEMM) ? resolve(a, t.a).cols : t.op == OP_SEQ ? t.lr : t.a.rows;
     info |= (uint64_t)(r.rows & 0xffff) << 16 | (uint64_t)(r.cols & 0xffff) << 32 | (uint64_t)(kd & 0xffff) << 48;
   }
   tr[2] = info;
@@ -2528,7 +2871,7 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
   // part of a fused DAG computes exactly as the H-LU's own DAG
   const bool sub = kSub && (!kLU || t.c1 == 1);
   if ((!kLU && (t.op == OP_GETRF || t.op == OP_TRSM_UT || t.op == OP_TRUNC || t.op == OP_TRUNC2)) ||
-      (!kSub && t.op == OP_GEMMP)) {
+      (!kSub && t.op == OP_GEMMP) || (kLU && t.op == OP_SEQ) || (!kLU && t.op == OP_TRTRI)) {
     if (threadIdx.x == 0) atomicOr(&a.status[0], ST_BADOP);
     return;
   }
@@ -2563,6 +2906,12 @@ __device__ void run_task_body(const ExecArgs& a, const Task& t, char* lds, doubl
       break;
     case OP_GEMMP:
       if (kSub) op_gemmp(a, t, lds);
+      break;
+    case OP_SEQ:
+      if (!kLU) op_seq(a, t, lds);
+      break;
+    case OP_TRTRI:
+      if (kLU) op_trtri(a, t, lds);
       break;
     case OP_TRUNC:
     case OP_TRUNC2:

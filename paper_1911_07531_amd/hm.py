@@ -21,7 +21,7 @@ LAPLACE3D, LOG2D = 0, 1
 DATAFLOW, LEVEL = 0, 1
 
 OP_NAMES = ["nop", "getrf", "trsm_l", "trsm_ut", "trsm_u", "gemm", "lrgemm", "trunc", "zero", "copy", "trunc2",
-            "gemmp"]
+            "gemmp", "seq", "trtri"]
 
 
 class HmError(RuntimeError):
@@ -33,7 +33,7 @@ class HmError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("leaf", C.c_int), ("eta", C.c_double), ("eps", C.c_double), ("max_rank", C.c_int),
-                ("prec", C.c_int), ("exec", C.c_int), ("lazy", C.c_int)]
+                ("prec", C.c_int), ("exec", C.c_int), ("lazy", C.c_int), ("coarsen", C.c_int)]
 
 
 class Tuning(C.Structure):
@@ -44,9 +44,9 @@ class Tuning(C.Structure):
 
 class LuStats(C.Structure):
     _fields_ = [("ntasks", C.c_int64), ("nedges", C.c_int64), ("nlevels", C.c_int64),
-                ("tasks_by_op", C.c_int64 * 12), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
+                ("tasks_by_op", C.c_int64 * 16), ("bytes_alg", C.c_int64), ("flops_alg", C.c_int64),
                 ("exec_ms", C.c_double), ("temp_bytes", C.c_int64), ("rank_overflows", C.c_int64),
-                ("op_busy_ms", C.c_double * 12), ("trunc_phase_ms", C.c_double * 12),
+                ("op_busy_ms", C.c_double * 16), ("trunc_phase_ms", C.c_double * 12),
                 ("trunc_mean_k", C.c_double), ("trunc_mean_mn", C.c_double)]
 
 
@@ -66,7 +66,7 @@ def exported_symbols():
             "h_solve", "h_matvec", "hm_footprint", "hm_export_leaf", "hm_lu_stats_get", "hm_dag_sizes",
             "hm_dag_export", "hm_dag_calls", "hm_semiauto_dag", "hm_lu_trace", "hm_tree_free", "hm_matrix_free", "hm_lu_free", "hm_last_error",
             "h_solve_async", "h_solve_noalloc", "h_lu_batched", "hm_batch_dag_export", "hm_get_tuning",
-            "hm_set_tuning", "hm_import"]
+            "hm_set_tuning", "hm_import", "hm_dag_seq_export", "hm_solve_trace"]
 
 
 def lib():
@@ -106,7 +106,9 @@ def lib():
         "hm_lu_stats_get": [vp, C.POINTER(LuStats)],
         "hm_dag_sizes": [vp, C.POINTER(Opts), ip, vp],
         "hm_dag_export": [vp, C.POINTER(Opts), ip, vp, vp, vp, vp, vp, vp],
+        "hm_dag_seq_export": [vp, C.POINTER(Opts), ip, C.POINTER(i64), vp],
         "hm_lu_trace": [vp, vp, C.POINTER(i64), C.POINTER(i64)],
+        "hm_solve_trace": [vp, vp, C.POINTER(i64), C.POINTER(i64)],
         "hm_dag_calls": [vp, C.POINTER(Opts), ip, C.POINTER(i64), vp, vp],
         "hm_semiauto_dag": [vp, ip, ip, C.POINTER(i64), C.POINTER(i64), vp, vp],
     }
@@ -160,8 +162,8 @@ def _check(code: int, info: int = 0):
         raise HmError(code, lib().hm_last_error().decode(), info)
 
 
-def make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=FP64, exec_mode=DATAFLOW, lazy=1) -> Opts:
-    return Opts(int(leaf), float(eta), float(eps), int(max_rank), int(prec), int(exec_mode), int(lazy))
+def make_opts(leaf=32, eta=2.0, eps=1e-6, max_rank=0, prec=FP64, exec_mode=DATAFLOW, lazy=1, coarsen=0) -> Opts:
+    return Opts(int(leaf), float(eta), float(eps), int(max_rank), int(prec), int(exec_mode), int(lazy), int(coarsen))
 
 
 def _stream_ptr(stream):
@@ -216,6 +218,12 @@ class Tree:
         _check(lib().hm_tree_export(self.h, perm.ctypes.data, cl.ctypes.data, box.ctypes.data, bl.ctypes.data))
         return perm, cl, box, bl
 
+    def dag_sizes(self, opts: Opts, which: int = 0) -> dict:
+        """Sizes of a traced DAG (hm_dag_sizes; host only): tasks, edges, levels."""
+        sz = np.zeros(9, np.int64)
+        _check(lib().hm_dag_sizes(self.h, C.byref(opts), which, sz.ctypes.data))
+        return {"tasks": int(sz[0]), "edges": int(sz[1]), "levels": int(sz[2])}
+
     def calls(self, opts: Opts, which: int = 0):
         """(calls (ncalls, 4) int32, task_call (ntasks,) int32) of a traced DAG (hm_dag_calls)."""
         nc = C.c_int64(0)
@@ -252,8 +260,14 @@ class Tree:
         lr = np.zeros((max(1, nlr), 6), np.int64)
         _check(lib().hm_dag_export(self.h, C.byref(opts), which, tasks.ctypes.data, sp.ctypes.data, si.ctypes.data,
                                    lv.ctypes.data, boff.ctypes.data, lr.ctypes.data))
+        nseq = C.c_int64(0)
+        _check(lib().hm_dag_seq_export(self.h, C.byref(opts), which, C.byref(nseq), None))
+        seq = np.zeros(nseq.value, TASK_DTYPE)
+        if nseq.value:
+            _check(lib().hm_dag_seq_export(self.h, C.byref(opts), which, C.byref(nseq), seq.ctypes.data))
         return dict(tasks=tasks, succ_ptr=sp, succ_idx=si[:nedges], level=lv[:ntasks], block_off=boff,
-                    lr=lr[:nlr], n_f64=n64, n_f32=n32, n_piv=npiv, nranks=nranks, nlevels=nlevels, nedges=nedges)
+                    lr=lr[:nlr], n_f64=n64, n_f32=n32, n_piv=npiv, nranks=nranks, nlevels=nlevels, nedges=nedges,
+                    seq=seq)
 
 
 class Matrix:
@@ -368,8 +382,8 @@ class LU:
         ph = ["gram", "cholesky", "core", "svd", "solve", "rebuild"]
         d["trunc_phase_ms"] = dict(zip([f"{x}_small" for x in ph] + [f"{x}_large" for x in ph],
                                        [float(x) for x in s.trunc_phase_ms]))
-        d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(11) if s.tasks_by_op[i]}
-        d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(11) if s.tasks_by_op[i]}
+        d["tasks_by_op"] = {OP_NAMES[i]: int(s.tasks_by_op[i]) for i in range(len(OP_NAMES)) if s.tasks_by_op[i]}
+        d["op_busy_ms"] = {OP_NAMES[i]: float(s.op_busy_ms[i]) for i in range(len(OP_NAMES)) if s.tasks_by_op[i]}
         return d
 
     def leaf(self, block: int):
@@ -385,6 +399,15 @@ class LU:
         _check(lib().hm_lu_trace(self.h, None, C.byref(n), C.byref(khz)))
         out = np.zeros((n.value, 8), np.uint64)
         _check(lib().hm_lu_trace(self.h, out.ctypes.data, C.byref(n), C.byref(khz)))
+        return out, khz.value
+
+    def solve_timeline(self):
+        """The last substitution pass's (ntasks, 8) task records as in timeline() and the tick rate
+        in kHz (needs HM_DEBUG_TRACE=1 before the factorization)."""
+        n, khz = C.c_int64(), C.c_int64()
+        _check(lib().hm_solve_trace(self.h, None, C.byref(n), C.byref(khz)))
+        out = np.zeros((n.value, 8), np.uint64)
+        _check(lib().hm_solve_trace(self.h, out.ctypes.data, C.byref(n), C.byref(khz)))
         return out, khz.value
 
     def footprint(self, kind=1) -> int:

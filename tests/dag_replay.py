@@ -12,7 +12,7 @@ import numpy as np
 import scipy.linalg as sla
 
 VT_F64, VT_F32, VT_IDENT, VT_NONE = 0, 1, 2, 3
-DYN_ROWS, DYN_COLS, DYN_COLS2 = 1, 2, 4
+DYN_ROWS, DYN_COLS, DYN_COLS2, DYN_LOCAL = 1, 2, 4, 8
 
 
 class Replay:
@@ -92,6 +92,25 @@ class Replay:
             lu, piv = sla.lu_factor(np.array(a, np.float64), check_finite=False)
             a[:] = lu
             self.piv[int(t["piv"]):int(t["piv"]) + m] = piv
+            perm = np.arange(m)
+            for j, q in enumerate(piv):  # (P x)[i] = x[perm[i]]
+                perm[[j, q]] = perm[[q, j]]
+            self.piv[int(t["piv"]) + m:int(t["piv"]) + 2 * m] = perm
+        elif op in (2, 4) and int(t["b"]["type"]) == VT_F64:  # substitution with the leaf's inverse
+            m = int(t["a"]["rows"])
+            inv = np.array(self.view(t["b"]), np.float64)
+            x = self.view(t["x"])
+            xs = np.array(x, np.float64)
+            if op == 2:
+                xs = xs[self.piv[int(t["piv"]) + m:int(t["piv"]) + 2 * m]]
+            x[:] = inv @ xs
+        elif op == 13:  # inverses of the triangles of a factored diagonal leaf
+            m = int(t["a"]["rows"])
+            lu = np.array(self.view(t["a"]), np.float64)
+            y = self.view(t["y"])
+            eye = np.eye(m)
+            y[:, :m] = sla.solve_triangular(lu, eye, lower=True, unit_diagonal=True, check_finite=False)
+            y[:, m:] = sla.solve_triangular(lu, eye, lower=False, check_finite=False)
         elif op in (2, 3, 4):
             m = int(t["a"]["rows"])
             a = np.array(self.view(t["a"]), np.float64)
@@ -139,6 +158,17 @@ class Replay:
                 bv["off"] = int(t["b"]["off"]) + p * int(t["piv"])
                 bsum = bsum + np.asarray(self.view(bv), np.float64)
             y[:] = np.asarray(y, np.float64) + t["alpha"] * (np.asarray(self.view(t["a"]), np.float64) @ bsum)
+        elif op == 12:  # coarsened substitution block: its micro-operations in order
+            base = int(t["y"]["off"])
+            first, count = int(t["piv"]), int(t["lr"])
+            for k in range(first, first + count):
+                u = self.d["seq"][k:k + 1].copy()
+                for key in ("y", "a", "b", "x"):
+                    if int(u[key]["dyn"][0]) & DYN_LOCAL:  # rows relative to the block
+                        u[key]["off"][0] = base + int(u[key]["off"][0])
+                        u[key]["dyn"][0] = int(u[key]["dyn"][0]) & ~DYN_LOCAL
+                assert int(u["op"][0]) in (2, 4, 5, 6), int(u["op"][0])
+                self.run_task(u[0])
         else:
             raise ValueError(op)
 

@@ -65,18 +65,28 @@ def test_replay_matches_oracle_hlu(n, leaf, eps, max_rank, orders):
                 assert np.array_equal(b.piv, ob.piv)
 
 
-@pytest.mark.parametrize("split", [None, "12"])
-def test_replay_solve_matches_oracle(split, monkeypatch):
+@pytest.mark.parametrize("split,coarsen", [(None, 0), ("12", 0), (None, 128), ("12", 256), (None, 40)])
+def test_replay_solve_matches_oracle(split, coarsen, monkeypatch):
     """The substitution DAG, with the large low-rank products split into
-    partial products and their sums (split = 12 rows) or not."""
+    partial products and their sums (split = 12 rows) or not, and with the
+    diagonal blocks of at most `coarsen` rows run as one task each (the
+    neighbouring block's product folded in) or not."""
     if split is not None:
         monkeypatch.setenv("HM_SOLVE_SPLIT", split)
     n, leaf, eps = 512, 32, 1e-6
     t, opts, a = _setup(n, leaf, 2.0, eps, 0)
+    opts.coarsen = coarsen
     ref = H.hlu(a)
     dag = t.dag(opts, 0)
     sdag = t.dag(opts, 1)
-    assert (sdag["tasks"]["op"] == 11).any() == (split is not None)
+    if coarsen == 0:
+        assert (sdag["tasks"]["op"] == 11).any() == (split is not None)
+    else:
+        seq = sdag["seq"]
+        assert (sdag["tasks"]["op"] == 12).any() and len(seq) > 0
+        # some neighbour products were folded into the blocks' tasks (source rows outside the block)
+        src_dyn = np.where(seq["op"] == 5, seq["b"]["dyn"], seq["x"]["dyn"])
+        assert ((np.isin(seq["op"], (5, 6))) & ((src_dyn & 8) == 0)).any()
     blocks = {b.index: b for b in H.leaf_blocks(a.root)}
     rp = Replay(dag, eps, 0)
     rp.load_matrix(blocks, dag["block_off"], dag["lr"])
@@ -89,12 +99,9 @@ def test_replay_solve_matches_oracle(split, monkeypatch):
     b = inputs.rhs(n, 5, seed=1)
     nrhs_slot = sdag["nranks"] - 1
     rs.ranks[nrhs_slot] = 5
-    panel_off = [int(tk["x"]["off"]) for tk in sdag["tasks"] if tk["op"] == 2][0]
-    # the panel is the view written by the first lower solve: rows start at its offset minus its row shift
-    first = sdag["tasks"][0]
-    del first
-    po = min(int(tk["x"]["off"]) for tk in sdag["tasks"] if tk["op"] in (2, 4))
-    assert po <= panel_off
+    # the panel: the lowest offset a triangular solve or a coarsened block writes
+    po = min([int(tk["x"]["off"]) for tk in sdag["tasks"] if tk["op"] in (2, 4)] +
+             [int(tk["y"]["off"]) for tk in sdag["tasks"] if tk["op"] == 12])
     rs.f64[po:po + n * 5] = b[a.perm].flatten(order="F")
     rs.run(np.random.default_rng(4))
     x = np.empty((n, 5))

@@ -190,17 +190,21 @@ def test_mixed_precision_c1():
 
 def test_solve_executors_identical(monkeypatch):
     """The substitution DAG gives bit-identical solutions level by level and
-    with the persistent executor."""
-    p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False)
+    with the persistent executor, also with refinement and with 64 columns."""
+    p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False, prec=hm.MIXED)
     f = hm.LU(p.A, p.opts)
-    b = inputs.rhs(p.n, 5, seed=3)
-    out = []
-    for mode in ("level", "dataflow"):
-        monkeypatch.setenv("HM_SOLVE_EXEC", mode)
-        x = device_rhs(b)
-        f.solve(x)
-        out.append(to_host(x))
-    assert np.array_equal(out[0], out[1])
+    for nr in (5, 64):
+        b = inputs.rhs(p.n, nr, seed=3)
+        out = []
+        for mode in ("level", "dataflow"):
+            monkeypatch.setenv("HM_SOLVE_EXEC", mode)
+            x = device_rhs(b)
+            f.solve(x)
+            y = device_rhs(b)
+            f.solve(y, refine_with=p.A, rtol=1e-10, max_iter=20)
+            out.append((to_host(x), to_host(y)))
+        for o in out[1:]:
+            assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
 
 
 def test_reused_temporaries_on_device(monkeypatch):
@@ -244,6 +248,49 @@ def test_split_solve_products(monkeypatch):
     assert np.array_equal(out[("0", "level")], out[("0", "dataflow")])
     ref = out[("0", "level")]
     assert np.max(np.abs(out[("128", "level")] - ref)) <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])
+def test_coarsened_solve(prec, monkeypatch):
+    """The substitution with diagonal blocks of at most 128, 256 or 512 rows
+    run as one task each (panel rows in LDS, the neighbouring block's product
+    folded in): the leaf-level solution up to rounding (1e-12 relative; the
+    updates of a block are summed in another order), bit-identical on both
+    executors, the solve residual against the oracle's factors within 2x the
+    oracle's own, and the same with 64 right-hand sides (two column sweeps
+    of the LDS copy for the larger blocks)."""
+    p = Problem(4096, 64, 1e-6, max_rank=64, prec=prec)
+    b = inputs.rhs(p.n, 32, seed=3)
+    b64 = inputs.rhs(p.n, 64, seed=5)
+    ref_lu = H.hlu(p.oa, lazy=True)
+    a_user = np.empty((p.n, p.n))
+    a_user[np.ix_(p.oa.perm, p.oa.perm)] = p.dense_exact()
+    ref_res = np.linalg.norm(b - a_user @ H.solve(ref_lu, b), axis=0) / np.linalg.norm(b, axis=0)
+    sols = {}
+    for c in (0, 128, 256, 512):
+        opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-6, max_rank=64, prec=prec, coarsen=c)
+        if c:
+            sdag = p.tree.dag(opts, 1)
+            assert (sdag["tasks"]["op"] == 12).any()
+        f = hm.LU(p.A, opts)
+        for mode in ("level", "dataflow"):
+            monkeypatch.setenv("HM_SOLVE_EXEC", mode)
+            x = device_rhs(b)
+            f.solve(x)
+            sols[(c, mode)] = to_host(x)
+            x = device_rhs(b64)
+            f.solve(x)
+            sols[(c, mode, 64)] = to_host(x)
+        assert np.array_equal(sols[(c, "level")], sols[(c, "dataflow")]), c
+        assert np.array_equal(sols[(c, "level", 64)], sols[(c, "dataflow", 64)]), c
+    ref, ref64 = sols[(0, "dataflow")], sols[(0, "dataflow", 64)]
+    for c in (128, 256, 512):
+        d = np.max(np.abs(sols[(c, "dataflow")] - ref)) / np.abs(ref).max()
+        d64 = np.max(np.abs(sols[(c, "dataflow", 64)] - ref64)) / np.abs(ref64).max()
+        print(f"coarsen {c}: relative difference to the leaf-level solve {d:.1e} (32 RHS), {d64:.1e} (64 RHS)")
+        assert d <= 1e-12 and d64 <= 1e-12, (c, d, d64)
+        res = np.linalg.norm(b - a_user @ sols[(c, "dataflow")], axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(res <= 2 * ref_res + 1e-12), (c, res.max(), ref_res.max())
 
 
 @pytest.mark.parametrize("prec", [hm.FP64, hm.MIXED])

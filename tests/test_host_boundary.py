@@ -105,8 +105,11 @@ def test_dag_is_forward_and_levels_consistent(prec):
         assert np.all(lv[si] >= lv[src] + 1)    # levels are a valid schedule
         assert lv.max() + 1 == d["nlevels"]
         ops = d["tasks"]["op"]
-        # the substitution DAG alone also holds sums of split partial products (11)
-        assert set(np.unique(ops)) <= set(range(1, 12 if which == 1 else 11))
+        # the substitution DAG alone holds sums of split partial products (11); the
+        # factorization's DAGs invert the factored diagonal leaves (13) instead
+        assert set(np.unique(ops)) <= (set(range(1, 12)) if which == 1 else set(range(1, 11)) | {13})
+        if which != 1:
+            assert (ops == 13).sum() == (ops == 1).sum()  # one inversion per factored leaf
     # every diagonal leaf is factored exactly once, in order along the diagonal
     d = t.dag(opts, 0)
     getrf = d["tasks"][d["tasks"]["op"] == 1]
