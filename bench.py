@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--lazy", type=int, default=1, choices=[0, 1, 2],
                     help="update scheme: 0 sequential, 1 collected per hmul call (default), "
                          "2 accumulated H-LU (Algorithms 4-8)")
-    ap.add_argument("--coarsen", type=int, default=0,
+    ap.add_argument("--coarsen", type=int, default=64,
                     help="substitution: diagonal blocks of at most this many rows run as one task (0 = leaf tasks)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (to scale HBM counters) and exit")

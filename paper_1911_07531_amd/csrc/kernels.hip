@@ -1659,42 +1659,70 @@ __device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, i
 }
 
 
-// G = X^T X (K x K, row-major) for X = the stacked panel st (m x K), staged
-// through LDS in chunks of up to `cap_rows` rows.
+// G = X^T X (K x K, row-major, K <= 32) for X = the stacked panel st (m x K),
+// staged through LDS in chunks of up to `cap_rows` rows, on the matrix cores
+// in FP64: wavefront w takes the rows 4 w + 16 s .. + 3 of every chunk into
+// its own 16 x 16 tiles of G (both MFMA operands are columns of X), and the
+// four wavefronts' tiles are summed in LDS at the end (the staging buffer,
+// free by then, holds them).
 __device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, double* G,
                             double* buf, int cap_rows) {
-  const int tid = threadIdx.x;
-  const int ld = cap_rows | 1;  // odd stride: conflict-free column reads
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // K*K <= 1024 entries: at most 4 per thread
+  using M = Mfma<double>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nt = (K + 15) >> 4;  // 1 or 2 tiles per side
+  const int ld = cap_rows | 1;   // odd stride: conflict-free column reads
+  M::acc_t acc00 = M::zero(), acc01 = M::zero(), acc11 = M::zero();
+  const int c0 = li, c1 = 16 + li;
   for (int r0 = 0; r0 < m; r0 += cap_rows) {
     const int rows = min(cap_rows, m - r0);
     // every chunk in batches of sixteen loads per thread over all columns
     stage_desc(desc, K, r0, rows, buf, ld);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      if (e < K * K) {
-        const double* xi = buf + (e / K) * ld;
-        const double* xj = buf + (e % K) * ld;
-        double s0 = 0.0, s1 = 0.0;
-        int t = 0;
-#pragma unroll 4
-        for (; t + 1 < rows; t += 2) {
-          s0 += xi[t] * xj[t];
-          s1 += xi[t + 1] * xj[t + 1];
-        }
-        if (t < rows) s0 += xi[t] * xj[t];
-        acc[q] += s0 + s1;
+    for (int t0 = 4 * wave; t0 < rows; t0 += 16) {
+      const int t = t0 + lk;
+      const bool in = t < rows;
+      const double x0 = (in && c0 < K) ? buf[c0 * ld + t] : 0.0;
+      const double x1 = (in && c1 < K) ? buf[c1 * ld + t] : 0.0;
+      acc00 = M::step(x0, x0, acc00);
+      if (nt > 1) {
+        acc01 = M::step(x0, x1, acc01);
+        acc11 = M::step(x1, x1, acc11);
       }
     }
     __syncthreads();
   }
+  // per-wavefront tiles (00, 01, 11) to LDS, then the sum over wavefronts
+  double* red = buf;  // 4 wavefronts x 3 tiles x 256
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + q * 256;
-    if (e < K * K) G[e] = acc[q];
+  for (int r = 0; r < 4; ++r) {
+    const int e = M::row(lk, r) * 16 + li;
+    red[(wave * 3 + 0) * 256 + e] = acc00[r];
+    red[(wave * 3 + 1) * 256 + e] = acc01[r];
+    red[(wave * 3 + 2) * 256 + e] = acc11[r];
   }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += blockDim.x) {
+    const int i = e / K, j = e % K;
+    // G(i, j) from tile (ti, tj); the lower tile (1, 0) is the transpose of (0, 1)
+    const int ti = i >> 4, tj = j >> 4;
+    int tile, ii = i & 15, jj = j & 15;
+    if (ti == 0 && tj == 0)
+      tile = 0;
+    else if (ti == 1 && tj == 1)
+      tile = 2;
+    else {
+      tile = 1;
+      if (ti == 1) {  // (1, 0): entry (jj, ii) of tile (0, 1)
+        const int x = ii;
+        ii = jj;
+        jj = x;
+      }
+    }
+    const int idx = tile * 256 + ii * 16 + jj;
+    G[e] = (red[idx] + red[3 * 256 + idx]) + (red[6 * 256 + idx] + red[9 * 256 + idx]);
+  }
+  __syncthreads();
 }
 
 // Scaled, diagonally pivoted Cholesky of G (K x K, K <= 128) by the calling
@@ -1842,13 +1870,7 @@ __device__ void rebuild_stream(const ExecArgs& a, const Stack& st, const ColDesc
     // every chunk in batches of sixteen loads per thread over all columns
     stage_desc(desc, K, r0, rows, buf, ld);
     __syncthreads();
-    for (int e = tid; e < rows * kk; e += blockDim.x) {
-      int i = e % rows, c = e / rows;
-      const double* tc = T + c * K;
-      double acc = 0.0;
-      for (int l = 0; l < K; ++l) acc += buf[l * ld + i] * tc[l];
-      vst(a, out, r0 + i, c, acc);
-    }
+    mfma_lds_gemm<double>(rows, kk, K, buf, ld, T, K, [&](int i, int c, double v) { vst(a, out, r0 + i, c, v); });
     __syncthreads();
   }
 }

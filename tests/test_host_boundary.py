@@ -107,7 +107,8 @@ def test_dag_is_forward_and_levels_consistent(prec):
         ops = d["tasks"]["op"]
         # the substitution DAG alone holds sums of split partial products (11); the
         # factorization's DAGs invert the factored diagonal leaves (13) instead
-        assert set(np.unique(ops)) <= (set(range(1, 12)) if which == 1 else set(range(1, 11)) | {13})
+        # coarsened diagonal blocks (12) with the default coarsening
+        assert set(np.unique(ops)) <= (set(range(1, 13)) if which == 1 else set(range(1, 11)) | {13})
         if which != 1:
             assert (ops == 13).sum() == (ops == 1).sum()  # one inversion per factored leaf
     # every diagonal leaf is factored exactly once, in order along the diagonal
