@@ -141,6 +141,7 @@ struct DevDag {
   int64_t ntasks = 0, nlevels = 0, nedges = 0;
   DevBuf tasks, indeg, succ_ptr, succ_idx, roots, order;
   DevBuf seq;  // micro-operations of coarsened substitution blocks (OP_SEQ)
+  DevBuf succ_crit;  // per edge: successor near the critical path
   int32_t nroots = 0;
   std::vector<int32_t> level_ptr;
 };
@@ -336,6 +337,7 @@ static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
   if ((st = upload(dd.roots, d.roots, s))) return st;
   if ((st = upload(dd.order, d.level_order, s))) return st;
   if (!d.seq.empty() && (st = upload(dd.seq, d.seq, s))) return st;
+  if (!d.succ_crit.empty() && (st = upload(dd.succ_crit, d.succ_crit, s))) return st;
   return HM_OK;
 }
 
@@ -413,6 +415,7 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.counters = solve && !es.trace.p ? nullptr : (unsigned long long*)es.counters.p;
   a.trace = (uint64_t*)es.trace.p;
   a.seq = (const Task*)dd.seq.p;
+  a.succ_crit = (const uint8_t*)dd.succ_crit.p;
   a.seq_panel = g_seq_panel;
   if (dd.seq.p && g_seq_panel < 1) return fail(HM_EDEVICE, "no LDS left for coarsened substitution blocks");
   int nwg = exec_workgroups();
@@ -602,6 +605,7 @@ void hm_tree_free(hm_tree t) {
       dev_free(dd->roots);
       dev_free(dd->order);
       dev_free(dd->seq);
+      dev_free(dd->succ_crit);
     }
     dev_free(pe->lr);
   }

@@ -117,6 +117,8 @@ struct ExecArgs {
   const Task* seq;
   int32_t seq_panel;
   int32_t pad1_;
+  // per edge: the successor is near the critical path (null: none flagged)
+  const uint8_t* succ_crit;
 };
 
 

@@ -58,6 +58,9 @@ struct Dag {
   std::vector<int32_t> roots;
   int64_t nedges = 0;
   std::vector<Task> seq;            // micro-operations of the OP_SEQ tasks
+  // per edge (aligned with succ_idx): the successor lies on or near the
+  // critical path of a static duration estimate
+  std::vector<uint8_t> succ_crit;
 };
 
 struct Plan {

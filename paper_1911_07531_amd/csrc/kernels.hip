@@ -3082,14 +3082,17 @@ __device__ __forceinline__ void dataflow_body(const ExecArgs& a, char* lds, int&
       for (int k0 = b; k0 < e; k0 += 64) {
         const int k = k0 + tid;
         int s = -1;
-        bool rel = false;
+        bool rel = false, crit = false;
         if (k < e) {
           s = a.succ_idx[k];
+          if (a.succ_crit) crit = a.succ_crit[k] != 0;
           rel = __hip_atomic_fetch_add(&a.deps[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1;
         }
         if (rel) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-        // substitution tasks only: the H-LU keeps its queue order
-        const bool can_keep = rel && (kMode == kModeSolve || (kMode == kModeFused && a.tasks[s].c1 == 1));
+        // kept: substitution tasks, and H-LU tasks near the critical path; the
+        // other H-LU tasks keep their queue order
+        const bool can_keep =
+            rel && (kMode == kModeSolve || crit || (kMode == kModeFused && a.tasks[s].c1 == 1));
         const unsigned long long m = __ballot(can_keep);
         int keep = -1;
         if (!kept && m) {
