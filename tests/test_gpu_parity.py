@@ -300,7 +300,12 @@ def test_fused_lu_solve_equals_separate(prec):
     followed by h_solve bit for bit (no product is split at this size); with
     70 right-hand sides the first 64 are fused and the rest solved after."""
     p = Problem(4096, 64, 1e-6, max_rank=64, oracle=False, prec=prec)
-    f = hm.LU(p.A, p.opts)
+    # the fused substitution runs at leaf granularity: compare with the
+    # uncoarsened separate substitution bit for bit, with the coarsened one
+    # (default) up to the rounding of its other summation order
+    opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-6, max_rank=64, prec=prec, coarsen=0)
+    f = hm.LU(p.A, opts)
+    fc = hm.LU(p.A, p.opts)
     _, _, _, bl = p.tree.tables()
     leaves = np.nonzero(bl[:, 2] != 0)[0]
     for nrhs in (5, 70):
@@ -308,8 +313,11 @@ def test_fused_lu_solve_equals_separate(prec):
         x1 = device_rhs(b)
         f.solve(x1)
         x2 = device_rhs(b)
-        g = hm.LU(p.A, p.opts, rhs=x2)
+        g = hm.LU(p.A, opts, rhs=x2)
         assert np.array_equal(to_host(x1), to_host(x2))
+        x3 = device_rhs(b)
+        fc.solve(x3)
+        assert np.max(np.abs(to_host(x3) - to_host(x2))) <= 1e-12 * np.abs(to_host(x2)).max()
         for bi in leaves[::7]:
             r1, r2 = f.leaf(int(bi)), g.leaf(int(bi))
             assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
