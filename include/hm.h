@@ -221,6 +221,10 @@ hm_status hm_batch_dag_export(const hm_tree* trees, int count, const hm_opts* op
 /* Solve A X = B in place through the factors: forward and backward block
  * substitution (not in the paper; the textbook substitution through L and U
  * of Sec. 2.2's A = LU, with the leaf pivots applied per diagonal leaf).
+ * A diagonal leaf's triangles are applied through their inverses, computed
+ * once per factorization right after the leaf's getrf; with opts->coarsen
+ * of the factorization, each diagonal block of at most that many rows is
+ * substituted by one task (the remark after Algorithm 11).
  * B: device, n x nrhs, column-major, leading dimension ldb >= n, caller-owned.
  * With A_or_null != NULL the solution is refined with r = b - A_H x (FP64
  * h_matvec) until every column has ||r|| / ||b|| <= rtol or max_iter

@@ -146,6 +146,35 @@ def test_eps_below_the_truncation_route_rejected(L):
         assert L.h_lu(None, ctypes.byref(opts), None, ctypes.byref(h), None) == hm.HM_EINVAL
 
 
+def test_coarsening_range_and_seq_export(L):
+    """hm_opts.coarsen outside [0, 1024] is refused; with coarsening the
+    substitution DAG holds OP_SEQ tasks whose micro-operations (exported by
+    hm_dag_seq_export) are leaf solves and products, every block-local panel
+    view inside its block, and the task count falls."""
+    t = hm.Tree(inputs.sphere_points(1024, 0), hm.make_opts(leaf=32))
+    h = ctypes.c_void_p()
+    for c in (-1, 1025):
+        opts = hm.make_opts(leaf=32, coarsen=c)
+        assert L.h_assemble(t.h, hm.LAPLACE3D, 1.0, ctypes.byref(opts), None, ctypes.byref(h)) == hm.HM_EINVAL
+        n = ctypes.c_int64()
+        assert L.hm_dag_seq_export(t.h, ctypes.byref(opts), 1, ctypes.byref(n), None) == hm.HM_EINVAL
+    d0 = t.dag(hm.make_opts(leaf=32, coarsen=0), 1)
+    d1 = t.dag(hm.make_opts(leaf=32, coarsen=128), 1)
+    assert len(d0["seq"]) == 0 and not (d0["tasks"]["op"] == 12).any()
+    seqt = d1["tasks"][d1["tasks"]["op"] == 12]
+    assert len(seqt) > 0 and len(d1["tasks"]) < len(d0["tasks"])
+    assert set(np.unique(d1["seq"]["op"])) <= {2, 4, 5, 6}
+    assert int(seqt["lr"].sum()) == len(d1["seq"])  # every micro-operation belongs to one block
+    for tk in seqt:
+        W = int(tk["y"]["rows"])
+        assert W <= 128
+        for u in d1["seq"][int(tk["piv"]):int(tk["piv"]) + int(tk["lr"])]:
+            for key in ("y", "a", "b", "x"):
+                v = u[key]
+                if int(v["dyn"]) & 8:  # block-local: rows inside the block
+                    assert 0 <= int(v["off"]) and int(v["off"]) + int(v["rows"]) <= W
+
+
 def test_solve_variants_reject_bad_arguments(L):
     """h_solve, h_solve_async and h_solve_noalloc check their arguments before
     touching a device."""
