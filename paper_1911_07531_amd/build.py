@@ -17,13 +17,16 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# -amdgpu-spill-vgpr-to-agpr=0: the truncation routines are separate functions
-# of the persistent executors; letting them park values in accumulation
-# registers would count against the register budget of two workgroups per
-# compute unit (the executors' launch bound), halving the executors' occupancy.
+# -amdgpu-spill-vgpr-to-agpr=0 and -amdgpu-mfma-vgpr-form: the truncation
+# routines are separate functions of the persistent executors; letting them
+# park values in, or keep matrix-core accumulators in, accumulation registers
+# counts against the register budget of two workgroups per compute unit (the
+# executors' launch bound) and halves the executors' occupancy.
 HIP_FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
+             "-mllvm", "-amdgpu-spill-vgpr-to-agpr=0", "-mllvm", "-amdgpu-mfma-vgpr-form"]
+# executors whose occupancy must stay at two waves per SIMD (two workgroups per CU)
+EXECUTORS = ("exec_dataflow_kernel", "exec_level_kernel", "fused_dataflow_kernel")
 
 
 def _run(cmd):
@@ -32,6 +35,19 @@ def _run(cmd):
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("build step failed: " + " ".join(cmd))
     return r
+
+
+def _check_occupancy(remarks: str) -> None:
+    """Fail the build when an H-LU executor kernel fits fewer than two waves per
+    SIMD (the compiler's resource-usage remarks), i.e. one workgroup per CU."""
+    name = None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split()[0]
+        elif "Occupancy [waves/SIMD]:" in line and name and any(e in name for e in EXECUTORS):
+            occ = int(line.split("Occupancy [waves/SIMD]:")[1].split()[0])
+            if occ < 2:
+                raise RuntimeError(f"{name}: occupancy {occ} wave(s) per SIMD, the executors need 2")
 
 
 def build(verbose: bool = False) -> str:
@@ -45,7 +61,10 @@ def build(verbose: bool = False) -> str:
         objs.append(o)
     for src in ("kernels.hip", "capi.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
+        extra = ["-Rpass-analysis=kernel-resource-usage"] if src == "kernels.hip" else []
+        r = _run([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o])
+        if extra:
+            _check_occupancy(r.stderr)
         objs.append(o)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs])
