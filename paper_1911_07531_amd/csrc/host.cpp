@@ -319,6 +319,9 @@ class Tracer {
       coarse_blocks(0);
       cb_sweep_.assign(cb_begin_.size(), 0);
       deferred_.assign(cb_begin_.size(), {});
+      def_lo_.assign(cb_begin_.size(), INT64_MAX);
+      def_hi_.assign(cb_begin_.size(), -1);
+      if (const char* e = getenv("HM_FOLD_REACH")) fold_reach_ = std::max(1, atoi(e));
     }
   }
   // +1 before the forward substitution, -1 before the backward one
@@ -643,6 +646,17 @@ class Tracer {
     emit(t, {{&a, ACC_R}, {&b, ACC_R}, {&y, beta != 0.0 ? ACC_RW : ACC_W}});
   }
   void lrgemm(const HView& y, double alpha, const HView& a, const HView& b, const HView& x, double beta) {
+    // a product whose target spans several coarse blocks and whose source
+    // folds into the first of them (in sweep order): that block's rows as
+    // their own product (folded into its task), the rest as a task
+    if (const int32_t cut = fold_cut(y.v, x.v); cut > 0 && beta == 1.0 && !(a.v.dyn & DYN_ROWS)) {
+      const int32_t m = y.v.rows;
+      const int32_t f0 = sweep_ > 0 ? 0 : m - cut, f1 = sweep_ > 0 ? cut : m;
+      const int32_t r0 = sweep_ > 0 ? cut : 0, r1 = sweep_ > 0 ? m : m - cut;
+      lrgemm(rows(y, f0, f1), alpha, rows(a, f0, f1), b, x, beta);
+      lrgemm(rows(y, r0, r1), alpha, rows(a, r0, r1), b, x, beta);
+      return;
+    }
     Task t = blank(OP_LRGEMM);
     t.alpha = alpha;
     t.beta = beta;
@@ -1375,10 +1389,37 @@ class Tracer {
   // block and whose source x is the whole neighbouring block just solved in
   // this sweep is folded into y's block task: it is the last update the block
   // waits for, and inside the task it needs no hand-off.
+  // A product y += ... x with y inside coarse block by folds into by's task
+  // when its source x lies in the coarse blocks among the fold_reach_
+  // blocks before by in sweep order (with reach 1: the neighbour, the last
+  // update by waits for; with more, products whose own task would finish
+  // after the neighbour's block task).
   bool folds_into_block(const View& y, const View& x) const {
-    if (coarsen_ <= 0 || !sub_ || !is_panel(y) || !is_panel(x)) return false;
-    const int by = block_of(y), bx = block_of(x);
-    return by >= 0 && bx >= 0 && bx == by - sweep_ && cb_sweep_[by] != sweep_;
+    if (coarsen_ <= 0 || !sub_ || !is_panel(y) || !is_panel(x) || x.rows <= 0) return false;
+    const int by = block_of(y);
+    if (by < 0 || cb_sweep_[by] == sweep_) return false;
+    const int64_t r0 = x.off - p_.panel_off, r1 = r0 + x.rows;
+    const int bf = cb_of_row_[(size_t)r0], bl = cb_of_row_[(size_t)(r1 - 1)];
+    if (bf < 0 || bl < 0) return false;
+    for (int k = bf; k < bl; ++k)
+      if (cb_end_[k] != cb_begin_[k + 1]) return false;  // the blocks must tile x's rows
+    if (sweep_ > 0) return bl < by && by - bf <= fold_reach_;
+    return bf > by && bl - by <= fold_reach_;
+  }
+  // Rows of y's first coarse block (in sweep order) when y covers several
+  // whole coarse blocks and x folds into that first block; else 0.
+  int32_t fold_cut(const View& y, const View& x) const {
+    if (coarsen_ <= 0 || !sub_ || in_seq_ || !is_panel(y) || y.rows <= 0) return 0;
+    const int64_t r0 = y.off - p_.panel_off, r1 = r0 + y.rows;
+    const int b0 = cb_of_row_[(size_t)r0], b1 = cb_of_row_[(size_t)(r1 - 1)];
+    if (b0 < 0 || b1 < 0 || b0 == b1 || r0 != cb_begin_[b0] || r1 != cb_end_[b1]) return 0;
+    for (int k = b0; k < b1; ++k)
+      if (cb_end_[k] != cb_begin_[k + 1]) return 0;
+    const int first = sweep_ > 0 ? b0 : b1;
+    View yb = y;
+    yb.off = p_.panel_off + cb_begin_[first];
+    yb.rows = (int32_t)(cb_end_[first] - cb_begin_[first]);
+    return folds_into_block(yb, x) ? yb.rows : 0;
   }
   bool defer_neighbour(const Task& tk) {
     const View& x = tk.op == OP_GEMM ? tk.b : tk.x;
@@ -1388,6 +1429,9 @@ class Tracer {
     u.y.off = tk.y.off - p_.panel_off - cb_begin_[by];
     u.y.dyn |= DYN_LOCAL;
     deferred_[by].push_back(u);
+    const int64_t r0 = x.off - p_.panel_off;
+    def_lo_[by] = std::min(def_lo_[by], r0);
+    def_hi_[by] = std::max(def_hi_[by], r0 + x.rows);
     return true;
   }
   // micro-operation of the open block: panel views become block-local
@@ -1416,7 +1460,10 @@ class Tracer {
     seq_W_ = x.v.rows;
     seq_cur_.assign(deferred_[b].begin(), deferred_[b].end());
     const bool folded = !deferred_[b].empty();
+    const int64_t src_lo = def_lo_[b], src_hi = def_hi_[b];
     deferred_[b].clear();
+    def_lo_[b] = INT64_MAX;
+    def_hi_[b] = -1;
     if (upper)
       solve_upper(d, x);
     else
@@ -1430,8 +1477,7 @@ class Tracer {
     d_.seq.insert(d_.seq.end(), seq_cur_.begin(), seq_cur_.end());
     seq_cur_.clear();
     if (folded) {
-      const int nb = b - sweep_;
-      HView src = rows(panel(), (int32_t)cb_begin_[nb], (int32_t)cb_end_[nb]);
+      HView src = rows(panel(), (int32_t)src_lo, (int32_t)src_hi);
       emit(t, {{&src, ACC_R}, {&x, ACC_RW}});
     } else {
       emit(t, {{&x, ACC_RW}});
@@ -1566,6 +1612,8 @@ class Tracer {
   std::vector<int64_t> cb_begin_, cb_end_;     // panel rows of each coarse block
   std::vector<int> cb_sweep_;                  // the sweep whose block task was emitted
   std::vector<std::vector<Task>> deferred_;    // neighbour products folded into a block's task
+  std::vector<int64_t> def_lo_, def_hi_;       // panel rows the folded products read
+  int fold_reach_ = 1;                         // blocks back a folded product's source may reach
   bool in_seq_ = false;                        // collecting a block's micro-operations
   int64_t seq_w0_ = 0;
   int32_t seq_W_ = 0;

@@ -65,14 +65,16 @@ def test_replay_matches_oracle_hlu(n, leaf, eps, max_rank, orders):
                 assert np.array_equal(b.piv, ob.piv)
 
 
-@pytest.mark.parametrize("split,coarsen", [(None, 0), ("12", 0), (None, 128), ("12", 256), (None, 40)])
-def test_replay_solve_matches_oracle(split, coarsen, monkeypatch):
+@pytest.mark.parametrize("split,coarsen,reach", [(None, 0, 1), ("12", 0, 1), (None, 128, 1), ("12", 256, 1),
+                                                (None, 40, 1), (None, 40, 3), ("12", 64, 4)])
+def test_replay_solve_matches_oracle(split, coarsen, reach, monkeypatch):
     """The substitution DAG, with the large low-rank products split into
     partial products and their sums (split = 12 rows) or not, and with the
     diagonal blocks of at most `coarsen` rows run as one task each (the
     neighbouring block's product folded in) or not."""
     if split is not None:
         monkeypatch.setenv("HM_SOLVE_SPLIT", split)
+    monkeypatch.setenv("HM_FOLD_REACH", str(reach))
     n, leaf, eps = 512, 32, 1e-6
     t, opts, a = _setup(n, leaf, 2.0, eps, 0)
     opts.coarsen = coarsen
