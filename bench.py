@@ -227,6 +227,10 @@ def run_serving(args):
     sizes = [16384, 32768, 65536, 131072, 262144, 16384, 32768, 65536][:args.serve_factors]
     os.environ.setdefault("HM_TEMP_BUDGET_GB", "2")  # temporaries of the resident plans
     opts = hm.make_opts(leaf=64, eta=2.0, eps=1e-4, max_rank=32, prec=hm.MIXED, coarsen=args.coarsen)
+    # 32 workgroups per substitution (one pass is as fast as with 128 at n = 131072), so that the
+    # factors' substitutions on their own streams fit the device side by side
+    tun = hm.get_tuning()
+    hm.set_tuning(exec_wg_per_cu=tun["exec_wg_per_cu"], solve_wg=32, batch_order=tun["batch_order"])
     t0 = time.perf_counter()
     res = []
     for k, n in enumerate(sizes):
@@ -252,7 +256,7 @@ def run_serving(args):
            "data": "synthetic",
            "config": {"workload": "serving", "factors_n": sizes, "rate_per_s": args.serve_rate,
                       "requests": args.serve_requests, "rhs_per_request": "U{1..64}", "refactor_frac": 0.01,
-                      "max_cols_per_batch": srv.max_cols, "eps": 1e-4, "max_rank": 32},
+                      "max_cols_per_batch": srv.max_cols, "eps": 1e-4, "max_rank": 32, "solve_workgroups": 32},
            "latency": summ, "wall_s": wall, "batches": int(srv.batches),
            "requests_per_batch": {"mean": float(bsizes.mean()), "max": int(bsizes.max())},
            "refactor_ms": srv.refactor_ms, "refactor_retries": srv.retries,

@@ -85,7 +85,7 @@ typedef struct {
   int prec;         /* hm_precision */
   int exec;         /* hm_exec of the factorization; the substitution DAGs of
                        h_solve, a few tasks per level, always run on the
-                       persistent executor with 128 workgroups */
+                       persistent executor with 64 workgroups */
   int lazy;         /* 0: truncate every update of a low-rank leaf when it is
                        produced, in the sequential order of Algorithm 1;
                        1: collect the updates of a low-rank leaf and add them
@@ -131,7 +131,7 @@ typedef struct {
  *   exec_wg_per_cu  workgroups per compute unit of the H-LU executors (1 or
  *                   2; 0 = as many as fit, which is 2)
  *   solve_wg        workgroups of the persistent substitution executor
- *                   (default 128, or HM_SOLVE_NWG)
+ *                   (default 64, or HM_SOLVE_NWG)
  *   batch_order     h_lu_batched queue order of the instances' first tasks:
  *                   0 as given, 1 the instances with the most tasks first */
 typedef struct {

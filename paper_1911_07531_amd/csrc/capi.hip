@@ -210,7 +210,7 @@ static int g_cus = 0;
 static int64_t g_clock_khz = 0;
 // Launch choices that the autotuner sets (hm_set_tuning); environment
 // variables give the defaults.
-static hm_tuning g_tuning = {0, 128, 0, {0, 0, 0, 0, 0}};
+static hm_tuning g_tuning = {0, 64, 0, {0, 0, 0, 0, 0}};
 
 // Workgroups of an H-LU executor launch under the current tuning.
 static int exec_workgroups() {
@@ -419,9 +419,9 @@ static hm_status run_dag(const DevDag& dd, ExecArgs a, ExecState& es, int mode, 
   a.seq_panel = g_seq_panel;
   if (dd.seq.p && g_seq_panel < 1) return fail(HM_EDEVICE, "no LDS left for coarsened substitution blocks");
   int nwg = exec_workgroups();
-  // The substitution DAG has a few tasks per level: 128 persistent
-  // workgroups hold every ready task (the tuning's solve_wg; HM_SOLVE_NWG
-  // sets its default).
+  // The substitution DAG has a few tasks per level: 64 persistent
+  // workgroups hold every ready task and leave room for substitutions on
+  // other streams (the tuning's solve_wg; HM_SOLVE_NWG sets its default).
   if (solve && mode != HM_EXEC_LEVEL) {
     const int v = g_tuning.solve_wg;
     if (v >= 1 && v < g_nwg) nwg = v;
