@@ -2847,10 +2847,12 @@ __device__ void run_task(const ExecArgs& a, int id, char* lds, double* scratch) 
 // follows the task; the record copy is still in LDS).
 __device__ void account_task(const ExecArgs& a, int id, char* lds) {
   if (!a.counters) return;
+  // the end tick first: the accounting's own loads are not the task's time
+  const uint64_t t1 = wall_clock64();
   const Task& t = *task_copy(lds);
   count_task(a, t, lds);
   if (t.op < 0 || t.op >= OP_COUNT) return;
-  const uint64_t t0 = *task_t0(lds), t1 = wall_clock64();
+  const uint64_t t0 = *task_t0(lds);
   wg_ctr(lds)[kCtrBusy + t.op] += t1 - t0;
   wg_ctr(lds)[kCtrCount + t.op] += 1;
   if (!a.trace) return;
