@@ -1641,17 +1641,18 @@ __device__ __forceinline__ void stack_descs(const ExecArgs& a, const Stack& st, 
 // Copies rows [r0, r0 + rows) of a stack of K described columns into buf
 // (column c at buf + c * ld): element e = c * rows + i, sixteen per thread in
 // flight, consecutive threads on consecutive rows.
+template <int kBatch = 16>
 __device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, int rows, double* buf, int ld) {
   const int total = rows * K;
-  for (int base = 0; base < total; base += 16 * kThreads) {
-    double v[16];
+  for (int base = 0; base < total; base += kBatch * kThreads) {
+    double v[kBatch];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kBatch; ++u) {
       const int e = base + u * kThreads + (int)threadIdx.x;
       v[u] = e < total ? desc_ld(desc[e / rows], r0 + e % rows) : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kBatch; ++u) {
       const int e = base + u * kThreads + (int)threadIdx.x;
       if (e < total) buf[(e / rows) * ld + e % rows] = v[u];
     }
@@ -2604,10 +2605,21 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
       [&](int i, int j, double x) { GV[i * K + j] = x; }, true, true, sA, sB);
   __syncthreads();
   phase_tick(a, lds, kCtrPhase + 6, tph);
-  // 2. R factors
+  // 2. R factors, in LDS whenever both Gram matrices fit there (the GEMM tiles
+  //    are free now): the left-looking steps then read earlier rows from LDS
+  //    instead of global scratch
+  if (!g_lds && 2 * K * K <= kLargeWork) {
+    double* LU = W;
+    double* LV = W + K * K;
+    copy_batched(LU, S.GU, K * K);
+    copy_batched(LV, S.GV, K * K);
+    __syncthreads();
+    GU = LU;
+    GV = LV;
+  }
   pivoted_cholesky_pair(GU, GV, K, v, s_int);
   const int rU = s_int[0], rV = s_int[1];
-  if (g_lds) {  // the factors move to global scratch to free the work area
+  if (GU != S.GU) {  // the factors move to global scratch to free the work area
     for (int e = tid; e < K * K; e += blockDim.x) {
       S.GU[e] = GU[e];
       S.GV[e] = GV[e];
