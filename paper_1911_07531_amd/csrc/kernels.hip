@@ -1427,12 +1427,14 @@ __device__ TruncScratch trunc_scratch(double* p) {
 }
 
 // One-sided Jacobi (Hestenes) on B (p x q, column-major, ld p): orthogonalise the
-// columns; Z (q x q, column-major) accumulates the rotations.  Round-robin
-// pairing, all pairs of a round in parallel.
+// columns; Z (q x q, column-major) accumulates the rotations, or is null when
+// the caller needs only B Z.  Round-robin pairing, all pairs of a round in
+// parallel.
 __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, double eps) {
   static_assert(kThreads == 256, "four wavefront partial sums below");
   const int tid = threadIdx.x;
-  for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
+  if (Z)
+    for (int e = tid; e < q * q; e += blockDim.x) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   __syncthreads();
   if (q < 2) return 0;
   const int N = q + (q & 1);
@@ -1497,11 +1499,12 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
           B[ci * p + r] = cs * x - sn * y;
           B[cj * p + r] = sn * x + cs * y;
         }
-        for (int r = lane; r < q; r += tpp) {
-          double x = Z[ci * q + r], y = Z[cj * q + r];
-          Z[ci * q + r] = cs * x - sn * y;
-          Z[cj * q + r] = sn * x + cs * y;
-        }
+        if (Z)
+          for (int r = lane; r < q; r += tpp) {
+            double x = Z[ci * q + r], y = Z[cj * q + r];
+            Z[ci * q + r] = cs * x - sn * y;
+            Z[cj * q + r] = sn * x + cs * y;
+          }
       }
       __syncthreads();
     }
@@ -1666,41 +1669,43 @@ __device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, i
 // its own 16 x 16 tiles of G (both MFMA operands are columns of X), and the
 // four wavefronts' tiles are summed in LDS at the end (the staging buffer,
 // free by then, holds them).
-__device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, double* G,
-                            double* buf, int cap_rows) {
+struct GramAcc {
+  Mfma<double>::acc_t a00, a01, a11;
+};
+
+// Adds rows [0, rows) of a staged chunk (column c at buf + c * ld) to the
+// calling wavefront's tiles.
+__device__ __forceinline__ void gram_rows(const double* buf, int ld, int rows, int K, GramAcc& g) {
+  using M = Mfma<double>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nt = (K + 15) >> 4;  // 1 or 2 tiles per side
+  const int c0 = li, c1 = 16 + li;
+  for (int t0 = 4 * wave; t0 < rows; t0 += 16) {
+    const int t = t0 + lk;
+    const bool in = t < rows;
+    const double x0 = (in && c0 < K) ? buf[c0 * ld + t] : 0.0;
+    const double x1 = (in && c1 < K) ? buf[c1 * ld + t] : 0.0;
+    g.a00 = M::step(x0, x0, g.a00);
+    if (nt > 1) {
+      g.a01 = M::step(x0, x1, g.a01);
+      g.a11 = M::step(x1, x1, g.a11);
+    }
+  }
+}
+
+// G from the four wavefronts' tiles, summed in a fixed order through `red`
+// (4 x 3 x 256 doubles of LDS not otherwise in use); ends with a barrier.
+__device__ __forceinline__ void gram_reduce(const GramAcc& g, int K, double* G, double* red) {
   using M = Mfma<double>;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int nt = (K + 15) >> 4;  // 1 or 2 tiles per side
-  const int ld = cap_rows | 1;   // odd stride: conflict-free column reads
-  M::acc_t acc00 = M::zero(), acc01 = M::zero(), acc11 = M::zero();
-  const int c0 = li, c1 = 16 + li;
-  for (int r0 = 0; r0 < m; r0 += cap_rows) {
-    const int rows = min(cap_rows, m - r0);
-    // every chunk in batches of sixteen loads per thread over all columns
-    stage_desc(desc, K, r0, rows, buf, ld);
-    __syncthreads();
-    for (int t0 = 4 * wave; t0 < rows; t0 += 16) {
-      const int t = t0 + lk;
-      const bool in = t < rows;
-      const double x0 = (in && c0 < K) ? buf[c0 * ld + t] : 0.0;
-      const double x1 = (in && c1 < K) ? buf[c1 * ld + t] : 0.0;
-      acc00 = M::step(x0, x0, acc00);
-      if (nt > 1) {
-        acc01 = M::step(x0, x1, acc01);
-        acc11 = M::step(x1, x1, acc11);
-      }
-    }
-    __syncthreads();
-  }
-  // per-wavefront tiles (00, 01, 11) to LDS, then the sum over wavefronts
-  double* red = buf;  // 4 wavefronts x 3 tiles x 256
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = M::row(lk, r) * 16 + li;
-    red[(wave * 3 + 0) * 256 + e] = acc00[r];
-    red[(wave * 3 + 1) * 256 + e] = acc01[r];
-    red[(wave * 3 + 2) * 256 + e] = acc11[r];
+    red[(wave * 3 + 0) * 256 + e] = g.a00[r];
+    red[(wave * 3 + 1) * 256 + e] = g.a01[r];
+    red[(wave * 3 + 2) * 256 + e] = g.a11[r];
   }
   __syncthreads();
   for (int e = tid; e < K * K; e += blockDim.x) {
@@ -1724,6 +1729,22 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* d
     G[e] = (red[idx] + red[3 * 256 + idx]) + (red[6 * 256 + idx] + red[9 * 256 + idx]);
   }
   __syncthreads();
+}
+
+__device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, double* G,
+                            double* buf, int cap_rows) {
+  using M = Mfma<double>;
+  const int ld = cap_rows | 1;  // odd stride: conflict-free column reads
+  GramAcc g{M::zero(), M::zero(), M::zero()};
+  for (int r0 = 0; r0 < m; r0 += cap_rows) {
+    const int rows = min(cap_rows, m - r0);
+    // every chunk in batches of sixteen loads per thread over all columns
+    stage_desc(desc, K, r0, rows, buf, ld);
+    __syncthreads();
+    gram_rows(buf, ld, rows, K, g);
+    __syncthreads();
+  }
+  gram_reduce(g, K, G, buf);
 }
 
 // Scaled, diagonally pivoted Cholesky of G (K x K, K <= 128) by the calling
@@ -1785,10 +1806,12 @@ __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
   return K;
 }
 
-// One-sided Jacobi on B (p x q, column-major, q <= 128) by the calling wavefront.
+// One-sided Jacobi on B (p x q, column-major, q <= 128) by the calling
+// wavefront; Z as for jacobi_svd (null: rotations not kept).
 __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
   const int lane = threadIdx.x & 63;
-  for (int e = lane; e < q * q; e += 64) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
+  if (Z)
+    for (int e = lane; e < q * q; e += 64) Z[e] = (e % q == e / q) ? 1.0 : 0.0;
   wave_sync();
   if (q < 2) return 0;
   const int N = q + (q & 1);
@@ -1822,14 +1845,36 @@ __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
         }
         if (ci >= q || cj >= q) ci = cj = -1;
       }
+      // a pair's columns stay in registers between the products and the
+      // rotation when each lane holds at most kRows of their rows (padding
+      // rows add exact zeros, so the sums are those of the plain loop)
+      constexpr int kRows = 8;
+      const bool inreg = p <= kRows * tpp;
+      double xs[kRows], ys[kRows];
       double al = 0.0, be = 0.0, ga = 0.0;
-      if (ci >= 0)
-        for (int r = sub; r < p; r += tpp) {
-          double x = B[ci * p + r], y = B[cj * p + r];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+      if (ci >= 0) {
+        if (inreg) {
+#pragma unroll
+          for (int k = 0; k < kRows; ++k) {
+            const int r = sub + k * tpp;
+            xs[k] = r < p ? B[ci * p + r] : 0.0;
+            ys[k] = r < p ? B[cj * p + r] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kRows; ++k) {
+            al += xs[k] * xs[k];
+            be += ys[k] * ys[k];
+            ga += xs[k] * ys[k];
+          }
+        } else {
+          for (int r = sub; r < p; r += tpp) {
+            double x = B[ci * p + r], y = B[cj * p + r];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
         }
+      }
       al = group_sum(al, tpp);
       be = group_sum(be, tpp);
       ga = group_sum(ga, tpp);
@@ -1837,16 +1882,28 @@ __device__ int jacobi_svd_wave(double* B, double* Z, int p, int q, double eps) {
         rotated = 1;
         double cs, sn;
         jacobi_rotation(al, be, ga, cs, sn);
-        for (int r = sub; r < p; r += tpp) {
-          double x = B[ci * p + r], y = B[cj * p + r];
-          B[ci * p + r] = cs * x - sn * y;
-          B[cj * p + r] = sn * x + cs * y;
+        if (inreg) {
+#pragma unroll
+          for (int k = 0; k < kRows; ++k) {
+            const int r = sub + k * tpp;
+            if (r < p) {
+              B[ci * p + r] = cs * xs[k] - sn * ys[k];
+              B[cj * p + r] = sn * xs[k] + cs * ys[k];
+            }
+          }
+        } else {
+          for (int r = sub; r < p; r += tpp) {
+            double x = B[ci * p + r], y = B[cj * p + r];
+            B[ci * p + r] = cs * x - sn * y;
+            B[cj * p + r] = sn * x + cs * y;
+          }
         }
-        for (int r = sub; r < q; r += tpp) {
-          double x = Z[ci * q + r], y = Z[cj * q + r];
-          Z[ci * q + r] = cs * x - sn * y;
-          Z[cj * q + r] = sn * x + cs * y;
-        }
+        if (Z)
+          for (int r = sub; r < q; r += tpp) {
+            double x = Z[ci * q + r], y = Z[cj * q + r];
+            Z[ci * q + r] = cs * x - sn * y;
+            Z[cj * q + r] = sn * x + cs * y;
+          }
       }
       wave_sync();
     }
@@ -2020,11 +2077,39 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
       wave_sync();
       if (lane < qq && qpos[lane] == kSmallK) {
         double* xj = B + lane * pp;
+        // rows in batches of eight, every load of a batch issued before its
+        // arithmetic (same order of accumulation as a plain loop)
         double w = 0.0;
-        for (int i = st; i < pp; ++i) w += xp[i] * xj[i];
+        int i = st;
+        for (; i + 8 <= pp; i += 8) {
+          double xv[8], pv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            xv[k] = xj[i + k];
+            pv[k] = xp[i + k];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) w += pv[k] * xv[k];
+        }
+        for (; i < pp; ++i) w += xp[i] * xj[i];
         const double f = be * w;
         double nn = 0.0;
-        for (int i = st; i < pp; ++i) {
+        i = st;
+        for (; i + 8 <= pp; i += 8) {
+          double xv[8], pv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            xv[k] = xj[i + k];
+            pv[k] = xp[i + k];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const double y = xv[k] - f * pv[k];
+            xj[i + k] = y;
+            if (i + k > st) nn += y * y;
+          }
+        }
+        for (; i < pp; ++i) {
           const double y = xj[i] - f * xp[i];
           xj[i] = y;
           if (i > st) nn += y * y;
@@ -2033,13 +2118,13 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
       }
       wave_sync();
     }
-    // R^T (q x r; column s is row s of R) in TU, its rotations in TV
+    // R^T (q x r; column s is row s of R) in TU; its rotations are not kept (only R^T Z is used)
     for (int e = lane; e < qq * r; e += 64) {
       const int j = e % qq, s2 = e / qq, pj = qpos[j];
       TU[e] = pj == s2 ? qa[s2] : (pj > s2 ? B[j * pp + s2] : 0.0);
     }
     wave_sync();
-    const int sw = r > 0 ? jacobi_svd_wave(TU, TV, qq, r, eps) : 0;
+    const int sw = r > 0 ? jacobi_svd_wave(TU, nullptr, qq, r, eps) : 0;
     if (lane == 0) s_int[3] = r;
     trunc_note(lds, 1, qq, r, sw, 0);
   }
@@ -2215,7 +2300,24 @@ __device__ void pivoted_cholesky_pair(double* GU, double* GV, int K, const Large
           val = piv;
         } else if (et >= 0.0) {
           double x = G[p * K + t] * dsc[p] * dsc[t];
-          for (int u = 0; u < s; ++u) {
+          // the earlier rows in batches of eight, every load of a batch
+          // issued before its products (same order of subtraction)
+          int u = 0;
+          for (; u + 8 <= s; u += 8) {
+            int pr[8];
+            double xa[8], xb[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pr[k] = perm[u + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const double* ru = G + (int64_t)pr[k] * K;
+              xa[k] = ru[p];
+              xb[k] = ru[t];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x -= xa[k] * xb[k];
+          }
+          for (; u < s; ++u) {
             const double* ru = G + (int64_t)perm[u] * K;
             x -= ru[p] * ru[t];
           }
@@ -2476,16 +2578,15 @@ __device__ int qr_svd(const ExecArgs& a, const LrDesc& d, const double* Bg, int 
     *sweeps = 0;
     return 0;
   }
-  // R^T (q x r, column-major: column s is row s of R) and its rotations
+  // R^T (q x r, column-major: column s is row s of R); only R^T Z is used
   double* Rt = rest;
-  double* Zb = Rt + q * r;
   for (int e = tid; e < q * r; e += blockDim.x) {
     const int j = e % q, s2 = e / q;
     const int pj = v.qpos[j];
     Rt[e] = pj == s2 ? v.qa[s2] : (pj > s2 ? X[j * p + s2] : 0.0);
   }
   __syncthreads();
-  *sweeps = jacobi_svd(Rt, Zb, q, r, s_int, eps);
+  *sweeps = jacobi_svd(Rt, nullptr, q, r, s_int, eps);
   const int kk = select_kept(a, d, Rt, q, r, v.sig, v.sel, s_int, eps);
   for (int e = tid; e < q * kk; e += blockDim.x) {
     const int j = e % q, c = e / q, sc = v.sel[c];
