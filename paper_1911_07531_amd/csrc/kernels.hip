@@ -1747,6 +1747,67 @@ __device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* d
   gram_reduce(g, K, G, buf);
 }
 
+// G = X^T X (K x K, row-major, K <= 64) for the K described columns of an
+// m-row stack, on the FP64 matrix cores.  Rows are staged through `buf`
+// (cap doubles) in chunks; the upper 16 x 16 tiles of G (at most ten) are
+// dealt to the four wavefronts in turn, and each wavefront sweeps all rows
+// of a chunk for its tiles, so no reduction between wavefronts is needed.
+// G may overlap buf: it is written after the last chunk has been read.
+__device__ void gram_tiles(const ColDesc* desc, int K, int m, double* G, double* buf, int cap) {
+  using M = Mfma<double>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nt = (K + 15) >> 4, ntiles = nt * (nt + 1) / 2;
+  const int cap_rows = cap / K - 1;
+  const int ld = cap_rows | 1;  // odd stride: conflict-free column reads
+  int ti[3], tj[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int idx = wave + 4 * s, a = 0;
+    ti[s] = tj[s] = -1;
+    if (idx < ntiles) {
+      while (idx >= nt - a) {  // row a of the upper triangle holds nt - a tiles
+        idx -= nt - a;
+        ++a;
+      }
+      ti[s] = a;
+      tj[s] = a + idx;
+    }
+  }
+  M::acc_t acc[3] = {M::zero(), M::zero(), M::zero()};
+  for (int r0 = 0; r0 < m; r0 += cap_rows) {
+    const int rows = min(cap_rows, m - r0);
+    stage_desc(desc, K, r0, rows, buf, ld);
+    __syncthreads();
+    for (int t0 = 0; t0 < rows; t0 += 4) {
+      const int t = t0 + lk;
+      const bool in = t < rows;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (ti[s] < 0) continue;
+        const int ca = 16 * ti[s] + li, cb = 16 * tj[s] + li;
+        const double xa = (in && ca < K) ? buf[ca * ld + t] : 0.0;
+        const double xb = (in && cb < K) ? buf[cb * ld + t] : 0.0;
+        acc[s] = M::step(xa, xb, acc[s]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (ti[s] < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti[s] + M::row(lk, r), j = 16 * tj[s] + li;
+      if (i < K && j < K) {
+        G[i * K + j] = acc[s][r];
+        if (ti[s] != tj[s]) G[j * K + i] = acc[s][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Scaled, diagonally pivoted Cholesky of G (K x K, K <= 128) by the calling
 // wavefront alone; same results as pivoted_cholesky.  Returns the rank.
 __device__ int pivoted_cholesky_wave(double* G, int K, int* perm, double* dsc) {
@@ -2694,22 +2755,38 @@ __device__ int trunc_gram(const ExecArgs& a, const LrDesc& d, int lr_index, cons
   double* sA = (double*)lds;
   double* sB = sA + TK * (TM + TP);
   double* W = (double*)lds;
-  // 1. Gram matrices, in LDS after the GEMM tiles when both fit
-  const bool g_lds = kTileDoubles + 2 * K * K <= kLargeWork;
-  double* GU = g_lds ? W + kTileDoubles : S.GU;
-  double* GV = g_lds ? GU + K * K : S.GV;
-  gemm_tiles<double>(
-      K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
-      [&](int i, int j, double x) { GU[i * K + j] = x; }, true, true, sA, sB);
-  gemm_tiles<double>(
-      K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
-      [&](int i, int j, double x) { GV[i * K + j] = x; }, true, true, sA, sB);
+  // 1. Gram matrices.  K <= 64: on the matrix cores from LDS-staged rows,
+  //    the column descriptors parked in the per-column vectors (not in use
+  //    before the Cholesky), G_U then G_V in the work area, each staged
+  //    through the space after it.  Otherwise by the tiled GEMM, in LDS
+  //    after the GEMM tiles when both fit.
+  const bool g_mfma = K <= 64;
+  const bool g_lds = !g_mfma && kTileDoubles + 2 * K * K <= kLargeWork;
+  double* GU = g_mfma ? W : g_lds ? W + kTileDoubles : S.GU;
+  double* GV = g_mfma ? W + K * K : g_lds ? GU + K * K : S.GV;
+  if (g_mfma) {
+    static_assert(2 * 64 * sizeof(ColDesc) <= kLargeVecBytes, "descriptors fit the vector area");
+    static_assert(2 * 64 * 64 <= kLargeWork && 64 * 64 + 2 * 64 * 2 <= kLargeWork, "G_U, G_V and a chunk fit");
+    ColDesc* du = (ColDesc*)v.dU;
+    stack_descs(a, su, K, du, 0);
+    stack_descs(a, sv, K, du + K, 64);
+    __syncthreads();
+    gram_tiles(du, K, m, GU, W, kLargeWork);
+    gram_tiles(du + K, K, n, GV, W + K * K, kLargeWork - K * K);
+  } else {
+    gemm_tiles<double>(
+        K, K, m, [&](int i, int r) { return su(a, r, i); }, [&](int r, int j) { return su(a, r, j); },
+        [&](int i, int j, double x) { GU[i * K + j] = x; }, true, true, sA, sB);
+    gemm_tiles<double>(
+        K, K, n, [&](int i, int r) { return sv(a, r, i); }, [&](int r, int j) { return sv(a, r, j); },
+        [&](int i, int j, double x) { GV[i * K + j] = x; }, true, true, sA, sB);
+  }
   __syncthreads();
   phase_tick(a, lds, kCtrPhase + 6, tph);
   // 2. R factors, in LDS whenever both Gram matrices fit there (the GEMM tiles
   //    are free now): the left-looking steps then read earlier rows from LDS
   //    instead of global scratch
-  if (!g_lds && 2 * K * K <= kLargeWork) {
+  if (!g_mfma && !g_lds && 2 * K * K <= kLargeWork) {
     double* LU = W;
     double* LV = W + K * K;
     copy_batched(LU, S.GU, K * K);
