@@ -1516,9 +1516,10 @@ __device__ int jacobi_svd(double* B, double* Z, int p, int q, int* s_flag, doubl
 }
 
 // Solve the r x r upper triangle of R' (rows of G, stride K) against rhs columns
-// (r x kk, column-major, ld r) in place; one thread per column.
-__device__ void upper_solve(const double* R, int K, int r, double* X, int kk) {
-  for (int j = threadIdx.x; j < kk; j += blockDim.x) {
+// (r x kk, column-major, ld r) in place; one thread per column (columns j0,
+// j0 + stride, ...).
+__device__ void upper_solve(const double* R, int K, int r, double* X, int kk, int j0, int stride) {
+  for (int j = j0; j < kk; j += stride) {
     double* x = X + (int64_t)j * r;
     for (int i = r - 1; i >= 0; --i) {
       double s = x[i];
@@ -2242,8 +2243,12 @@ __device__ int trunc_core_small(const ExecArgs& a, const LrDesc& d, int lr_index
     for (int e = tid; e < rV * kk; e += blockDim.x) yv[e] = vc[e];
   }
   __syncthreads();
-  upper_solve(GU, K, rU, yu, kk);
-  upper_solve(GV, K, rV, yv, kk);
+  // both triangles at once: the first half of the workgroup solves with R_U,
+  // the second with R_V
+  if (tid < 128)
+    upper_solve(GU, K, rU, yu, kk, tid, 128);
+  else
+    upper_solve(GV, K, rV, yv, kk, tid - 128, 128);
   __syncthreads();
   double* T_U = B;  // K x kk <= K x K
   double* T_V = Z;
