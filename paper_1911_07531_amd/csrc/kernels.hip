@@ -1664,12 +1664,8 @@ __device__ __forceinline__ void stage_desc(const ColDesc* desc, int K, int r0, i
 }
 
 
-// G = X^T X (K x K, row-major, K <= 32) for X = the stacked panel st (m x K),
-// staged through LDS in chunks of up to `cap_rows` rows, on the matrix cores
-// in FP64: wavefront w takes the rows 4 w + 16 s .. + 3 of every chunk into
-// its own 16 x 16 tiles of G (both MFMA operands are columns of X), and the
-// four wavefronts' tiles are summed in LDS at the end (the staging buffer,
-// free by then, holds them).
+// The three 16 x 16 tiles (00, 01, 11) of a K <= 32 Gram matrix held by one
+// wavefront.
 struct GramAcc {
   Mfma<double>::acc_t a00, a01, a11;
 };
@@ -1732,6 +1728,12 @@ __device__ __forceinline__ void gram_reduce(const GramAcc& g, int K, double* G, 
   __syncthreads();
 }
 
+// G = X^T X (K x K, row-major, K <= 32) for X = the stacked panel st (m x K),
+// staged through LDS in chunks of up to `cap_rows` rows, on the matrix cores
+// in FP64: wavefront w takes the rows 4 w + 16 s .. + 3 of every chunk into
+// its own 16 x 16 tiles of G (both MFMA operands are columns of X), and the
+// four wavefronts' tiles are summed in LDS at the end (the staging buffer,
+// free by then, holds them).
 __device__ void gram_stream(const ExecArgs& a, const Stack& st, const ColDesc* desc, int K, int m, double* G,
                             double* buf, int cap_rows) {
   using M = Mfma<double>;
