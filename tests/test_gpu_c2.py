@@ -81,3 +81,32 @@ def test_lu_error_bound_matrix_free(c2):
     err = lu_error_estimate(pts[perm], diag, fac)
     print(f"||PA - LU||_2 / ||A||_2 ~ {err:.3e} (bound {10 * float(g['eps']):.1e})")
     assert err <= 10 * float(g["eps"])
+
+
+def test_truncation_routes_exercised(c2, monkeypatch):
+    """The comparisons above cover the device's truncation routes: the same
+    factorization, repeated with the per-task timeline on (which does not
+    change the arithmetic: the ranks must equal the untimed run's), records
+    for every truncation its route and stacked width K.  Required: the
+    small-rank route (K <= 32), the dense small-leaf route, and the Gram route
+    both with K <= 64 (Gram matrices on the matrix cores) and with K > 64
+    (tiled GEMM); the histogram is printed."""
+    g, _, _, tree, A, f0 = c2
+    opts = hm.make_opts(leaf=int(g["leaf"]), eta=float(g["eta"]), eps=float(g["eps"]), max_rank=int(g["max_rank"]),
+                        prec=hm.FP64, lazy=int(g["lazy"]))
+    monkeypatch.setenv("HM_DEBUG_TRACE", "1")
+    f = hm.LU(A, opts)
+    tl, _ = f.timeline()
+    ops = tree.dag(opts, 0)["tasks"]["op"]
+    tr = np.isin(ops, (hm.OP_NAMES.index("trunc"), hm.OP_NAMES.index("trunc2")))
+    info, info2 = tl[tr, 2], tl[tr, 3]
+    K = ((info >> 16) & 0xFFFF).astype(np.int64)
+    route = (info2 & 0xFF).astype(np.int64)
+    for r in np.unique(route):
+        sel = route == r
+        print(f"route {r}: {int(sel.sum())} truncations, K {int(K[sel].min())}..{int(K[sel].max())}")
+    assert ((route == 1) & (K <= 32)).any()
+    assert (route == 2).any()
+    assert ((route == 3) & (K > 32) & (K <= 64)).any()
+    assert ((route == 3) & (K > 64)).any()
+    assert np.array_equal(_ranks(f.h, 1, g["blocks"]), _ranks(f0.h, 1, g["blocks"]))
