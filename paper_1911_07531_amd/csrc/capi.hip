@@ -144,6 +144,7 @@ struct DevDag {
   DevBuf succ_crit;  // per edge: successor near the critical path
   int32_t nroots = 0;
   std::vector<int32_t> level_ptr;
+  int64_t tasks_by_op[kOpSlots] = {};  // counted once at upload (a pass over the host records is slow)
 };
 
 struct PlanEntry {
@@ -154,7 +155,25 @@ struct PlanEntry {
   DevDag lu, solve, fused;
   DevBuf lr;
   int device = -1;
+  // tasks per kind of the H-LU DAG, counted on first use (a pass over the
+  // host task records costs tens of milliseconds at a few million tasks)
+  int64_t lu_ops[kOpSlots] = {};
+  bool lu_ops_done = false;
+  // the block copy list from the first assembled matrix's layout into this
+  // plan's factor layout (mixed precision), kept on the device for reuse
+  const PlanEntry* conv_src = nullptr;
+  DevBuf conv;
+  int64_t nconv = 0;
 };
+
+static const int64_t* lu_op_counts(PlanEntry* pe) {
+  if (!pe->lu_ops_done) {
+    for (const Task& tk : pe->plan.lu.tasks)
+      if (tk.op >= 0 && tk.op < OP_COUNT) pe->lu_ops[tk.op]++;
+    pe->lu_ops_done = true;
+  }
+  return pe->lu_ops;
+}
 
 struct hm_tree_s {
   Tree t;
@@ -329,6 +348,9 @@ static hm_status upload_dag(const Dag& d, DevDag& dd, hipStream_t s) {
   dd.nlevels = (int64_t)d.level_ptr.size() - 1;
   dd.level_ptr = d.level_ptr;
   dd.nroots = (int32_t)d.roots.size();
+  for (int k = 0; k < kOpSlots; ++k) dd.tasks_by_op[k] = 0;
+  for (const Task& tk : d.tasks)
+    if (tk.op >= 0 && tk.op < OP_COUNT) dd.tasks_by_op[tk.op]++;
   hm_status st;
   if ((st = upload(dd.tasks, d.tasks, s))) return st;
   if ((st = upload(dd.indeg, d.indeg, s))) return st;
@@ -608,6 +630,7 @@ void hm_tree_free(hm_tree t) {
       dev_free(dd->succ_crit);
     }
     dev_free(pe->lr);
+    dev_free(pe->conv);
   }
   delete t;
 }
@@ -1024,7 +1047,6 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
   if ((st = ensure_uploaded(pe, s))) return st;
   const Plan& p = pe->plan;
   const DevDag& dag = fused ? pe->fused : pe->lu;
-  const Dag& hdag = fused ? p.fused : p.lu;
   const Plan& pa = A->pe->plan;
   auto F = std::make_unique<hm_lu_s>();
   F->tree = t;
@@ -1061,28 +1083,60 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
   if (opts->prec == HM_FP64) {
     HIPCHK(hipMemcpyAsync(F->f64.p, A->f64.p, pa.blocks_f64 * 8, hipMemcpyDeviceToDevice, s));
   } else {
-    std::vector<CopyDesc> cd;
-    const Tree& tr = t->t;
-    for (size_t b = 0; b < tr.bl.size(); ++b) {
-      const BlockNode& bn = tr.bl[b];
-      if (bn.kind == BK_DENSE) {
-        int64_t cnt = tr.cl[bn.tau].size() * tr.cl[bn.sigma].size();
-        cd.push_back(CopyDesc{pa.data_off[b], p.data_off[b], cnt, p.data_type[b], 0});
-      } else if (bn.kind == BK_LOWRANK) {
-        const LrDesc& da = pa.lr[pa.lr_index[b]];
-        const LrDesc& dl = p.lr[p.lr_index[b]];
-        cd.push_back(CopyDesc{da.u_off, dl.u_off, (int64_t)da.m * da.cap, dl.type, 0});
-        cd.push_back(CopyDesc{da.v_off, dl.v_off, (int64_t)da.n * da.cap, dl.type, 0});
+    // The copy list depends only on the two layouts: built and uploaded on
+    // the first call, reused while the matrices come from that same
+    // assembly layout (another layout gets a list of its own for the call).
+    auto build_list = [&](std::vector<CopyDesc>& cd) {
+      const Tree& tr = t->t;
+      for (size_t b = 0; b < tr.bl.size(); ++b) {
+        const BlockNode& bn = tr.bl[b];
+        if (bn.kind == BK_DENSE) {
+          int64_t cnt = tr.cl[bn.tau].size() * tr.cl[bn.sigma].size();
+          cd.push_back(CopyDesc{pa.data_off[b], p.data_off[b], cnt, p.data_type[b], 0});
+        } else if (bn.kind == BK_LOWRANK) {
+          const LrDesc& da = pa.lr[pa.lr_index[b]];
+          const LrDesc& dl = p.lr[p.lr_index[b]];
+          cd.push_back(CopyDesc{da.u_off, dl.u_off, (int64_t)da.m * da.cap, dl.type, 0});
+          cd.push_back(CopyDesc{da.v_off, dl.v_off, (int64_t)da.n * da.cap, dl.type, 0});
+        }
+      }
+    };
+    const CopyDesc* list = nullptr;
+    int64_t nlist = 0;
+    DevBuf cbuf;
+    std::vector<CopyDesc> cd;  // the host source of an upload lives until it is done
+    {
+      std::lock_guard<std::mutex> lk(t->mu);
+      if (!pe->conv_src) {
+        build_list(cd);
+        if ((st = upload(pe->conv, cd, s))) {
+          dev_free(pe->conv);
+          return st;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        pe->nconv = (int64_t)cd.size();
+        pe->conv_src = A->pe;
+        cd.clear();
+      }
+      if (pe->conv_src == A->pe) {
+        list = (const CopyDesc*)pe->conv.p;
+        nlist = pe->nconv;
       }
     }
-    DevBuf cbuf;
-    if ((st = upload(cbuf, cd, s))) return st;
-    if (!cd.empty())
-      hipLaunchKernelGGL(convert_blocks_kernel, dim3((unsigned)cd.size()), dim3(256), 0, s, (const double*)A->f64.p,
-                         (double*)F->f64.p, (float*)F->f32.p, (const CopyDesc*)cbuf.p);
+    if (!list) {
+      build_list(cd);
+      if ((st = upload(cbuf, cd, s))) return st;
+      list = (const CopyDesc*)cbuf.p;
+      nlist = (int64_t)cd.size();
+    }
+    if (nlist > 0)
+      hipLaunchKernelGGL(convert_blocks_kernel, dim3((unsigned)nlist), dim3(256), 0, s, (const double*)A->f64.p,
+                         (double*)F->f64.p, (float*)F->f32.p, list);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    dev_free(cbuf);
+    if (cbuf.p) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_free(cbuf);
+    }
   }
   DevBuf scratch;
   if (!dev_alloc(scratch, (size_t)g_nwg * kScratchPerWg * 8, s)) return fail(HM_ENOMEM, "device allocation failed");
@@ -1122,8 +1176,7 @@ static hm_status lu_impl(hm_matrix A, const hm_opts* opts, void* stream, hm_lu* 
   F->stats.ntasks = dag.ntasks;
   F->stats.nedges = dag.nedges;
   F->stats.nlevels = dag.nlevels;
-  for (const Task& tk : hdag.tasks)
-    if (tk.op >= 0 && tk.op < OP_COUNT) F->stats.tasks_by_op[tk.op]++;
+  for (int k = 0; k < OP_COUNT; ++k) F->stats.tasks_by_op[k] = dag.tasks_by_op[k];
   F->stats.bytes_alg = (int64_t)ctr[0];
   F->stats.flops_alg = (int64_t)ctr[1];
   F->stats.exec_ms = ms;
@@ -1530,8 +1583,7 @@ hm_status h_lu_batched(const hm_matrix* As, int count, const hm_opts* opts, void
   bst.exec_ms = ms;
   bst.rank_overflows = stv[2];
   for (int i = 0; i < count; ++i)
-    for (const Task& tk : pes[i]->plan.lu.tasks)
-      if (tk.op >= 0 && tk.op < OP_COUNT) bst.tasks_by_op[tk.op]++;
+    for (int k = 0; k < OP_COUNT; ++k) bst.tasks_by_op[k] += lu_op_counts(pes[i])[k];
   std::vector<std::unique_ptr<hm_lu_s>> made(count);
   for (int i = 0; i < count; ++i) {
     const Plan& p = pes[i]->plan;
