@@ -166,6 +166,7 @@ struct PlanEntry {
   int64_t nconv = 0;
 };
 
+// (the caller holds the tree's mutex)
 static const int64_t* lu_op_counts(PlanEntry* pe) {
   if (!pe->lu_ops_done) {
     for (const Task& tk : pe->plan.lu.tasks)
@@ -1582,8 +1583,11 @@ hm_status h_lu_batched(const hm_matrix* As, int count, const hm_opts* opts, void
   bst.flops_alg = (int64_t)ctr[1];
   bst.exec_ms = ms;
   bst.rank_overflows = stv[2];
-  for (int i = 0; i < count; ++i)
-    for (int k = 0; k < OP_COUNT; ++k) bst.tasks_by_op[k] += lu_op_counts(pes[i])[k];
+  for (int i = 0; i < count; ++i) {
+    std::lock_guard<std::mutex> lk(As[i]->tree->mu);  // the counts are filled on first use
+    const int64_t* c = lu_op_counts(pes[i]);
+    for (int k = 0; k < OP_COUNT; ++k) bst.tasks_by_op[k] += c[k];
+  }
   std::vector<std::unique_ptr<hm_lu_s>> made(count);
   for (int i = 0; i < count; ++i) {
     const Plan& p = pes[i]->plan;
